@@ -1,0 +1,220 @@
+/*
+ * qsim.h -- C-ABI of libqsim, an MI355X (gfx950) engine for expectation
+ * values of variational quantum circuits and their gradients.
+ *
+ * What is computed follows the paper (Patti, Kossaifi, Yelin, Anandkumar,
+ * "TensorLy-Quantum: Quantum Machine Learning with Tensor Methods"):
+ *   - Sec. 1: quantum expectation values define the objective of variational
+ *     (QML) algorithms, optimised by classical gradient descent;
+ *   - Sec. 2: circuits are built from pre-defined or custom gates acting on
+ *     states; operators are kept in factorized form;
+ *   - Sec. 3: the forward value <H> and the full gradient d<H>/dtheta for a
+ *     transverse-field Ising Hamiltonian; a dense operator matrix is never
+ *     formed (its memory grows as 4^n);
+ *   - Sec. 4: "causality-simplified contraction" (future work there) is the
+ *     light-cone mode here.
+ *
+ * Conventions (readings of points the paper leaves open):
+ *   - qubit q is bit q of an amplitude index (little-endian);
+ *   - RX/RY/RZ(t) = exp(-i t P / 2) with P = X/Y/Z;
+ *   - CZ = diag(1,1,1,-1) on (q0, q1); CNOT has control q0 and target q1;
+ *   - U1 is a fixed caller-given 2x2 unitary (row-major complex128, 8 doubles
+ *     re,im interleaved);
+ *   - H = sum_t coeff[t] * P_t with real coefficients and Pauli strings P_t
+ *     on distinct qubits; the empty string is the identity.
+ *
+ * Status codes: every call returns QSIM_OK (0) or a negative QSIM_E* code and
+ * never throws across the ABI.  A context records the text of its last error
+ * (qsim_last_error).  NaN parameters propagate to the results; they are not
+ * rejected.
+ *
+ * Memory: every array passed in is owned by the caller and only read during
+ * the call (qsim_submit deep-copies its request).  Results are written to
+ * caller-owned host buffers.  Objects returned through out-pointers
+ * (contexts, states) are owned by the library until the matching destroy or
+ * finalize call.
+ *
+ * Streams: "stream" arguments are hipStream_t values (NULL = the context's
+ * own stream).  Calls that return host results synchronize that stream.
+ */
+#ifndef QSIM_H
+#define QSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QSIM_OK 0
+#define QSIM_PENDING 1      /* qsim_poll: result not ready yet (not an error) */
+#define QSIM_EINVAL (-1)    /* bad argument: qubit, duplicate qubit, kind, Pauli, n, batch */
+#define QSIM_ENOMEM (-2)    /* device or host allocation failed */
+#define QSIM_ETOOBIG (-3)   /* footprint above the budget, or a light cone above the cap */
+#define QSIM_EAGAIN (-4)    /* serving queue full: retry later */
+#define QSIM_ENOTFOUND (-5) /* unknown or already-consumed ticket */
+#define QSIM_EDEVICE (-6)   /* HIP runtime error (text in qsim_last_error) */
+#define QSIM_ECANCELED (-7) /* request was cancelled */
+#define QSIM_ESHUTDOWN (-8) /* context shut down with the request pending */
+
+enum { QSIM_RX = 0, QSIM_RY = 1, QSIM_RZ = 2, QSIM_CZ = 3, QSIM_CNOT = 4, QSIM_U1 = 5 };
+enum { QSIM_C64 = 0, QSIM_C128 = 1 };
+enum { QSIM_MODE_AUTO = 0, QSIM_MODE_DENSE = 1, QSIM_MODE_LIGHTCONE = 2 };
+
+/* One gate.  Rotations take theta[param] when param >= 0, else 'angle'.
+ * Two-qubit gates use q0 and q1 (distinct); others use q0 only.  'mat' is read
+ * for U1 only.  Layout (32 bytes): kind@0, q0@4, q1@8, param@12, angle@16, mat@24. */
+typedef struct {
+    uint8_t kind;
+    uint8_t pad[3];
+    int32_t q0, q1;
+    int32_t param;
+    double angle;
+    const double* mat;
+} qsim_gate;
+
+/* A circuit: gates applied in array order to |0...0> on n_qubits qubits. */
+typedef struct {
+    int32_t n_qubits;
+    int32_t n_gates;
+    int32_t n_params;
+    int32_t pad;
+    const qsim_gate* gates;
+} qsim_circuit;
+
+/* H = sum_t coeff[t] * prod_{k in [term_off[t], term_off[t+1])} paulis[k] on qubits[k];
+ * paulis are the bytes 'X', 'Y', 'Z'. */
+typedef struct {
+    int32_t n_terms;
+    int32_t pad;
+    const double* coeff;
+    const int32_t* term_off;
+    const int32_t* qubits;
+    const uint8_t* paulis;
+} qsim_hamiltonian;
+
+/* Context options; zero fields take defaults. */
+typedef struct {
+    int32_t device;             /* HIP device ordinal */
+    int32_t max_queue;          /* serving: queued + in-flight requests (default 4096) */
+    int32_t cone_cap;           /* light cones above this many qubits are ETOOBIG (default 20) */
+    int32_t pad;
+    uint64_t hbm_budget_bytes;  /* serving: bytes of state memory in flight (default 64 GiB) */
+} qsim_options;
+
+typedef struct qsim_ctx qsim_ctx;
+typedef struct qsim_state qsim_state;
+
+/* Create a context on opt->device (opt may be NULL).  Owns a HIP stream,
+ * device workspaces and the plan cache. */
+int qsim_init(const qsim_options* opt, qsim_ctx** out);
+/* Stop the serving loop (pending tickets end with QSIM_ESHUTDOWN), free everything. */
+void qsim_finalize(qsim_ctx* ctx);
+/* Static text for a status code. */
+const char* qsim_strerror(int code);
+/* Text of the context's most recent error ("" if none).  Valid until the next call on ctx. */
+const char* qsim_last_error(qsim_ctx* ctx);
+
+/* ---- stateful interface (Sec. 2: gates acting on states) --------------------------- */
+
+/* A batch of 'batch' states of n_qubits each, set to |0...0>.  dtype: QSIM_C64 or
+ * QSIM_C128.  dev_buf NULL = library-owned memory, else a caller device buffer of
+ * batch * 2^n * (8 or 16) bytes that must outlive the state (borrowed).  Layout:
+ * state b, amplitude x at element b*2^n + x, (re, im) interleaved. */
+int qsim_create_state(qsim_ctx* ctx, int n_qubits, int batch, int dtype, void* dev_buf, void* stream,
+                      qsim_state** out);
+int qsim_destroy_state(qsim_state* st);
+/* Append gates to the state's queue.  params: host float64 [batch * n_params] (row b
+ * for state b), read during the call only; may be NULL when no gate has param >= 0.
+ * Queued gates are planned and applied at the next qsim_expect or qsim_state_to_host. */
+int qsim_apply_layer(qsim_state* st, const qsim_gate* gates, int n_gates, const double* params, int n_params);
+/* out[b] = <psi_b|H|psi_b> (float64, host, [batch]); flushes queued gates. */
+int qsim_expect(qsim_state* st, const qsim_hamiltonian* H, double* out);
+/* Copy the states to host memory (batch * 2^n complex of the state's dtype); flushes. */
+int qsim_state_to_host(qsim_state* st, void* host);
+/* Device pointer of the amplitudes (layout as in qsim_create_state); flushes first. */
+int qsim_state_device_ptr(qsim_state* st, void** ptr);
+
+/* ---- one-call evaluation (Sec. 3: forward value) ----------------------------------- */
+
+/* out[b] = <psi(theta_b)|H|psi(theta_b)> for b < batch, theta_b = params + b*n_params
+ * (host float64).  mode: dense state vector, per-term light cones (batch 1), or AUTO
+ * (light cones when n > 30 or when all cones are far smaller than n).  If keep != NULL
+ * (dense mode only), the final states are returned in *keep for qsim_expect_grad. */
+int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
+                        const qsim_hamiltonian* H, int mode, int dtype, void* stream, double* out,
+                        qsim_state** keep);
+
+/* ---- gradient (Sec. 3: full gradient; here by the adjoint method) ------------------ */
+
+/* E[b] = <H> and grad[b*n_params + j] = d<H>/dtheta_j (float64, host) for b < batch.
+ * saved: final states from qsim_expect_circuit(keep) with the same circuit/params, or
+ * NULL to run the forward pass first.  A saved state is consumed (its amplitudes are
+ * overwritten by the backward sweep) but must still be destroyed by the caller. */
+int qsim_expect_grad(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
+                     const qsim_hamiltonian* H, int dtype, void* stream, qsim_state* saved, double* E,
+                     double* grad);
+
+/* ---- light cones (Sec. 4: causality-simplified contraction) ------------------------- */
+
+/* Canonical light-cone qubit sets, ascending, term by term: set t is
+ * qubits[off[t] .. off[t+1]).  Start from the term's qubits, walk the gates
+ * backwards, add both qubits of every two-qubit gate touching the set.  Host only
+ * (no device use, ctx not needed).  cap = capacity of 'qubits'; QSIM_ETOOBIG if short. */
+int qsim_lightcone_sets(const qsim_circuit* c, const qsim_hamiltonian* H, int32_t* off, int32_t* qubits,
+                        int cap);
+
+/* Plan summary for a dense evaluation on the host (no device use): passes,
+ * stages and ops that the given options produce.  info[0] = passes, info[1] =
+ * stages, info[2] = device ops, info[3] = measurement passes.  If 'order' is not
+ * NULL it receives, for every gate of c in execution order, (pass, stage, gate
+ * index) triples; cap_triples bounds it. */
+int qsim_plan_dense(const qsim_circuit* c, const qsim_hamiltonian* H, int dtype, int64_t* info, int32_t* order,
+                    int cap_triples);
+
+/* ---- measurement ------------------------------------------------------------------ */
+
+/* Per-launch timing of the synchronous calls' pass kernels on ctx: with on != 0,
+ * every pass launch that follows is bracketed by HIP events recorded on the
+ * stream it runs on; on == 0 stops recording.  Enabling clears old records. */
+int qsim_timing_enable(qsim_ctx* ctx, int on);
+/* Copy up to cap records of launches finished so far: ms[i] = kernel time in
+ * milliseconds, bytes[i] = algorithmic HBM bytes of that launch (each amplitude
+ * read and/or written once, per the pass's flags), flags[i] = the pass flags
+ * (bit 1 generate |0...0>, 2 load psi, 4 store psi, 8 load lambda, 16 store
+ * lambda, 64 measure, 128 gradient), kind[i] = 0 dense pass, 1 light-cone batch.
+ * *count = number of records copied. */
+int qsim_timing_get(qsim_ctx* ctx, double* ms, double* bytes, int32_t* flags, int32_t* kind, int cap, int* count);
+
+/* ---- serving (continuous batching) ----------------------------------------------- */
+
+typedef struct {
+    const qsim_circuit* circuit;
+    const double* params;      /* host float64 [n_params] */
+    const qsim_hamiltonian* H;
+    int32_t want_grad;
+    int32_t pad;
+} qsim_request;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, cancelled, failed;
+    uint64_t steps, launches, inflight_bytes, peak_inflight_bytes;
+    uint64_t queued, running;
+} qsim_server_stats;
+
+/* Enqueue a request (deep copy).  EAGAIN when the queue is full, ETOOBIG when the
+ * request alone exceeds the memory budget.  Thread-safe. */
+int qsim_submit(qsim_ctx* ctx, const qsim_request* req, uint64_t* ticket);
+/* QSIM_PENDING while running; QSIM_OK once done: E[0] and, if the request asked
+ * for it, grad[n_params] are written and the ticket is consumed.  A failed or
+ * cancelled request returns its error code and is consumed.  Thread-safe. */
+int qsim_poll(qsim_ctx* ctx, uint64_t ticket, double* E, double* grad);
+/* Cancel a queued or running request.  Thread-safe. */
+int qsim_cancel(qsim_ctx* ctx, uint64_t ticket);
+int qsim_server_stats_get(qsim_ctx* ctx, qsim_server_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSIM_H */

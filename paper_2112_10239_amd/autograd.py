@@ -1,0 +1,50 @@
+"""``torch.autograd.Function`` over the library's forward pass and adjoint backward.
+
+The paper (Sec. 2, Sec. 3) gets gradients of expectation values by PyTorch
+Autograd backpropagation through the whole contraction.  Here the forward
+keeps only the final state of every batch row on the device, and the backward
+calls the library's adjoint sweep, which recomputes earlier states by
+applying inverse gates in reverse order (no stored activations).  torch only
+provides the parameter tensor, the stream and the chain-rule product with the
+incoming gradient.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import qsim
+
+
+def _stream_handle(t: torch.Tensor):
+    if t.is_cuda:
+        return torch.cuda.current_stream(t.device).cuda_stream
+    return None
+
+
+class Expectation(torch.autograd.Function):
+    """E[b] = <psi(theta_b)|H|psi(theta_b)> for theta of shape [B, P]."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, engine: "qsim.Context", circuit, hamiltonian):
+        th = theta.detach().to("cpu", torch.float64).contiguous().numpy().reshape(theta.shape[0], -1)
+        stream = _stream_handle(theta)
+        E, state = engine.expect_circuit(circuit, hamiltonian, th, mode=qsim.MODE_DENSE, dtype=qsim.C64,
+                                         stream=stream, keep=True)
+        ctx.engine, ctx.circuit, ctx.hamiltonian, ctx.state, ctx.theta_np = engine, circuit, hamiltonian, state, th
+        ctx.stream = stream
+        return torch.as_tensor(np.asarray(E, dtype=np.float64), device=theta.device).to(theta.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_E: torch.Tensor):
+        _, g = ctx.engine.expect_grad(ctx.circuit, ctx.hamiltonian, ctx.theta_np, dtype=qsim.C64, stream=ctx.stream,
+                                      saved=ctx.state, want_E=False)
+        ctx.state.destroy()
+        ctx.state = None
+        g = torch.as_tensor(np.asarray(g).reshape(ctx.theta_np.shape), device=grad_E.device, dtype=grad_E.dtype)
+        return grad_E.reshape(-1, 1) * g, None, None, None
+
+
+def expectation(theta: torch.Tensor, engine: "qsim.Context", circuit, hamiltonian) -> torch.Tensor:
+    """Differentiable <H>; theta [B, P] -> [B]."""
+    return Expectation.apply(theta, engine, circuit, hamiltonian)

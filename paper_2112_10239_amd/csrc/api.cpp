@@ -1,0 +1,430 @@
+// The C-ABI of libqsim (declared in include/qsim.h).
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "engine.h"
+#include "serve.h"
+
+using namespace qsim;
+
+#define HIP_TRY(expr, where)                                 \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, where);   \
+  } while (0)
+
+namespace {
+
+size_t amp_bytes(int dtype) { return dtype == QSIM_C128 ? 16 : 8; }
+
+bool valid_dtype(int dtype) { return dtype == QSIM_C64 || dtype == QSIM_C128; }
+
+hipStream_t pick_stream(qsim_ctx* ctx, void* stream) {
+  return stream ? reinterpret_cast<hipStream_t>(stream) : ctx->stream;
+}
+
+// Apply the state's queued gates; measure terms if given.
+int flush(qsim_state* st, const std::vector<Term>* terms, double* out) {
+  qsim_ctx* ctx = st->ctx;
+  const bool has_gates = !st->queue.gates.empty();
+  const bool need_store = has_gates || (st->fresh && !terms);
+  if (!has_gates && !terms && !st->fresh) return QSIM_OK;
+  st->queue.n = st->n;
+  int rc = QSIM_OK;
+  auto dp = get_dense_plan(ctx, st->queue, terms ? *terms : std::vector<Term>{}, st->dtype == QSIM_C128, st->fresh,
+                           need_store, terms != nullptr, rc);
+  if (!dp) return rc;
+  rc = run_dense(ctx, ctx->ws, *dp, st->queue, st->qparams.empty() ? nullptr : st->qparams.data(), st->batch,
+                 st->dtype == QSIM_C128, st->buf, nullptr, st->stream, out);
+  if (rc) return rc;
+  if (need_store) st->fresh = false;
+  st->queue.gates.clear();
+  st->queue.n_params = 0;
+  st->qparams.clear();
+  return QSIM_OK;
+}
+
+int check_state(qsim_state* st) { return (st && st->ctx) ? QSIM_OK : QSIM_EINVAL; }
+
+int no_device(qsim_ctx* ctx) {
+  set_error(ctx, "host-only context: no device");
+  return QSIM_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qsim_strerror(int code) {
+  switch (code) {
+    case QSIM_OK: return "ok";
+    case QSIM_PENDING: return "pending";
+    case QSIM_EINVAL: return "invalid argument";
+    case QSIM_ENOMEM: return "out of memory";
+    case QSIM_ETOOBIG: return "too big for the budget or the light-cone cap";
+    case QSIM_EAGAIN: return "queue full, retry";
+    case QSIM_ENOTFOUND: return "unknown or consumed ticket";
+    case QSIM_EDEVICE: return "device error";
+    case QSIM_ECANCELED: return "cancelled";
+    case QSIM_ESHUTDOWN: return "shut down";
+    default: return "unknown status";
+  }
+}
+
+const char* qsim_last_error(qsim_ctx* ctx) {
+  if (!ctx) return "";
+  std::lock_guard<std::mutex> g(ctx->err_mu);
+  return ctx->err.c_str();
+}
+
+int qsim_init(const qsim_options* opt, qsim_ctx** out) {
+  if (!out) return QSIM_EINVAL;
+  *out = nullptr;
+  qsim_ctx* ctx = new (std::nothrow) qsim_ctx();
+  if (!ctx) return QSIM_ENOMEM;
+  if (opt) ctx->opt = *opt;
+  if (ctx->opt.max_queue <= 0) ctx->opt.max_queue = 4096;
+  if (ctx->opt.cone_cap <= 0) ctx->opt.cone_cap = 20;
+  if (ctx->opt.hbm_budget_bytes == 0) ctx->opt.hbm_budget_bytes = 64ull << 30;
+  ctx->device = ctx->opt.device;
+  if (ctx->device < 0) {  // host-only context: planning and a simulated serving loop
+    ctx->mock = true;
+    *out = ctx;
+    return QSIM_OK;
+  }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= ctx->device || ctx->device < 0) {
+    delete ctx;
+    return QSIM_EDEVICE;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete ctx;
+    return QSIM_EDEVICE;
+  }
+  *out = ctx;
+  return QSIM_OK;
+}
+
+void qsim_finalize(qsim_ctx* ctx) {
+  if (!ctx) return;
+  ctx->server.reset();  // stops the scheduler; pending tickets end with QSIM_ESHUTDOWN
+  if (ctx->mock) {
+    delete ctx;
+    return;
+  }
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->plans.clear();
+  ctx->ws.release();
+  ctx->psi.release();
+  (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+int qsim_create_state(qsim_ctx* ctx, int n_qubits, int batch, int dtype, void* dev_buf, void* stream,
+                      qsim_state** out) {
+  if (!ctx || !out) return QSIM_EINVAL;
+  *out = nullptr;
+  if (ctx->mock) return no_device(ctx);
+  if (n_qubits < 1 || n_qubits > kMaxQubits || batch < 1 || !valid_dtype(dtype)) {
+    set_error(ctx, "create_state: n_qubits in [1, 40], batch >= 1 and dtype C64/C128 required");
+    return QSIM_EINVAL;
+  }
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  qsim_state* st = new (std::nothrow) qsim_state();
+  if (!st) return QSIM_ENOMEM;
+  st->ctx = ctx;
+  st->n = n_qubits;
+  st->batch = batch;
+  st->dtype = dtype;
+  st->stream = pick_stream(ctx, stream);
+  st->queue.n = n_qubits;
+  if (dev_buf) {
+    st->buf = dev_buf;
+    st->owned = false;
+  } else {
+    const size_t bytes = (size_t)batch * ((size_t)1 << n_qubits) * amp_bytes(dtype);
+    hipError_t e = hipMalloc(&st->buf, bytes);
+    if (e != hipSuccess) {
+      delete st;
+      return hip_fail(ctx, e, "state allocation");
+    }
+  }
+  *out = st;
+  return QSIM_OK;
+}
+
+int qsim_destroy_state(qsim_state* st) {
+  if (!st) return QSIM_EINVAL;
+  if (st->ctx) {
+    (void)hipSetDevice(st->ctx->device);
+    (void)hipStreamSynchronize(st->stream);
+  }
+  if (st->owned && st->buf) (void)hipFree(st->buf);
+  delete st;
+  return QSIM_OK;
+}
+
+int qsim_apply_layer(qsim_state* st, const qsim_gate* gates, int n_gates, const double* params, int n_params) {
+  if (check_state(st)) return QSIM_EINVAL;
+  qsim_ctx* ctx = st->ctx;
+  if (n_gates < 0 || n_params < 0) return QSIM_EINVAL;
+  qsim_circuit view{st->n, n_gates, n_params, 0, gates};
+  CircuitDesc layer;
+  int rc = to_circuit(ctx, &view, layer);
+  if (rc) return rc;
+  bool uses = false;
+  for (const Gate& g : layer.gates) uses |= g.param >= 0;
+  if (uses && !params) {
+    set_error(ctx, "apply_layer: parameterised gates need params");
+    return QSIM_EINVAL;
+  }
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  const int old = st->queue.n_params;
+  for (Gate x : layer.gates) {
+    if (x.param >= 0) x.param += old;
+    st->queue.gates.push_back(x);
+  }
+  const int total = old + n_params;
+  std::vector<double> np((size_t)st->batch * total);
+  for (int b = 0; b < st->batch; ++b) {
+    for (int k = 0; k < old; ++k) np[(size_t)b * total + k] = st->qparams[(size_t)b * old + k];
+    for (int k = 0; k < n_params; ++k) np[(size_t)b * total + old + k] = params[(size_t)b * n_params + k];
+  }
+  st->qparams.swap(np);
+  st->queue.n_params = total;
+  return QSIM_OK;
+}
+
+int qsim_expect(qsim_state* st, const qsim_hamiltonian* H, double* out) {
+  if (check_state(st) || !out) return QSIM_EINVAL;
+  qsim_ctx* ctx = st->ctx;
+  std::vector<Term> terms;
+  int rc = to_terms(ctx, H, st->n, terms);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  return flush(st, &terms, out);
+}
+
+int qsim_state_to_host(qsim_state* st, void* host) {
+  if (check_state(st) || !host) return QSIM_EINVAL;
+  qsim_ctx* ctx = st->ctx;
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  int rc = flush(st, nullptr, nullptr);
+  if (rc) return rc;
+  const size_t bytes = (size_t)st->batch * ((size_t)1 << st->n) * amp_bytes(st->dtype);
+  HIP_TRY(hipMemcpyAsync(host, st->buf, bytes, hipMemcpyDeviceToHost, st->stream), "state copy");
+  HIP_TRY(hipStreamSynchronize(st->stream), "stream sync");
+  return QSIM_OK;
+}
+
+int qsim_state_device_ptr(qsim_state* st, void** ptr) {
+  if (check_state(st) || !ptr) return QSIM_EINVAL;
+  qsim_ctx* ctx = st->ctx;
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  int rc = flush(st, nullptr, nullptr);
+  if (rc) return rc;
+  *ptr = st->buf;
+  return QSIM_OK;
+}
+
+int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
+                        const qsim_hamiltonian* H, int mode, int dtype, void* stream, double* out, qsim_state** keep) {
+  if (!ctx || !out || batch < 1 || !valid_dtype(dtype)) return QSIM_EINVAL;
+  if (keep) *keep = nullptr;
+  if (ctx->mock) return no_device(ctx);
+  CircuitDesc cd;
+  int rc = to_circuit(ctx, c, cd);
+  if (rc) return rc;
+  std::vector<Term> terms;
+  if ((rc = to_terms(ctx, H, cd.n, terms))) return rc;
+  if (cd.n_params > 0 && !params) {
+    set_error(ctx, "expect_circuit: params missing");
+    return QSIM_EINVAL;
+  }
+  if (mode == QSIM_MODE_AUTO) mode = (cd.n > 30 && !keep) ? QSIM_MODE_LIGHTCONE : QSIM_MODE_DENSE;
+  const int c128 = dtype == QSIM_C128;
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  hipStream_t st = pick_stream(ctx, stream);
+  if (mode == QSIM_MODE_LIGHTCONE) {
+    if (keep) {
+      set_error(ctx, "expect_circuit: keep is only available in dense mode");
+      return QSIM_EINVAL;
+    }
+    auto dp = get_cone_plan(ctx, cd, terms, c128, rc);
+    if (!dp) return rc;
+    for (int b = 0; b < batch; ++b) {
+      rc = run_cones(ctx, ctx->ws, *dp, cd, params ? params + (size_t)b * cd.n_params : nullptr, c128, st, out + b);
+      if (rc) return rc;
+    }
+    return QSIM_OK;
+  }
+  if (mode != QSIM_MODE_DENSE) return QSIM_EINVAL;
+  if (cd.n > kMaxQubits) {
+    set_error(ctx, "dense mode supports at most 40 qubits");
+    return QSIM_ETOOBIG;
+  }
+  auto dp = get_dense_plan(ctx, cd, terms, c128, true, keep != nullptr, true, rc);
+  if (!dp) return rc;
+  const size_t bytes = (size_t)batch * ((size_t)1 << cd.n) * amp_bytes(dtype);
+  void* A = nullptr;
+  if (keep) {
+    HIP_TRY(hipMalloc(&A, bytes), "state allocation");
+  } else {
+    HIP_TRY(ctx->psi.ensure(bytes), "state workspace");
+    A = ctx->psi.p;
+  }
+  rc = run_dense(ctx, ctx->ws, *dp, cd, params, batch, c128, A, nullptr, st, out);
+  if (rc) {
+    if (keep) (void)hipFree(A);
+    return rc;
+  }
+  if (keep) {
+    qsim_state* s = new (std::nothrow) qsim_state();
+    if (!s) {
+      (void)hipFree(A);
+      return QSIM_ENOMEM;
+    }
+    s->ctx = ctx;
+    s->n = cd.n;
+    s->batch = batch;
+    s->dtype = dtype;
+    s->buf = A;
+    s->owned = true;
+    s->fresh = false;
+    s->stream = st;
+    s->queue.n = cd.n;
+    *keep = s;
+  }
+  return QSIM_OK;
+}
+
+int qsim_expect_grad(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch, const qsim_hamiltonian* H,
+                     int dtype, void* stream, qsim_state* saved, double* E, double* grad) {
+  if (!ctx || batch < 1 || !valid_dtype(dtype) || !grad) return QSIM_EINVAL;
+  if (ctx->mock) return no_device(ctx);
+  CircuitDesc cd;
+  int rc = to_circuit(ctx, c, cd);
+  if (rc) return rc;
+  std::vector<Term> terms;
+  if ((rc = to_terms(ctx, H, cd.n, terms))) return rc;
+  if (cd.n_params > 0 && !params) {
+    set_error(ctx, "expect_grad: params missing");
+    return QSIM_EINVAL;
+  }
+  if (cd.n > kMaxQubits) {
+    set_error(ctx, "gradients use the dense mode: at most 40 qubits");
+    return QSIM_ETOOBIG;
+  }
+  if (saved && (saved->n != cd.n || saved->batch != batch || saved->dtype != dtype || !saved->queue.gates.empty())) {
+    set_error(ctx, "expect_grad: saved state does not match the circuit, batch or dtype");
+    return QSIM_EINVAL;
+  }
+  const int c128 = dtype == QSIM_C128;
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  hipStream_t st = pick_stream(ctx, stream);
+  const size_t bytes = (size_t)batch * ((size_t)1 << cd.n) * amp_bytes(dtype);
+  void* A = nullptr;
+  if (saved) {
+    A = saved->buf;
+    if (E) {  // <H> of the saved state: a measurement-only plan
+      CircuitDesc empty;
+      empty.n = cd.n;
+      auto mp = get_dense_plan(ctx, empty, terms, c128, false, false, true, rc);
+      if (!mp) return rc;
+      if ((rc = run_dense(ctx, ctx->ws, *mp, empty, nullptr, batch, c128, A, nullptr, st, E))) return rc;
+    }
+  } else {
+    auto fp = get_dense_plan(ctx, cd, terms, c128, true, true, true, rc);
+    if (!fp) return rc;
+    HIP_TRY(ctx->psi.ensure(bytes), "state workspace");
+    A = ctx->psi.p;
+    std::vector<double> e_tmp(batch);
+    if ((rc = run_dense(ctx, ctx->ws, *fp, cd, params, batch, c128, A, nullptr, st, E ? E : e_tmp.data()))) return rc;
+  }
+  std::shared_ptr<DevPlan> hp;
+  auto ap = get_grad_plans(ctx, cd, terms, c128, hp, rc);
+  if (!ap) return rc;
+  HIP_TRY(ctx->ws.lambda.ensure(bytes), "lambda workspace");
+  return run_grad(ctx, ctx->ws, *hp, *ap, cd, params, batch, c128, A, ctx->ws.lambda.p, st, grad);
+}
+
+int qsim_timing_enable(qsim_ctx* ctx, int on) {
+  if (!ctx) return QSIM_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  if (on) ctx->tdone.clear();
+  ctx->timing = on != 0;
+  return QSIM_OK;
+}
+
+int qsim_timing_get(qsim_ctx* ctx, double* ms, double* bytes, int32_t* flags, int32_t* kind, int cap, int* count) {
+  if (!ctx || !count) return QSIM_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  const int n = std::min<int>(cap, (int)ctx->tdone.size());
+  for (int i = 0; i < n; ++i) {
+    if (ms) ms[i] = ctx->tdone[i].ms;
+    if (bytes) bytes[i] = ctx->tdone[i].bytes;
+    if (flags) flags[i] = ctx->tdone[i].flags;
+    if (kind) kind[i] = ctx->tdone[i].kind;
+  }
+  *count = n;
+  return QSIM_OK;
+}
+
+int qsim_lightcone_sets(const qsim_circuit* c, const qsim_hamiltonian* H, int32_t* off, int32_t* qubits, int cap) {
+  if (!off || (cap > 0 && !qubits)) return QSIM_EINVAL;
+  CircuitDesc cd;
+  int rc = to_circuit(nullptr, c, cd);
+  if (rc) return rc;
+  std::vector<Term> terms;
+  if ((rc = to_terms(nullptr, H, cd.n, terms))) return rc;
+  int pos = 0;
+  off[0] = 0;
+  for (size_t t = 0; t < terms.size(); ++t) {
+    std::vector<int> support, set, gates;
+    for (auto [q, L] : terms[t].ops) support.push_back(q);
+    light_cone(cd, support, set, gates);
+    if (pos + (int)set.size() > cap) return QSIM_ETOOBIG;
+    for (int q : set) qubits[pos++] = q;
+    off[t + 1] = pos;
+  }
+  return QSIM_OK;
+}
+
+int qsim_plan_dense(const qsim_circuit* c, const qsim_hamiltonian* H, int dtype, int64_t* info, int32_t* order,
+                    int cap_entries) {
+  if (!info || !valid_dtype(dtype)) return QSIM_EINVAL;
+  CircuitDesc cd;
+  int rc = to_circuit(nullptr, c, cd);
+  if (rc) return rc;
+  std::vector<Term> terms;
+  if (H && (rc = to_terms(nullptr, H, cd.n, terms))) return rc;
+  if (cd.n > kMaxQubits) return QSIM_ETOOBIG;
+  Plan plan;
+  std::vector<PGate> pg, meas;
+  forward_pgates(cd, true, pg, plan.slots);
+  double cst = 0;
+  term_pgates(terms, false, meas, cst);
+  PlanOptions o = fwd_options(dtype == QSIM_C128);
+  std::string err;
+  if (plan_forward(cd.n, pg, meas, o, plan, err)) return QSIM_EINVAL;
+  info[0] = (int64_t)plan.passes.size();
+  info[1] = (int64_t)plan.stages.size();
+  info[2] = (int64_t)plan.ops.size();
+  info[3] = plan.meas_passes;
+  if (order) {
+    if ((int)plan.order.size() / 4 > cap_entries) return QSIM_ETOOBIG;
+    std::memcpy(order, plan.order.data(), plan.order.size() * sizeof(int32_t));
+  }
+  return QSIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,593 @@
+// Evaluation paths: dense passes, light-cone batches and the adjoint sweep.
+#include "engine.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace qsim {
+
+void set_error(qsim_ctx* ctx, const std::string& msg) {
+  if (!ctx) return;
+  std::lock_guard<std::mutex> g(ctx->err_mu);
+  ctx->err = msg;
+}
+
+int hip_fail(qsim_ctx* ctx, hipError_t e, const char* where) {
+  set_error(ctx, std::string(where) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? QSIM_ENOMEM : QSIM_EDEVICE;
+}
+
+#define HIP_TRY(expr, where)                       \
+  do {                                             \
+    hipError_t _e = (expr);                        \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
+  } while (0)
+
+int timing_begin(qsim_ctx* ctx, hipStream_t st, double bytes, int flags, int kind) {
+  if (!ctx->timing) return -1;
+  TimingRec r;
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+  r.bytes = bytes;
+  r.flags = flags;
+  r.kind = kind;
+  (void)hipEventRecord(r.a, st);
+  ctx->tpending.push_back(r);
+  return (int)ctx->tpending.size() - 1;
+}
+
+void timing_end(qsim_ctx* ctx, int idx, hipStream_t st) {
+  if (idx >= 0) (void)hipEventRecord(ctx->tpending[idx].b, st);
+}
+
+void timing_collect(qsim_ctx* ctx) {
+  for (TimingRec& r : ctx->tpending) {
+    float ms = 0.f;
+    (void)hipEventSynchronize(r.b);
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    r.ms = ms;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+    r.a = r.b = nullptr;
+    ctx->tdone.push_back(r);
+  }
+  ctx->tpending.clear();
+}
+
+static double pass_bytes(const PassDesc& p, int rows, int c128) {
+  const double amps = (double)rows * (double)(1ull << p.n);
+  int k = 0;
+  k += (p.flags & PF_LOAD_A) ? 1 : 0;
+  k += (p.flags & PF_STORE_A) ? 1 : 0;
+  k += (p.flags & PF_LOAD_B) ? 1 : 0;
+  k += (p.flags & PF_STORE_B) ? 1 : 0;
+  return amps * k * (c128 ? 16.0 : 8.0);
+}
+
+PlanOptions fwd_options(int c128) {
+  PlanOptions o;
+  o.m_max = c128 ? 13 : 14;
+  o.r = 4;
+  o.c_low = 6;
+  return o;
+}
+
+PlanOptions dual_options(int c128) {
+  PlanOptions o;
+  o.m_max = c128 ? 12 : 13;
+  o.r = c128 ? 3 : 4;
+  o.c_low = 6;
+  o.fuse = false;
+  return o;
+}
+
+DevPlan::~DevPlan() {
+  (void)hipFree(d_passes);
+  (void)hipFree(d_stages);
+  (void)hipFree(d_ops);
+  (void)hipFree(d_cones);
+  (void)hipFree(d_order);
+  (void)hipFree(d_poff);
+  (void)hipFree(d_pslots);
+}
+
+template <class V>
+static hipError_t upload_vec(const std::vector<V>& v, V** d) {
+  const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(V);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(d), bytes);
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(*d, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice);
+  return e;
+}
+
+hipError_t DevPlan::upload(bool mock) {
+  if (mock) return hipSuccess;
+  hipError_t e;
+  if ((e = upload_vec(plan.passes, &d_passes)) != hipSuccess) return e;
+  if ((e = upload_vec(plan.stages, &d_stages)) != hipSuccess) return e;
+  if ((e = upload_vec(plan.ops, &d_ops)) != hipSuccess) return e;
+  if (!cones.empty()) {
+    if ((e = upload_vec(cones, &d_cones)) != hipSuccess) return e;
+    if ((e = upload_vec(order, &d_order)) != hipSuccess) return e;
+  }
+  if (plan.n_gslots > 0) {
+    int np = 0;
+    for (int p : plan.gslot_param) np = std::max(np, p + 1);
+    std::vector<int32_t> off(np + 1, 0), slots;
+    for (int p : plan.gslot_param) off[p + 1]++;
+    for (int p = 0; p < np; ++p) off[p + 1] += off[p];
+    slots.resize(plan.gslot_param.size());
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int s = 0; s < (int)plan.gslot_param.size(); ++s) slots[fill[plan.gslot_param[s]]++] = s;
+    if ((e = upload_vec(off, &d_poff)) != hipSuccess) return e;
+    if ((e = upload_vec(slots, &d_pslots)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// conversions
+// ---------------------------------------------------------------------------
+
+int to_circuit(qsim_ctx* ctx, const qsim_circuit* c, CircuitDesc& out) {
+  if (!c || c->n_gates < 0 || (c->n_gates > 0 && !c->gates)) {
+    set_error(ctx, "circuit: null or negative gate count");
+    return QSIM_EINVAL;
+  }
+  out.n = c->n_qubits;
+  out.n_params = c->n_params;
+  out.gates.resize(c->n_gates);
+  for (int g = 0; g < c->n_gates; ++g) {
+    const qsim_gate& x = c->gates[g];
+    Gate& y = out.gates[g];
+    y.kind = x.kind;
+    y.q0 = x.q0;
+    y.q1 = x.q1;
+    y.param = (x.kind == QSIM_RX || x.kind == QSIM_RY || x.kind == QSIM_RZ) ? x.param : -1;
+    if (y.param < -1) y.param = -1;
+    y.angle = x.angle;
+    std::memset(y.mat, 0, sizeof(y.mat));
+    if (x.kind == QSIM_U1) {
+      if (!x.mat) {
+        set_error(ctx, "gate " + std::to_string(g) + ": U1 without a matrix");
+        return QSIM_EINVAL;
+      }
+      std::memcpy(y.mat, x.mat, sizeof(y.mat));
+    }
+  }
+  const std::string err = validate_circuit(out);
+  if (!err.empty()) {
+    set_error(ctx, "circuit: " + err);
+    return QSIM_EINVAL;
+  }
+  return QSIM_OK;
+}
+
+int to_terms(qsim_ctx* ctx, const qsim_hamiltonian* H, int n, std::vector<Term>& out) {
+  out.clear();
+  if (!H) {
+    set_error(ctx, "hamiltonian: null");
+    return QSIM_EINVAL;
+  }
+  if (H->n_terms < 0 || (H->n_terms > 0 && (!H->coeff || !H->term_off))) {
+    set_error(ctx, "hamiltonian: bad arrays");
+    return QSIM_EINVAL;
+  }
+  out.resize(H->n_terms);
+  for (int t = 0; t < H->n_terms; ++t) {
+    const int a = H->term_off[t], b = H->term_off[t + 1];
+    if (b < a || (b > a && (!H->qubits || !H->paulis))) {
+      set_error(ctx, "hamiltonian: bad term offsets");
+      return QSIM_EINVAL;
+    }
+    out[t].c = H->coeff[t];
+    for (int k = a; k < b; ++k) out[t].ops.emplace_back(H->qubits[k], (char)H->paulis[k]);
+  }
+  const std::string err = validate_terms(out, n);
+  if (!err.empty()) {
+    set_error(ctx, "hamiltonian: " + err);
+    return QSIM_EINVAL;
+  }
+  return QSIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+
+static std::shared_ptr<DevPlan> cache_get(qsim_ctx* ctx, uint64_t key) {
+  std::lock_guard<std::mutex> g(ctx->plan_mu);
+  auto it = ctx->plans.find(key);
+  return it == ctx->plans.end() ? nullptr : it->second;
+}
+
+static void cache_put(qsim_ctx* ctx, uint64_t key, std::shared_ptr<DevPlan> p) {
+  std::lock_guard<std::mutex> g(ctx->plan_mu);
+  if (ctx->plans.size() >= 256) ctx->plans.clear();
+  ctx->plans[key] = std::move(p);
+}
+
+std::shared_ptr<DevPlan> get_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
+                                        int c128, bool init, bool store_final, bool measure, int& rc) {
+  rc = QSIM_OK;
+  const int extra = 0x100 | c128 | (init << 1) | (store_final << 2) | (measure << 3);
+  const uint64_t key = structure_hash(c, measure ? terms : std::vector<Term>{}, extra);
+  if (auto p = cache_get(ctx, key)) return p;
+  auto dp = std::make_shared<DevPlan>();
+  std::vector<PGate> pg, meas;
+  forward_pgates(c, true, pg, dp->plan.slots);
+  double cst = 0;
+  if (measure) term_pgates(terms, false, meas, cst);
+  PlanOptions o = fwd_options(c128);
+  o.init = init;
+  o.store_final = store_final;
+  std::string err;
+  if (plan_forward(c.n, pg, meas, o, dp->plan, err)) {
+    set_error(ctx, err);
+    rc = QSIM_EINVAL;
+    return nullptr;
+  }
+  dp->plan.const_term = cst;
+  hipError_t e = dp->upload(ctx->mock);
+  if (e != hipSuccess) {
+    rc = hip_fail(ctx, e, "plan upload");
+    return nullptr;
+  }
+  cache_put(ctx, key, dp);
+  return dp;
+}
+
+std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
+                                        int c128, std::shared_ptr<DevPlan>& happly, int& rc) {
+  rc = QSIM_OK;
+  const PlanOptions o = dual_options(c128);
+  // lambda = H psi
+  {
+    CircuitDesc shape;
+    shape.n = c.n;
+    const uint64_t key = structure_hash(shape, terms, 0x300 | c128);
+    happly = cache_get(ctx, key);
+    if (!happly) {
+      auto dp = std::make_shared<DevPlan>();
+      std::vector<PGate> ht;
+      double cst = 0;
+      term_pgates(terms, true, ht, cst);
+      // identity terms: lambda gets c * psi as a diagonal term with an empty mask
+      if (cst != 0.0) {
+        PGate p;
+        p.kind = PG_H_Z;
+        p.c = cst;
+        ht.push_back(p);
+      }
+      std::string err;
+      if (plan_happly(c.n, ht, o, dp->plan, err)) {
+        set_error(ctx, err);
+        rc = QSIM_EINVAL;
+        return nullptr;
+      }
+      hipError_t e = dp->upload(ctx->mock);
+      if (e != hipSuccess) {
+        rc = hip_fail(ctx, e, "plan upload");
+        return nullptr;
+      }
+      cache_put(ctx, key, dp);
+      happly = dp;
+    }
+  }
+  const uint64_t key = structure_hash(c, {}, 0x200 | c128);
+  if (auto p = cache_get(ctx, key)) return p;
+  auto dp = std::make_shared<DevPlan>();
+  std::vector<PGate> pg;
+  std::vector<int> gsp;
+  adjoint_pgates(c, pg, dp->plan.slots, gsp);
+  std::string err;
+  if (plan_adjoint(c.n, pg, o, dp->plan, err)) {
+    set_error(ctx, err);
+    rc = QSIM_EINVAL;
+    return nullptr;
+  }
+  hipError_t e = dp->upload(ctx->mock);
+  if (e != hipSuccess) {
+    rc = hip_fail(ctx, e, "plan upload");
+    return nullptr;
+  }
+  cache_put(ctx, key, dp);
+  return dp;
+}
+
+std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, int c128,
+                                       int& rc) {
+  rc = QSIM_OK;
+  const uint64_t key = structure_hash(c, terms, 0x400 | c128);
+  if (auto p = cache_get(ctx, key)) return p;
+  auto dp = std::make_shared<DevPlan>();
+  Plan& all = dp->plan;
+  const PlanOptions base = fwd_options(c128);
+  const int cap = ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20;
+  std::vector<int> relabel(c.n, -1);
+  for (const Term& t : terms) {
+    if (t.ops.empty()) {
+      all.const_term += t.c;
+      continue;
+    }
+    std::vector<int> support, set, gates;
+    for (auto [q, L] : t.ops) support.push_back(q);
+    light_cone(c, support, set, gates);
+    const int s = (int)set.size();
+    if (s > cap) {
+      set_error(ctx, "light cone of " + std::to_string(s) + " qubits exceeds the cap of " + std::to_string(cap));
+      rc = QSIM_ETOOBIG;
+      return nullptr;
+    }
+    const int s_eff = std::max(s, 4);  // the cone kernel holds 16 amplitudes per thread
+    for (int k = 0; k < s; ++k) relabel[set[k]] = k;
+    CircuitDesc sub;
+    sub.n = s_eff;
+    sub.n_params = c.n_params;
+    for (int g : gates) {
+      Gate x = c.gates[g];
+      x.q0 = relabel[x.q0];
+      if (x.kind == G_CZ || x.kind == G_CNOT) x.q1 = relabel[x.q1];
+      sub.gates.push_back(x);
+    }
+    std::vector<PGate> pg, slots, meas;
+    forward_pgates(sub, true, pg, slots);
+    for (auto* v : {&pg, &slots})
+      for (PGate& p : *v)
+        for (int& src : p.srcs) src = gates[src];
+    double cst = 0;
+    term_pgates({t}, false, meas, cst, &relabel);
+    PlanOptions o = base;
+    o.init = true;
+    o.store_final = false;
+    Plan cp;
+    std::string err;
+    if (plan_forward(s_eff, pg, meas, o, cp, err)) {
+      set_error(ctx, err);
+      rc = QSIM_EINVAL;
+      return nullptr;
+    }
+    for (int k = 0; k < s; ++k) relabel[set[k]] = -1;
+    ConeDesc cd;
+    std::memset(&cd, 0, sizeof(cd));
+    cd.pass_begin = (int)all.passes.size();
+    cd.pass_end = cd.pass_begin + (int)cp.passes.size();
+    cd.coef_begin = (int)all.slots.size();
+    cd.out_index = (int)dp->cones.size();
+    cd.n = s_eff;
+    if (s_eff > cp.m) {
+      cd.scratch_off = dp->scratch_amps;
+      dp->scratch_amps += 1ll << s_eff;
+    }
+    const int sb = (int)all.stages.size(), ob = (int)all.ops.size();
+    for (PassDesc pd : cp.passes) {
+      pd.stage_begin += sb;
+      pd.stage_end += sb;
+      if (pd.store_stage >= 0) pd.store_stage += sb;
+      all.passes.push_back(pd);
+    }
+    for (StageDesc st : cp.stages) {
+      st.op_begin += ob;
+      st.op_end += ob;
+      all.stages.push_back(st);
+    }
+    all.ops.insert(all.ops.end(), cp.ops.begin(), cp.ops.end());
+    all.slots.insert(all.slots.end(), slots.begin(), slots.end());
+    dp->cone_m_max = std::max(dp->cone_m_max, cp.m);
+    dp->cones.push_back(cd);
+  }
+  // largest cones first, so the tail of the launch holds the short ones
+  dp->order.resize(dp->cones.size());
+  for (int i = 0; i < (int)dp->order.size(); ++i) dp->order[i] = i;
+  std::stable_sort(dp->order.begin(), dp->order.end(), [&](int a, int b) {
+    const ConeDesc &x = dp->cones[a], &y = dp->cones[b];
+    const int ox = all.stages[all.passes[x.pass_end - 1].stage_end - 1].op_end -
+                   all.stages[all.passes[x.pass_begin].stage_begin].op_begin;
+    const int oy = all.stages[all.passes[y.pass_end - 1].stage_end - 1].op_end -
+                   all.stages[all.passes[y.pass_begin].stage_begin].op_begin;
+    if (x.n != y.n) return x.n > y.n;
+    return ox > oy;
+  });
+  all.n = c.n;
+  all.r = 4;
+  hipError_t e = dp->upload(ctx->mock);
+  if (e != hipSuccess) {
+    rc = hip_fail(ctx, e, "plan upload");
+    return nullptr;
+  }
+  cache_put(ctx, key, dp);
+  return dp;
+}
+
+// ---------------------------------------------------------------------------
+// runs
+// ---------------------------------------------------------------------------
+
+static int stage_coefficients(qsim_ctx* ctx, Workspace& ws, const CircuitDesc& c, const std::vector<PGate>& slots,
+                              const double* params, int rows, int c128, hipStream_t st, int64_t& crs) {
+  const size_t scal = c128 ? 8 : 4;
+  crs = (int64_t)std::max<size_t>(1, slots.size()) * 8;
+  const size_t bytes = (size_t)rows * crs * scal;
+  HIP_TRY(ws.h_coef.ensure(bytes), "pinned coefficient buffer");
+  HIP_TRY(ws.coef.ensure(bytes), "coefficient buffer");
+  if (c128) build_coefficients<double>(c, slots, params, rows, crs, (double*)ws.h_coef.p);
+  else build_coefficients<float>(c, slots, params, rows, crs, (float*)ws.h_coef.p);
+  HIP_TRY(hipMemcpyAsync(ws.coef.p, ws.h_coef.p, bytes, hipMemcpyHostToDevice, st), "coefficient upload");
+  return QSIM_OK;
+}
+
+static int fetch_out(qsim_ctx* ctx, Workspace& ws, size_t count, hipStream_t st, double* out_host) {
+  HIP_TRY(ws.h_out.ensure(count * sizeof(double)), "pinned result buffer");
+  HIP_TRY(hipMemcpyAsync(ws.h_out.p, ws.out.p, count * sizeof(double), hipMemcpyDeviceToHost, st), "result copy");
+  HIP_TRY(hipStreamSynchronize(st), "stream sync");
+  timing_collect(ctx);
+  std::memcpy(out_host, ws.h_out.p, count * sizeof(double));
+  return QSIM_OK;
+}
+
+int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params, int rows,
+              int c128, void* A, void* B, hipStream_t st, double* out_host) {
+  const Plan& P = dp.plan;
+  int64_t crs = 8;
+  int rc = stage_coefficients(ctx, ws, c, P.slots, params, rows, c128, st, crs);
+  if (rc) return rc;
+  const int64_t tiles = 1ll << (P.n - P.m);
+  if (P.n_meas > 0) HIP_TRY(ws.meas.ensure((size_t)rows * P.n_meas * tiles * sizeof(double)), "partials buffer");
+  for (size_t p = 0; p < P.passes.size(); ++p) {
+    PassLaunch L;
+    L.d_pass = dp.d_passes + p;
+    L.h_pass = &P.passes[p];
+    L.d_stages = dp.d_stages;
+    L.d_ops = dp.d_ops;
+    L.A = A;
+    L.B = B;
+    L.row_stride = 1ll << P.n;
+    L.coef = ws.coef.p;
+    L.coef_row_stride = crs;
+    L.meas = (double*)ws.meas.p;
+    L.n_meas = P.n_meas;
+    L.grad = nullptr;
+    L.n_gslots = 0;
+    L.rows = rows;
+    L.c128 = c128;
+    L.dual = 0;
+    const int ti = timing_begin(ctx, st, pass_bytes(P.passes[p], rows, c128), P.passes[p].flags, 0);
+    HIP_TRY(launch_pass(L, st), "pass launch");
+    timing_end(ctx, ti, st);
+  }
+  if (out_host) {
+    if (P.n_meas == 0) {
+      HIP_TRY(hipStreamSynchronize(st), "stream sync");
+      timing_collect(ctx);
+      for (int r = 0; r < rows; ++r) out_host[r] = P.const_term;
+      return QSIM_OK;
+    }
+    HIP_TRY(ws.out.ensure((size_t)rows * sizeof(double)), "result buffer");
+    HIP_TRY(launch_reduce_rows((const double*)ws.meas.p, rows, (int64_t)P.n_meas * tiles, P.const_term,
+                               (double*)ws.out.p, st),
+            "reduce launch");
+    return fetch_out(ctx, ws, rows, st, out_host);
+  }
+  HIP_TRY(hipStreamSynchronize(st), "stream sync");
+  timing_collect(ctx);
+  return QSIM_OK;
+}
+
+int run_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& hp, const DevPlan& ap, const CircuitDesc& c,
+             const double* params, int rows, int c128, void* A, void* B, hipStream_t st, double* grad_host) {
+  const Plan& H = hp.plan;
+  const Plan& P = ap.plan;
+  int64_t crs = 8;
+  int rc = stage_coefficients(ctx, ws, c, P.slots, params, rows, c128, st, crs);
+  if (rc) return rc;
+  auto mk = [&](const DevPlan& d, size_t p) {
+    PassLaunch L;
+    L.d_pass = d.d_passes + p;
+    L.h_pass = &d.plan.passes[p];
+    L.d_stages = d.d_stages;
+    L.d_ops = d.d_ops;
+    L.A = A;
+    L.B = B;
+    L.row_stride = 1ll << d.plan.n;
+    L.coef = ws.coef.p;
+    L.coef_row_stride = crs;
+    L.meas = nullptr;
+    L.n_meas = 0;
+    L.grad = (double*)ws.grad.p;
+    L.n_gslots = d.plan.n_gslots;
+    L.rows = rows;
+    L.c128 = c128;
+    L.dual = 1;
+    return L;
+  };
+  const int64_t tiles = 1ll << (P.n - P.m);
+  const int ns = P.n_gslots;
+  if (ns > 0) HIP_TRY(ws.grad.ensure((size_t)rows * ns * tiles * sizeof(double)), "gradient partials");
+  for (size_t p = 0; p < H.passes.size(); ++p) {
+    const int ti = timing_begin(ctx, st, pass_bytes(H.passes[p], rows, c128), H.passes[p].flags, 0);
+    HIP_TRY(launch_pass(mk(hp, p), st), "H-apply launch");
+    timing_end(ctx, ti, st);
+  }
+  for (size_t p = 0; p < P.passes.size(); ++p) {
+    const int ti = timing_begin(ctx, st, pass_bytes(P.passes[p], rows, c128), P.passes[p].flags, 0);
+    HIP_TRY(launch_pass(mk(ap, p), st), "adjoint launch");
+    timing_end(ctx, ti, st);
+  }
+  const int np = c.n_params;
+  if (np == 0) {
+    HIP_TRY(hipStreamSynchronize(st), "stream sync");
+    timing_collect(ctx);
+    return QSIM_OK;
+  }
+  if (ns == 0) {
+    HIP_TRY(hipStreamSynchronize(st), "stream sync");
+    timing_collect(ctx);
+    std::memset(grad_host, 0, sizeof(double) * (size_t)rows * np);
+    return QSIM_OK;
+  }
+  HIP_TRY(ws.slot_total.ensure((size_t)rows * ns * sizeof(double)), "slot totals");
+  HIP_TRY(launch_reduce_rows((const double*)ws.grad.p, rows * ns, tiles, 0.0, (double*)ws.slot_total.p, st),
+          "gradient reduce");
+  // parameters that no gate uses keep a zero gradient: CSR covers [0, max used param]
+  int np_used = 0;
+  for (int p : P.gslot_param) np_used = std::max(np_used, p + 1);
+  HIP_TRY(ws.out.ensure((size_t)rows * np * sizeof(double)), "gradient buffer");
+  if (np_used == np) {
+    HIP_TRY(launch_grad_scatter((const double*)ws.slot_total.p, rows, ns, ap.d_poff, ap.d_pslots, np,
+                                (double*)ws.out.p, st),
+            "gradient scatter");
+    return fetch_out(ctx, ws, (size_t)rows * np, st, grad_host);
+  }
+  // fewer used parameters than declared: scatter into a [rows][np_used] block, then widen on the host
+  HIP_TRY(launch_grad_scatter((const double*)ws.slot_total.p, rows, ns, ap.d_poff, ap.d_pslots, np_used,
+                              (double*)ws.out.p, st),
+          "gradient scatter");
+  std::vector<double> tmp((size_t)rows * np_used);
+  rc = fetch_out(ctx, ws, tmp.size(), st, tmp.data());
+  if (rc) return rc;
+  for (int r = 0; r < rows; ++r) {
+    std::memcpy(grad_host + (size_t)r * np, tmp.data() + (size_t)r * np_used, sizeof(double) * np_used);
+    std::memset(grad_host + (size_t)r * np + np_used, 0, sizeof(double) * (np - np_used));
+  }
+  return QSIM_OK;
+}
+
+int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params, int c128,
+              hipStream_t st, double* out_host) {
+  const Plan& P = dp.plan;
+  if (dp.cones.empty()) {
+    *out_host = P.const_term;
+    return QSIM_OK;
+  }
+  int64_t crs = 8;
+  int rc = stage_coefficients(ctx, ws, c, P.slots, params, 1, c128, st, crs);
+  if (rc) return rc;
+  const size_t amp = c128 ? 16 : 8;
+  if (dp.scratch_amps > 0) HIP_TRY(ws.scratch.ensure((size_t)dp.scratch_amps * amp), "cone scratch");
+  const size_t nc = dp.cones.size();
+  HIP_TRY(ws.meas.ensure(nc * sizeof(double)), "cone partials");
+  ConeLaunch L;
+  L.d_cones = dp.d_cones;
+  L.d_order = dp.d_order;
+  L.n_cones = (int)nc;
+  L.d_passes = dp.d_passes;
+  L.d_stages = dp.d_stages;
+  L.d_ops = dp.d_ops;
+  L.scratch = ws.scratch.p;
+  L.coef = ws.coef.p;
+  L.out = (double*)ws.meas.p;
+  L.m_max = dp.cone_m_max;
+  L.r = 4;
+  L.c128 = c128;
+  double cone_bytes = 0;  // only cones above the tile size touch HBM scratch
+  for (const PassDesc& pd : P.passes)
+    if (pd.n > pd.m) cone_bytes += pass_bytes(pd, 1, c128);
+  const int ti = timing_begin(ctx, st, cone_bytes, 0, 1);
+  HIP_TRY(launch_cones(L, st), "cone launch");
+  timing_end(ctx, ti, st);
+  HIP_TRY(ws.out.ensure(sizeof(double)), "result buffer");
+  HIP_TRY(launch_reduce_rows((const double*)ws.meas.p, 1, (int64_t)nc, P.const_term, (double*)ws.out.p, st),
+          "cone reduce");
+  return fetch_out(ctx, ws, 1, st, out_host);
+}
+
+}  // namespace qsim

@@ -1,0 +1,174 @@
+// Internal engine: device workspaces, cached plans and the evaluation paths
+// behind the C-ABI.  Host C++ on the HIP runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.h"
+#include "planner.h"
+#include "../../include/qsim.h"
+
+namespace qsim {
+
+// A grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) bytes = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+// A pinned host staging buffer.
+struct HostBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e == hipSuccess) bytes = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+// A plan with its device copy.
+struct DevPlan {
+  Plan plan;
+  PassDesc* d_passes = nullptr;
+  StageDesc* d_stages = nullptr;
+  DevOp* d_ops = nullptr;
+  // light-cone / small-circuit batches
+  std::vector<ConeDesc> cones;
+  std::vector<int32_t> order;
+  ConeDesc* d_cones = nullptr;
+  int32_t* d_order = nullptr;
+  int64_t scratch_amps = 0;
+  int cone_m_max = 0;
+  // gradient scatter (CSR parameter -> gradient slots)
+  int32_t* d_poff = nullptr;
+  int32_t* d_pslots = nullptr;
+  ~DevPlan();
+  hipError_t upload(bool mock);
+};
+
+struct Workspace {
+  DevBuf coef, meas, grad, slot_total, out, scratch, lambda;
+  HostBuf h_coef, h_out;
+  void release() {
+    coef.release();
+    meas.release();
+    grad.release();
+    slot_total.release();
+    out.release();
+    scratch.release();
+    lambda.release();
+    h_coef.release();
+    h_out.release();
+  }
+};
+
+class Server;  // serving loop (serve.cpp)
+
+}  // namespace qsim
+
+namespace qsim {
+struct TimingRec {
+  hipEvent_t a = nullptr, b = nullptr;
+  double bytes = 0, ms = 0;
+  int flags = 0, kind = 0;
+};
+}  // namespace qsim
+
+struct qsim_ctx {
+  int device = 0;
+  bool timing = false;
+  std::vector<qsim::TimingRec> tpending, tdone;
+  bool mock = false;     // no device: plans only, serving simulates execution (host tests)
+  hipStream_t stream = nullptr;
+  qsim_options opt{};
+  std::mutex api_mu;     // synchronous calls
+  std::mutex plan_mu;    // plan cache
+  std::unordered_map<uint64_t, std::shared_ptr<qsim::DevPlan>> plans;
+  qsim::Workspace ws;
+  qsim::DevBuf psi;      // state workspace of qsim_expect_circuit
+  std::mutex err_mu;
+  std::string err;
+  std::unique_ptr<qsim::Server> server;
+};
+
+struct qsim_state {
+  qsim_ctx* ctx = nullptr;
+  int n = 0, batch = 0, dtype = 0;
+  void* buf = nullptr;
+  bool owned = true;
+  bool fresh = true;      // content is |0...0> but not yet written
+  hipStream_t stream = nullptr;
+  qsim::CircuitDesc queue;          // gates not yet applied
+  std::vector<double> qparams;      // [batch][queue.n_params]
+};
+
+namespace qsim {
+
+void set_error(qsim_ctx* ctx, const std::string& msg);
+int hip_fail(qsim_ctx* ctx, hipError_t e, const char* where);
+
+// Conversions from the ABI structs.
+int to_circuit(qsim_ctx* ctx, const qsim_circuit* c, CircuitDesc& out);
+int to_terms(qsim_ctx* ctx, const qsim_hamiltonian* H, int n, std::vector<Term>& out);
+
+// Plan construction (cached).
+std::shared_ptr<DevPlan> get_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
+                                        int c128, bool init, bool store_final, bool measure, int& rc);
+std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
+                                        int c128, std::shared_ptr<DevPlan>& happly, int& rc);
+std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
+                                       int c128, int& rc);
+
+// Run a dense plan on states A (and B) with 'rows' rows; coefficients from params.
+int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params, int rows,
+              int c128, void* A, void* B, hipStream_t st, double* out_host);
+int run_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& hp, const DevPlan& ap, const CircuitDesc& c,
+             const double* params, int rows, int c128, void* A, void* B, hipStream_t st, double* grad_host);
+int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params, int c128,
+              hipStream_t st, double* out_host);
+
+// Launch bracketing for qsim_timing_*: returns the record index or -1.
+int timing_begin(qsim_ctx* ctx, hipStream_t st, double bytes, int flags, int kind);
+void timing_end(qsim_ctx* ctx, int idx, hipStream_t st);
+void timing_collect(qsim_ctx* ctx);  // after a stream sync
+
+// Tile options per state precision and kernel kind.
+PlanOptions fwd_options(int c128);
+PlanOptions dual_options(int c128);
+
+}  // namespace qsim

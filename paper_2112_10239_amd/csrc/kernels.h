@@ -1,0 +1,66 @@
+// Launch wrappers for the gfx950 kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "qsim_types.h"
+
+namespace qsim {
+
+// Arguments of one dense pass over a batch of states.
+struct PassLaunch {
+  const PassDesc* d_pass;   // device copy of the pass descriptor
+  const PassDesc* h_pass;   // host copy (for n, m, r, flags)
+  const StageDesc* d_stages;
+  const DevOp* d_ops;
+  void* A;                  // psi, [rows][2^n] complex
+  void* B;                  // lambda (dual passes) or nullptr
+  int64_t row_stride;       // amplitudes per row
+  const void* coef;         // [rows][coef_row_stride] scalars
+  int64_t coef_row_stride;
+  double* meas;             // [rows][n_meas][tiles]
+  int n_meas;
+  double* grad;             // [rows][n_gslots][tiles]
+  int n_gslots;
+  int rows;
+  int c128;                 // 0: complex64, 1: complex128
+  int dual;                 // 0: psi only, 1: psi and lambda
+};
+
+hipError_t launch_pass(const PassLaunch& L, hipStream_t stream);
+
+// One workgroup per cone (or per small circuit); cones[order[b]] for block b.
+struct ConeLaunch {
+  const ConeDesc* d_cones;
+  const int32_t* d_order;
+  int n_cones;
+  const PassDesc* d_passes;
+  const StageDesc* d_stages;
+  const DevOp* d_ops;
+  void* scratch;            // cone states with more than m qubits
+  const void* coef;         // slots of all cones
+  double* out;              // [n_out] measurement per cone
+  int m_max;                // largest tile of any cone pass
+  int r;
+  int c128;
+};
+
+hipError_t launch_cones(const ConeLaunch& L, hipStream_t stream);
+
+// Many requests' passes in one launch; all items share precision, r and dual.
+hipError_t launch_pass_multi(const PassItem* d_items, int n_items, int64_t total_tiles, int m_max, int r, int c128,
+                             int dual, hipStream_t stream);
+
+// out[row] = add + sum_k part[row * per_row + k], in a fixed order.
+hipError_t launch_reduce_rows(const double* part, int rows, int64_t per_row, double add, double* out,
+                              hipStream_t stream);
+// grad[row * n_params + p] = sum over slots s of p (CSR param_slots) of slot_total[row * n_slots + s].
+hipError_t launch_grad_scatter(const double* slot_total, int rows, int n_slots, const int32_t* p_off,
+                               const int32_t* p_slots, int n_params, double* grad, hipStream_t stream);
+
+// Dynamic LDS bytes for a pass kernel with tile size 2^m.
+size_t pass_lds_bytes(int m, int c128, int dual);
+int max_lds_bytes();
+
+}  // namespace qsim

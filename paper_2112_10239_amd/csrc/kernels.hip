@@ -1,0 +1,678 @@
+// gfx950 kernels: tiled gate passes over a dense state, batched light cones,
+// and deterministic reductions.
+//
+// Gate application is bandwidth-bound for 1- and 2-qubit gates (a few flops
+// per 16 bytes moved), so a pass is organised around moving every amplitude
+// through HBM exactly once: a workgroup owns a tile of 2^m amplitudes (the
+// amplitudes that agree on the n-m non-local index bits), holds it in
+// registers (2^r per thread) and in LDS (one exchange per change of register
+// bits), applies every op the planner put in the pass, and writes the tile
+// back.  The first and the storing stage keep the six lowest index bits in
+// the lanes, so each wave moves 512 contiguous bytes per access.  Diagonal
+// gates, CNOT controls and measurement signs read any index bit: register
+// bits are compile-time per register, thread bits come from the lane's local
+// index, tile bits from the tile's base index.
+//
+// Expectation values (paper, Sec. 1 and Sec. 3) are reduced in the same
+// passes: per-thread sums in the state's precision over the thread's
+// registers, fp64 across threads, one fp64 partial per tile, then a
+// fixed-order cross-tile reduction, so results do not depend on scheduling.
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace qsim {
+namespace {
+
+template <class T>
+struct __attribute__((aligned(2 * sizeof(T)))) cpx {
+  T x, y;
+};
+
+template <int N>
+using IC = std::integral_constant<int, N>;
+
+// XOR swizzle of an LDS slot index: lanes that differ only in bits 5..9 of
+// the local index land in different banks.
+__device__ __forceinline__ uint32_t swz(uint32_t l) { return l ^ ((l >> 5) & 31u); }
+
+template <int R, int J = 0, class F>
+__device__ __forceinline__ void for_bit(int j, F&& f) {
+  if constexpr (J < R) {
+    if (j == J) f(IC<J>{});
+    else for_bit<R, J + 1>(j, f);
+  }
+}
+
+template <int NR, int M = 1, class F>
+__device__ __forceinline__ void for_mask(uint32_t mask, F&& f) {
+  if constexpr (M < NR) {
+    if (mask == (uint32_t)M) f(IC<M>{});
+    else for_mask<NR, M + 1>(mask, f);
+  }
+}
+
+struct BitSel {
+  uint32_t kind, idx, val;
+};
+
+__device__ __forceinline__ BitSel mkbit(uint32_t kind, uint32_t idx, uint32_t tl, uint64_t base) {
+  BitSel b{kind, idx, 0u};
+  if (kind == BK_THREAD) b.val = (tl >> idx) & 1u;
+  else if (kind == BK_TILE) b.val = (uint32_t)(base >> idx) & 1u;
+  return b;
+}
+
+__device__ __forceinline__ uint32_t bitv(const BitSel& b, int i) {
+  return b.kind == BK_REG ? (((uint32_t)i >> b.idx) & 1u) : b.val;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T sgn(int odd) {
+  return odd ? T(-1) : T(1);
+}
+
+// ---------------------------------------------------------------------------
+// register-level ops
+// ---------------------------------------------------------------------------
+
+template <class T, int R, int J>
+__device__ __forceinline__ void ap_u(cpx<T>* a, const T* __restrict__ u, const BitSel& c) {
+  const T u00r = u[0], u00i = u[1], u01r = u[2], u01i = u[3];
+  const T u10r = u[4], u10i = u[5], u11r = u[6], u11i = u[7];
+  const bool ctl = c.kind != BK_NONE;
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    if (i & (1 << J)) continue;
+    const int i1 = i | (1 << J);
+    const cpx<T> x0 = a[i], x1 = a[i1];
+    cpx<T> y0, y1;
+    y0.x = u00r * x0.x - u00i * x0.y + u01r * x1.x - u01i * x1.y;
+    y0.y = u00r * x0.y + u00i * x0.x + u01r * x1.y + u01i * x1.x;
+    y1.x = u10r * x0.x - u10i * x0.y + u11r * x1.x - u11i * x1.y;
+    y1.y = u10r * x0.y + u10i * x0.x + u11r * x1.y + u11i * x1.x;
+    if (ctl) {
+      const bool on = bitv(c, i) != 0u;
+      a[i] = on ? y0 : x0;
+      a[i1] = on ? y1 : x1;
+    } else {
+      a[i] = y0;
+      a[i1] = y1;
+    }
+  }
+}
+
+template <class T, int R, int J>
+__device__ __forceinline__ void ap_ry(cpx<T>* a, const T* __restrict__ u, const BitSel& c) {
+  const T cs = u[0], sn = u[1];
+  const bool ctl = c.kind != BK_NONE;
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    if (i & (1 << J)) continue;
+    const int i1 = i | (1 << J);
+    const cpx<T> x0 = a[i], x1 = a[i1];
+    cpx<T> y0, y1;
+    y0.x = cs * x0.x - sn * x1.x;
+    y0.y = cs * x0.y - sn * x1.y;
+    y1.x = sn * x0.x + cs * x1.x;
+    y1.y = sn * x0.y + cs * x1.y;
+    if (ctl) {
+      const bool on = bitv(c, i) != 0u;
+      a[i] = on ? y0 : x0;
+      a[i1] = on ? y1 : x1;
+    } else {
+      a[i] = y0;
+      a[i1] = y1;
+    }
+  }
+}
+
+template <class T, int R, int J>
+__device__ __forceinline__ void ap_x(cpx<T>* a, const BitSel& c) {
+  const bool ctl = c.kind != BK_NONE;
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    if (i & (1 << J)) continue;
+    const int i1 = i | (1 << J);
+    const cpx<T> x0 = a[i], x1 = a[i1];
+    const bool on = !ctl || bitv(c, i) != 0u;
+    a[i] = on ? x1 : x0;
+    a[i1] = on ? x0 : x1;
+  }
+}
+
+template <class T, int R>
+__device__ __forceinline__ void ap_phase(cpx<T>* a, const T* __restrict__ d, const BitSel& b) {
+  const T d0r = d[0], d0i = d[1], d1r = d[2], d1i = d[3];
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const bool one = bitv(b, i) != 0u;
+    const T dr = one ? d1r : d0r, di = one ? d1i : d0i;
+    const cpx<T> x = a[i];
+    a[i].x = dr * x.x - di * x.y;
+    a[i].y = dr * x.y + di * x.x;
+  }
+}
+
+template <class T, int R>
+__device__ __forceinline__ void ap_cz(cpx<T>* a, const BitSel& b1, const BitSel& b2) {
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const bool neg = (bitv(b1, i) & bitv(b2, i)) != 0u;
+    a[i].x = neg ? -a[i].x : a[i].x;
+    a[i].y = neg ? -a[i].y : a[i].y;
+  }
+}
+
+// sum_i (-1)^{z(i)} |a_i|^2 ; z(i) = parity(i & rz) xor par
+template <class T, int R>
+__device__ __forceinline__ double meas_z(const cpx<T>* a, uint32_t rz, uint32_t par) {
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const T p = a[i].x * a[i].x + a[i].y * a[i].y;
+    s += sgn<T>(__popc((uint32_t)i & rz) & 1) * p;
+  }
+  return par ? -(double)s : (double)s;
+}
+
+// Re( i^ph * sum_y (-1)^{z(y)} conj(a_{y^F}) a_y )
+template <class T, int R, int F>
+__device__ __forceinline__ double meas_f(const cpx<T>* a, uint32_t rz, uint32_t par, uint32_t ph) {
+  T sr = 0, si = 0;
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const int k = i ^ F;
+    const T g = sgn<T>(__popc((uint32_t)i & rz) & 1);
+    sr += g * (a[k].x * a[i].x + a[k].y * a[i].y);
+    si += g * (a[k].x * a[i].y - a[k].y * a[i].x);
+  }
+  double vr = sr, vi = si;
+  if (par) {
+    vr = -vr;
+    vi = -vi;
+  }
+  return ph == 0 ? vr : ph == 1 ? -vi : ph == 2 ? -vr : vi;
+}
+
+// b_i += c (-1)^{z(i)} a_i
+template <class T, int R>
+__device__ __forceinline__ void h_z(const cpx<T>* a, cpx<T>* b, T c, uint32_t rz, uint32_t par) {
+  const T cc = par ? -c : c;
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const T g = cc * sgn<T>(__popc((uint32_t)i & rz) & 1);
+    b[i].x += g * a[i].x;
+    b[i].y += g * a[i].y;
+  }
+}
+
+// b_i += c i^ph (-1)^{z(i^F)} a_{i^F}
+template <class T, int R, int F>
+__device__ __forceinline__ void h_f(const cpx<T>* a, cpx<T>* b, T c, uint32_t rz, uint32_t par, uint32_t ph) {
+  const T cc = par ? -c : c;
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const int k = i ^ F;
+    const T g = cc * sgn<T>(__popc((uint32_t)k & rz) & 1);
+    const T xr = a[k].x, xi = a[k].y;
+    const T pr = ph == 0 ? xr : ph == 1 ? -xi : ph == 2 ? -xr : xi;
+    const T pi = ph == 0 ? xi : ph == 1 ? xr : ph == 2 ? -xi : -xr;
+    b[i].x += g * pr;
+    b[i].y += g * pi;
+  }
+}
+
+// Im sum_i conj(b_i) (P a)_i for P = X, Y on register bit J, or Z on a bit.
+template <class T, int R, int J>
+__device__ __forceinline__ T grad_x(const cpx<T>* a, const cpx<T>* b) {
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const cpx<T> p = a[i ^ (1 << J)];
+    s += b[i].x * p.y - b[i].y * p.x;
+  }
+  return s;
+}
+
+template <class T, int R, int J>
+__device__ __forceinline__ T grad_y(const cpx<T>* a, const cpx<T>* b) {
+  // (Y a)_i = -i (-1)^{bit_J(i)} a_{i^J};  Im(conj(b) * (-i) * a') = -Re(conj(b) a')
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const cpx<T> p = a[i ^ (1 << J)];
+    const T re = b[i].x * p.x + b[i].y * p.y;
+    s += ((i >> J) & 1) ? re : -re;
+  }
+  return s;
+}
+
+template <class T, int R>
+__device__ __forceinline__ T grad_z(const cpx<T>* a, const cpx<T>* b, const BitSel& bit) {
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const T im = b[i].x * a[i].y - b[i].y * a[i].x;
+    s += bitv(bit, i) ? -im : im;
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// one tile of one pass
+// ---------------------------------------------------------------------------
+
+template <class T, int R, bool DUAL>
+__device__ __forceinline__ double run_tile(const PassDesc* __restrict__ P, const StageDesc* __restrict__ SD,
+                           const DevOp* __restrict__ OPS, cpx<T>* __restrict__ A, cpx<T>* __restrict__ B,
+                           const T* __restrict__ coef, uint64_t tile, cpx<T>* lds, double* red, double* gacc,
+                           double* __restrict__ grad_out, int64_t grad_stride) {
+  constexpr int NR = 1 << R;
+  const int n = P->n, m = P->m, flags = P->flags;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const bool active = tid < (1 << (m - R));
+  const int lane = tid & 63, wave = tid >> 6, nwaves = (nthr + 63) >> 6;
+  const uint32_t tsize = 1u << m;
+  uint64_t base = 0;
+  for (int k = 0; k < n - m; ++k)
+    if ((tile >> k) & 1) base |= 1ull << P->npos[k];
+  const int gcount = DUAL ? P->grad_count : 0;
+  const int gbegin = DUAL ? P->grad_begin : 0;
+  if (DUAL && (flags & PF_GRAD)) {
+    for (int k = tid; k < nwaves * gcount; k += nthr) gacc[k] = 0.0;
+    __syncthreads();
+  }
+  cpx<T> a[NR];
+  cpx<T> b[DUAL ? NR : 1];
+  double acc = 0.0;
+  const int s0 = P->stage_begin, s1 = P->stage_end, sst = P->store_stage;
+  for (int s = s0; s < s1; ++s) {
+    const StageDesc* S = SD + s;
+    uint32_t tl = 0;
+    for (int k = 0; k < m - R; ++k) tl |= ((uint32_t)(tid >> k) & 1u) << S->tb[k];
+    uint32_t rl[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) rl[j] = 1u << S->rb[j];
+    auto roff = [&](int i) __attribute__((always_inline)) {
+      uint32_t o = 0;
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if ((i >> j) & 1) o |= rl[j];
+      return o;
+    };
+    auto gaddr = [&](uint64_t* gr) __attribute__((always_inline)) {  // per-thread global part; per-register parts in gr
+      uint64_t gt = base;
+      for (int k = 0; k < m - R; ++k)
+        if ((tid >> k) & 1) gt |= 1ull << P->lpos[S->tb[k]];
+#pragma unroll
+      for (int j = 0; j < R; ++j) gr[j] = 1ull << P->lpos[S->rb[j]];
+      return gt;
+    };
+    if (s == s0) {
+      const bool ld_a = (flags & PF_LOAD_A) != 0, ld_b = DUAL && (flags & PF_LOAD_B) != 0;
+      uint64_t gr[R];
+      const uint64_t gt = gaddr(gr);
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        uint64_t g = gt;
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+          if ((i >> j) & 1) g |= gr[j];
+        cpx<T> z;
+        z.x = 0;
+        z.y = 0;
+        if (ld_a) {
+          a[i] = active ? A[g] : z;
+        } else {
+          a[i] = z;
+          if ((flags & PF_INIT) && active && base == 0 && (tl | roff(i)) == 0u) a[i].x = T(1);
+        }
+        if constexpr (DUAL) b[i] = (ld_b && active) ? B[g] : z;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        cpx<T> z;
+        z.x = 0;
+        z.y = 0;
+        const uint32_t l = swz(tl | roff(i));
+        a[i] = active ? lds[l] : z;
+        if constexpr (DUAL) b[i] = active ? lds[tsize + l] : z;
+      }
+    }
+
+    for (int o = S->op_begin; o < S->op_end; ++o) {
+      const DevOp op = OPS[o];
+      const uint32_t type = op.type;
+      if (type == OP_U || type == OP_RY || type == OP_X) {
+        const T* u = coef + (int64_t)op.slot * 8;
+        const BitSel c = mkbit(op.ck, op.cb, tl, base);
+        for_bit<R>(op.j, [&](auto JC) __attribute__((always_inline)) {
+          constexpr int J = decltype(JC)::value;
+          if (type == OP_U) {
+            ap_u<T, R, J>(a, u, c);
+            if constexpr (DUAL) ap_u<T, R, J>(b, u, c);
+          } else if (type == OP_RY) {
+            ap_ry<T, R, J>(a, u, c);
+            if constexpr (DUAL) ap_ry<T, R, J>(b, u, c);
+          } else {
+            ap_x<T, R, J>(a, c);
+            if constexpr (DUAL) ap_x<T, R, J>(b, c);
+          }
+        });
+      } else if (type == OP_PHASE) {
+        const T* d = coef + (int64_t)op.slot * 8;
+        const BitSel c = mkbit(op.ck, op.cb, tl, base);
+        ap_phase<T, R>(a, d, c);
+        if constexpr (DUAL) ap_phase<T, R>(b, d, c);
+      } else if (type == OP_CZ) {
+        const BitSel c1 = mkbit(op.ck, op.cb, tl, base);
+        const BitSel c2 = mkbit(op.ck2, op.cb2, tl, base);
+        ap_cz<T, R>(a, c1, c2);
+        if constexpr (DUAL) ap_cz<T, R>(b, c1, c2);
+      } else if (type == OP_MEAS_Z) {
+        const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
+        acc += op.c * meas_z<T, R>(a, op.rz, par);
+      } else if (type == OP_MEAS_F) {
+        const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
+        for_mask<NR>(op.fr, [&](auto FC) __attribute__((always_inline)) {
+          constexpr int F = decltype(FC)::value;
+          acc += op.c * meas_f<T, R, F>(a, op.rz, par, op.ph);
+        });
+      } else if constexpr (DUAL) {
+        if (type == OP_H_Z) {
+          const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
+          h_z<T, R>(a, b, (T)op.c, op.rz, par);
+        } else if (type == OP_H_F) {
+          const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
+          for_mask<NR>(op.fr, [&](auto FC) __attribute__((always_inline)) {
+            constexpr int F = decltype(FC)::value;
+            h_f<T, R, F>(a, b, (T)op.c, op.rz, par, op.ph);
+          });
+        } else if (type == OP_GRAD_X || type == OP_GRAD_Y || type == OP_GRAD_Z) {
+          T v = 0;
+          if (type == OP_GRAD_Z) {
+            v = grad_z<T, R>(a, b, mkbit(op.ck, op.cb, tl, base));
+          } else {
+            for_bit<R>(op.j, [&](auto JC) __attribute__((always_inline)) {
+              constexpr int J = decltype(JC)::value;
+              v = type == OP_GRAD_X ? grad_x<T, R, J>(a, b) : grad_y<T, R, J>(a, b);
+            });
+          }
+          const T w = wave_sum(v);
+          if (lane == 0) gacc[wave * gcount + (op.slot - gbegin)] += (double)w;
+        }
+      }
+    }
+
+    if (s == sst) {
+      const bool st_a = (flags & PF_STORE_A) != 0, st_b = DUAL && (flags & PF_STORE_B) != 0;
+      uint64_t gr[R];
+      const uint64_t gt = gaddr(gr);
+      if (active) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          uint64_t g = gt;
+#pragma unroll
+          for (int j = 0; j < R; ++j)
+            if ((i >> j) & 1) g |= gr[j];
+          if (st_a) A[g] = a[i];
+          if constexpr (DUAL) {
+            if (st_b) B[g] = b[i];
+          }
+        }
+      }
+    }
+    if (s + 1 < s1) {
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          const uint32_t l = swz(tl | roff(i));
+          lds[l] = a[i];
+          if constexpr (DUAL) lds[tsize + l] = b[i];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  double total = 0.0;
+  if (flags & PF_MEASURE) {
+    const double v = wave_sum(acc);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (tid == 0)
+      for (int w = 0; w < nwaves; ++w) total += red[w];
+    __syncthreads();
+  }
+  if (DUAL && (flags & PF_GRAD)) {
+    __syncthreads();
+    for (int k = tid; k < gcount; k += nthr) {
+      double sum = 0.0;
+      for (int w = 0; w < nwaves; ++w) sum += gacc[w * gcount + k];
+      grad_out[(int64_t)(gbegin + k) * grad_stride] = sum;
+    }
+    __syncthreads();
+  }
+  return total;
+}
+
+constexpr int kRedSlots = 16;
+
+// Threads per workgroup: 2^(m-r).  Single-state complex64 tiles go up to
+// m = 14 (1024 threads); dual-state and complex128 tiles up to m = 13.
+template <class T, bool DUAL>
+constexpr int pass_max_threads() {
+  return (DUAL || sizeof(T) == 8) ? 512 : 1024;
+}
+
+template <class T, int R, bool DUAL>
+__global__ __launch_bounds__((pass_max_threads<T, DUAL>())) void k_pass(const PassDesc* __restrict__ P, const StageDesc* __restrict__ SD,
+                                               const DevOp* __restrict__ OPS, cpx<T>* A, cpx<T>* B,
+                                               int64_t row_stride, const T* __restrict__ coef,
+                                               int64_t coef_row_stride, double* meas, int n_meas, double* grad,
+                                               int n_gslots) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int m = P->m;
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  double* red = reinterpret_cast<double*>(smem + ((size_t)(DUAL ? 2 : 1) * sizeof(cpx<T>) << m));
+  double* gacc = red + kRedSlots;
+  const uint64_t tile = blockIdx.x;
+  const int64_t tiles = gridDim.x;
+  const int64_t row = blockIdx.y;
+  double* gout = (DUAL && grad) ? grad + row * n_gslots * tiles + (int64_t)tile : nullptr;
+  const double v = run_tile<T, R, DUAL>(P, SD, OPS, A + row * row_stride, DUAL ? B + row * row_stride : nullptr,
+                                        coef + row * coef_row_stride, tile, lds, red, gacc, gout, tiles);
+  if ((P->flags & PF_MEASURE) && threadIdx.x == 0) meas[(row * n_meas + P->meas_index) * tiles + (int64_t)tile] = v;
+}
+
+template <class T, int R, bool DUAL>
+__global__ __launch_bounds__((pass_max_threads<T, DUAL>())) void k_pass_multi(const PassItem* __restrict__ items,
+                                                                             int n_items, int m_max) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  double* red = reinterpret_cast<double*>(smem + ((size_t)(DUAL ? 2 : 1) * sizeof(cpx<T>) << m_max));
+  double* gacc = red + kRedSlots;
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {  // last item with tile_begin <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].tile_begin <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const PassItem it = items[lo];
+  const PassDesc* P = it.pass;
+  const int64_t tiles = 1ll << (P->n - P->m);
+  const uint64_t tile = (uint64_t)(b - it.tile_begin);
+  double* gout = (DUAL && it.grad) ? it.grad + (int64_t)tile : nullptr;
+  const double v = run_tile<T, R, DUAL>(P, it.stages, it.ops, reinterpret_cast<cpx<T>*>(it.A),
+                                        reinterpret_cast<cpx<T>*>(it.B), reinterpret_cast<const T*>(it.coef), tile,
+                                        lds, red, gacc, gout, tiles);
+  if ((P->flags & PF_MEASURE) && threadIdx.x == 0) it.meas[(int64_t)P->meas_index * tiles + (int64_t)tile] = v;
+}
+
+template <class T, int R>
+__global__ __launch_bounds__((pass_max_threads<T, false>())) void k_cones(const ConeDesc* __restrict__ cones, const int32_t* __restrict__ order,
+                                                const PassDesc* __restrict__ P, const StageDesc* __restrict__ SD,
+                                                const DevOp* __restrict__ OPS, cpx<T>* scratch,
+                                                const T* __restrict__ coef, double* out, int m_max) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  double* red = reinterpret_cast<double*>(smem + (sizeof(cpx<T>) << m_max));
+  const ConeDesc cd = cones[order[blockIdx.x]];
+  double total = 0.0;
+  for (int p = cd.pass_begin; p < cd.pass_end; ++p) {
+    const PassDesc* pp = P + p;
+    const int64_t tiles = 1ll << (pp->n - pp->m);
+    for (int64_t t = 0; t < tiles; ++t) {
+      total += run_tile<T, R, false>(pp, SD, OPS, scratch + cd.scratch_off, nullptr,
+                                     coef + (int64_t)cd.coef_begin * 8, (uint64_t)t, lds, red, nullptr, nullptr, 0);
+      __syncthreads();
+    }
+    // the next pass reads what other waves of this workgroup stored
+    __threadfence();
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[cd.out_index] = total;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_rows(const double* __restrict__ part, int64_t per_row, double add,
+                                                     double* out) {
+  __shared__ double sh[256];
+  const int64_t row = blockIdx.x;
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < per_row; k += 256) s += part[row * per_row + k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[row] = sh[0] + add;
+}
+
+__global__ __launch_bounds__(256) void k_grad_scatter(const double* __restrict__ slot_total, int rows, int n_slots,
+                                                      const int32_t* __restrict__ p_off,
+                                                      const int32_t* __restrict__ p_slots, int n_params,
+                                                      double* grad) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)rows * n_params) return;
+  const int64_t row = idx / n_params;
+  const int p = (int)(idx % n_params);
+  double s = 0.0;
+  for (int k = p_off[p]; k < p_off[p + 1]; ++k) s += slot_total[row * n_slots + p_slots[k]];
+  grad[idx] = s;
+}
+
+template <class K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+template <class T, int R, bool DUAL>
+hipError_t launch_pass_t(const PassLaunch& L, hipStream_t stream) {
+  const int m = L.h_pass->m, n = L.h_pass->n;
+  const size_t lds = pass_lds_bytes(m, sizeof(T) == 8, DUAL);
+  auto kern = k_pass<T, R, DUAL>;
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  const int threads = std::max(64, 1 << (m - R));
+  dim3 grid((unsigned)(1ull << (n - m)), (unsigned)L.rows);
+  hipLaunchKernelGGL(kern, grid, dim3(threads), lds, stream, L.d_pass, L.d_stages, L.d_ops,
+                     reinterpret_cast<cpx<T>*>(L.A), reinterpret_cast<cpx<T>*>(L.B), L.row_stride,
+                     reinterpret_cast<const T*>(L.coef), L.coef_row_stride, L.meas, L.n_meas, L.grad, L.n_gslots);
+  return hipGetLastError();
+}
+
+template <class T, bool DUAL>
+hipError_t launch_pass_r(const PassLaunch& L, hipStream_t stream) {
+  switch (L.h_pass->r) {
+    case 1: return launch_pass_t<T, 1, DUAL>(L, stream);
+    case 2: return launch_pass_t<T, 2, DUAL>(L, stream);
+    case 3: return launch_pass_t<T, 3, DUAL>(L, stream);
+    case 4: return launch_pass_t<T, 4, DUAL>(L, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class T, int R>
+hipError_t launch_cones_t(const ConeLaunch& L, hipStream_t stream) {
+  const size_t lds = (sizeof(cpx<T>) << L.m_max) + kRedSlots * sizeof(double);
+  auto kern = k_cones<T, R>;
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  const int threads = std::max(64, 1 << (L.m_max - R));
+  hipLaunchKernelGGL(kern, dim3((unsigned)L.n_cones), dim3(threads), lds, stream, L.d_cones, L.d_order,
+                     L.d_passes, L.d_stages, L.d_ops, reinterpret_cast<cpx<T>*>(L.scratch),
+                     reinterpret_cast<const T*>(L.coef), L.out, L.m_max);
+  return hipGetLastError();
+}
+
+template <class T, int R, bool DUAL>
+hipError_t launch_multi_t(const PassItem* items, int n_items, int64_t total, int m_max, hipStream_t stream) {
+  const size_t lds = pass_lds_bytes(m_max, sizeof(T) == 8, DUAL);
+  auto kern = k_pass_multi<T, R, DUAL>;
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  const int threads = std::max(64, 1 << (m_max - R));
+  hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(threads), lds, stream, items, n_items, m_max);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_pass_multi(const PassItem* d_items, int n_items, int64_t total_tiles, int m_max, int r, int c128,
+                             int dual, hipStream_t stream) {
+  if (n_items == 0) return hipSuccess;
+  if (r != 4 || c128) return hipErrorInvalidValue;  // serving runs complex64 with 16 registers per thread
+  return dual ? launch_multi_t<float, 4, true>(d_items, n_items, total_tiles, m_max, stream)
+              : launch_multi_t<float, 4, false>(d_items, n_items, total_tiles, m_max, stream);
+}
+
+size_t pass_lds_bytes(int m, int c128, int dual) {
+  const size_t amp = c128 ? 16 : 8;
+  return (size_t)(dual ? 2 : 1) * (amp << m) + kRedSlots * sizeof(double) +
+         (dual ? (size_t)kRedSlots * kMaxGradPerPass * sizeof(double) : 0);
+}
+
+int max_lds_bytes() { return 160 * 1024; }
+
+hipError_t launch_pass(const PassLaunch& L, hipStream_t stream) {
+  if (L.c128) return L.dual ? launch_pass_r<double, true>(L, stream) : launch_pass_r<double, false>(L, stream);
+  return L.dual ? launch_pass_r<float, true>(L, stream) : launch_pass_r<float, false>(L, stream);
+}
+
+hipError_t launch_cones(const ConeLaunch& L, hipStream_t stream) {
+  if (L.n_cones == 0) return hipSuccess;
+  if (L.r != 4) return hipErrorInvalidValue;
+  return L.c128 ? launch_cones_t<double, 4>(L, stream) : launch_cones_t<float, 4>(L, stream);
+}
+
+hipError_t launch_reduce_rows(const double* part, int rows, int64_t per_row, double add, double* out,
+                              hipStream_t stream) {
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)rows), dim3(256), 0, stream, part, per_row, add, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_scatter(const double* slot_total, int rows, int n_slots, const int32_t* p_off,
+                               const int32_t* p_slots, int n_params, double* grad, hipStream_t stream) {
+  const int64_t total = (int64_t)rows * n_params;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_scatter, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, slot_total, rows,
+                     n_slots, p_off, p_slots, n_params, grad);
+  return hipGetLastError();
+}
+
+}  // namespace qsim

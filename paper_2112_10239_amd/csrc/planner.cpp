@@ -1,0 +1,858 @@
+// Host planner: turns an ordered gate list into tiled passes, register
+// stages and device ops; builds light cones and per-row coefficients.
+//
+// Pass selection.  A gate whose target is not among a pass's local qubits
+// cannot be applied in that pass (its amplitude pairs straddle tiles), while
+// diagonal gates (RZ phases, CZ) and the control of a CNOT need no locality.
+// Gates are applied in a per-qubit order: a gate is ready once every earlier
+// gate sharing a qubit with it has been applied.  Each pass picks its local
+// set greedily among a few candidates (grown from the earliest ready gates,
+// or a contiguous window of qubits) and applies every ready gate it can; one
+// forward scan with "blocked" qubits computes that closure exactly.  This
+// plays the role that contraction-path search plays in the paper's stack
+// (Sec. 1, Sec. 3), for a memory layout where every pass streams the whole
+// state through HBM once.
+//
+// Stage selection does the same at the register level inside a tile.
+#include "planner.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <numeric>
+
+namespace qsim {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+
+std::string validate_circuit(const CircuitDesc& c) {
+  if (c.n < 1 || c.n > (1 << 24)) return "n_qubits out of range";
+  if (c.n_params < 0) return "n_params < 0";
+  for (size_t g = 0; g < c.gates.size(); ++g) {
+    const Gate& x = c.gates[g];
+    const std::string at = "gate " + std::to_string(g) + ": ";
+    if (x.q0 < 0 || x.q0 >= c.n) return at + "qubit out of range";
+    switch (x.kind) {
+      case G_CZ:
+      case G_CNOT:
+        if (x.q1 < 0 || x.q1 >= c.n) return at + "second qubit out of range";
+        if (x.q1 == x.q0) return at + "duplicate qubit";
+        break;
+      case G_RX:
+      case G_RY:
+      case G_RZ:
+        if (x.param >= c.n_params) return at + "parameter index out of range";
+        break;
+      case G_U1:
+        break;
+      default:
+        return at + "unknown gate kind";
+    }
+  }
+  return "";
+}
+
+std::string validate_terms(const std::vector<Term>& terms, int n) {
+  for (size_t t = 0; t < terms.size(); ++t) {
+    const auto& ops = terms[t].ops;
+    for (size_t k = 0; k < ops.size(); ++k) {
+      const int q = ops[k].first;
+      const char p = ops[k].second;
+      if (q < 0 || q >= n) return "term " + std::to_string(t) + ": qubit out of range";
+      if (p != 'X' && p != 'Y' && p != 'Z') return "term " + std::to_string(t) + ": bad Pauli letter";
+      for (size_t k2 = 0; k2 < k; ++k2)
+        if (ops[k2].first == q) return "term " + std::to_string(t) + ": duplicate qubit";
+    }
+  }
+  return "";
+}
+
+// ---------------------------------------------------------------------------
+// pgates
+// ---------------------------------------------------------------------------
+
+static int kind_of_1q(int k) { return k == G_RY ? PG_RY : k == G_RZ ? PG_PHASE : PG_U; }
+
+void forward_pgates(const CircuitDesc& c, bool fuse, std::vector<PGate>& out, std::vector<PGate>& slots) {
+  out.clear();
+  slots.clear();
+  std::vector<int> open(c.n, -1);  // pgate holding the current run of 1-qubit gates on a qubit
+  for (int g = 0; g < (int)c.gates.size(); ++g) {
+    const Gate& x = c.gates[g];
+    if (x.kind == G_CZ || x.kind == G_CNOT) {
+      open[x.q0] = open[x.q1] = -1;
+      PGate p;
+      if (x.kind == G_CZ) {
+        p.kind = PG_CZ;
+        p.q = x.q0;
+        p.q2 = x.q1;
+      } else {
+        p.kind = PG_X;
+        p.q = x.q1;   // target
+        p.q2 = x.q0;  // control
+      }
+      p.srcs = {g};
+      out.push_back(p);
+      continue;
+    }
+    const int pk = kind_of_1q(x.kind);
+    if (fuse && open[x.q0] >= 0) {
+      PGate& p = out[open[x.q0]];
+      p.srcs.push_back(g);
+      if (p.kind != pk) p.kind = PG_U;  // RY after RY stays real, RZ after RZ stays diagonal
+      continue;
+    }
+    PGate p;
+    p.kind = pk;
+    p.q = x.q0;
+    p.srcs = {g};
+    open[x.q0] = (int)out.size();
+    out.push_back(p);
+  }
+  for (auto& p : out) {
+    if (p.kind == PG_U || p.kind == PG_RY || p.kind == PG_PHASE) {
+      p.slot = (int)slots.size();
+      slots.push_back(p);
+    }
+  }
+}
+
+void adjoint_pgates(const CircuitDesc& c, std::vector<PGate>& out, std::vector<PGate>& slots,
+                    std::vector<int>& gslot_param) {
+  out.clear();
+  slots.clear();
+  gslot_param.clear();
+  for (int g = (int)c.gates.size() - 1; g >= 0; --g) {
+    const Gate& x = c.gates[g];
+    if (x.kind == G_CZ || x.kind == G_CNOT) {  // self-inverse
+      PGate p;
+      p.kind = x.kind == G_CZ ? PG_CZ : PG_X;
+      p.q = x.kind == G_CZ ? x.q0 : x.q1;
+      p.q2 = x.kind == G_CZ ? x.q1 : x.q0;
+      p.srcs = {g};
+      out.push_back(p);
+      continue;
+    }
+    if ((x.kind == G_RX || x.kind == G_RY || x.kind == G_RZ) && x.param >= 0) {
+      PGate gp;
+      gp.kind = PG_GRAD;
+      gp.q = x.q0;
+      gp.gen = x.kind == G_RX ? 'X' : x.kind == G_RY ? 'Y' : 'Z';
+      gp.slot = x.param;  // parameter index; the plan numbers gradient slots in execution order
+      gp.srcs = {g};
+      gslot_param.push_back(x.param);
+      out.push_back(gp);
+    }
+    PGate p;
+    p.kind = kind_of_1q(x.kind);
+    p.q = x.q0;
+    p.srcs = {g};
+    p.inverse = true;
+    p.slot = (int)slots.size();
+    slots.push_back(p);
+    out.push_back(p);
+  }
+}
+
+void term_pgates(const std::vector<Term>& terms, bool happly, std::vector<PGate>& out, double& const_term,
+                 const std::vector<int>* relabel) {
+  out.clear();
+  const_term = 0;
+  for (const Term& t : terms) {
+    if (t.ops.empty()) {
+      const_term += t.c;
+      continue;
+    }
+    PGate p;
+    int ny = 0;
+    for (auto [q0, L] : t.ops) {
+      const int q = relabel ? (*relabel)[q0] : q0;
+      const uint64_t b = 1ull << q;
+      if (L == 'X' || L == 'Y') p.fmask |= b;
+      if (L == 'Y' || L == 'Z') p.zmask |= b;
+      if (L == 'Y') ++ny;
+    }
+    p.ph = ny & 3;
+    p.c = t.c;
+    p.kind = p.fmask ? (happly ? PG_H_F : PG_MEAS_F) : (happly ? PG_H_Z : PG_MEAS_Z);
+    out.push_back(p);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass and stage planning
+// ---------------------------------------------------------------------------
+
+namespace {
+
+bool is_term(const PGate& g) { return g.kind >= PG_MEAS_Z; }
+
+// Qubits that must be local (register-resident) for g to be applied.
+uint64_t need_mask(const PGate& g) {
+  switch (g.kind) {
+    case PG_U:
+    case PG_RY:
+    case PG_X:
+      return 1ull << g.q;
+    case PG_GRAD:
+      return g.gen == 'Z' ? 0 : 1ull << g.q;
+    case PG_MEAS_F:
+    case PG_H_F:
+      return g.fmask;
+    default:
+      return 0;
+  }
+}
+
+// Qubits that order g against other gates.
+int order_qubits(const PGate& g, int out[2]) {
+  if (is_term(g)) return 0;
+  int k = 0;
+  if (g.q >= 0) out[k++] = g.q;
+  if (g.q2 >= 0) out[k++] = g.q2;
+  return k;
+}
+
+int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+// One forward scan: which pending gates a pass with local mask L applies.
+double scan_pass(const std::vector<PGate>& G, const std::vector<int>& pending, uint64_t L, int n, int max_grad,
+                 std::vector<int>* applied) {
+  std::vector<char> blocked(n, 0);
+  double score = 0;
+  int ngrad = 0;
+  for (int idx : pending) {
+    const PGate& g = G[idx];
+    int qs[2];
+    const int k = order_qubits(g, qs);
+    bool b = false;
+    for (int t = 0; t < k; ++t) b |= blocked[qs[t]] != 0;
+    const uint64_t need = need_mask(g);
+    bool ok = !b && (need & ~L) == 0;
+    if (ok && g.kind == PG_GRAD && ngrad >= max_grad) ok = false;
+    if (ok) {
+      score += need ? 1.0 : 0.01;
+      if (g.kind == PG_GRAD) ++ngrad;
+      if (applied) applied->push_back(idx);
+    } else {
+      for (int t = 0; t < k; ++t) blocked[qs[t]] = 1;
+    }
+  }
+  return score;
+}
+
+// Candidate grown from the earliest ready gates.
+uint64_t grow_candidate(const std::vector<PGate>& G, const std::vector<int>& pending, uint64_t base, int n, int m) {
+  std::vector<char> blocked(n, 0);
+  uint64_t L = base;
+  for (int idx : pending) {
+    const PGate& g = G[idx];
+    int qs[2];
+    const int k = order_qubits(g, qs);
+    bool b = false;
+    for (int t = 0; t < k; ++t) b |= blocked[qs[t]] != 0;
+    const uint64_t need = need_mask(g);
+    if (!b && (need & ~L) != 0 && popcount64(L | need) <= m) L |= need;
+    if (b || (need & ~L) != 0)
+      for (int t = 0; t < k; ++t) blocked[qs[t]] = 1;
+  }
+  for (int q = 0; q < n && popcount64(L) < m; ++q) L |= 1ull << q;
+  return L;
+}
+
+struct StageBuild {
+  std::vector<int> rb;  // local indices
+  std::vector<const PGate*> items;
+};
+
+bool rb_has(const std::vector<int>& rb, int k) { return std::find(rb.begin(), rb.end(), k) != rb.end(); }
+
+void fill_rb(std::vector<int>& rb, int r, int m, int lo) {
+  for (int k = m - 1; k >= lo && (int)rb.size() < r; --k)
+    if (!rb_has(rb, k)) rb.push_back(k);
+  for (int k = m - 1; k >= 0 && (int)rb.size() < r; --k)
+    if (!rb_has(rb, k)) rb.push_back(k);
+}
+
+// Local indices of a physical mask (all bits must be local).
+std::vector<int> local_bits(uint64_t mask, const std::vector<int>& lidx) {
+  std::vector<int> out;
+  while (mask) {
+    const int q = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    out.push_back(lidx[q]);
+  }
+  return out;
+}
+
+// Try to place item g into a stage with register bits rb (extending rb within r and 'lo').
+bool try_place(const PGate& g, std::vector<int>& rb, int r, int lo, const std::vector<int>& lidx) {
+  const std::vector<int> need = local_bits(need_mask(g), lidx);
+  std::vector<int> add;
+  for (int k : need)
+    if (!rb_has(rb, k)) {
+      if (k < lo) return false;
+      add.push_back(k);
+    }
+  if ((int)(rb.size() + add.size()) > r) return false;
+  for (int k : add) rb.push_back(k);
+  return true;
+}
+
+struct BitRef {
+  uint8_t kind, idx;
+};
+
+struct PassEmitter {
+  Plan& plan;
+  int n, m, r;
+  std::vector<int> L;     // physical qubits, ascending
+  std::vector<int> lidx;  // physical -> local index (-1 = non-local)
+
+  PassEmitter(Plan& p, int n_, int m_, int r_, uint64_t Lmask) : plan(p), n(n_), m(m_), r(r_), lidx(n_, -1) {
+    for (int q = 0; q < n; ++q)
+      if ((Lmask >> q) & 1) {
+        lidx[q] = (int)L.size();
+        L.push_back(q);
+      }
+  }
+
+  BitRef bitref(int q, const std::vector<int>& rb) const {
+    const int k = lidx[q];
+    if (k < 0) return {BK_TILE, (uint8_t)q};
+    for (int j = 0; j < (int)rb.size(); ++j)
+      if (rb[j] == k) return {BK_REG, (uint8_t)j};
+    return {BK_THREAD, (uint8_t)k};
+  }
+
+  void zmasks(uint64_t z, const std::vector<int>& rb, DevOp& op) const {
+    op.rz = op.tz = 0;
+    op.pz = 0;
+    while (z) {
+      const int q = __builtin_ctzll(z);
+      z &= z - 1;
+      const BitRef b = bitref(q, rb);
+      if (b.kind == BK_REG) op.rz |= 1u << b.idx;
+      else if (b.kind == BK_THREAD) op.tz |= 1u << b.idx;
+      else op.pz |= 1ull << b.idx;
+    }
+  }
+
+  DevOp to_devop(const PGate& g, const std::vector<int>& rb) const {
+    DevOp op;
+    std::memset(&op, 0, sizeof(op));
+    op.slot = g.slot;
+    auto regpos = [&](int q) { return bitref(q, rb).idx; };
+    switch (g.kind) {
+      case PG_U:
+      case PG_RY:
+      case PG_X: {
+        op.type = g.kind == PG_U ? OP_U : g.kind == PG_RY ? OP_RY : OP_X;
+        op.j = regpos(g.q);
+        if (g.q2 >= 0) {
+          const BitRef b = bitref(g.q2, rb);
+          op.ck = b.kind;
+          op.cb = b.idx;
+        }
+        break;
+      }
+      case PG_PHASE: {
+        op.type = OP_PHASE;
+        const BitRef b = bitref(g.q, rb);
+        op.ck = b.kind;
+        op.cb = b.idx;
+        break;
+      }
+      case PG_CZ: {
+        op.type = OP_CZ;
+        const BitRef a = bitref(g.q, rb), b = bitref(g.q2, rb);
+        op.ck = a.kind;
+        op.cb = a.idx;
+        op.ck2 = b.kind;
+        op.cb2 = b.idx;
+        break;
+      }
+      case PG_GRAD: {
+        if (g.gen == 'Z') {
+          op.type = OP_GRAD_Z;
+          const BitRef b = bitref(g.q, rb);
+          op.ck = b.kind;
+          op.cb = b.idx;
+        } else {
+          op.type = g.gen == 'X' ? OP_GRAD_X : OP_GRAD_Y;
+          op.j = regpos(g.q);
+        }
+        break;
+      }
+      case PG_MEAS_Z:
+      case PG_H_Z:
+      case PG_MEAS_F:
+      case PG_H_F: {
+        op.type = g.kind == PG_MEAS_Z ? OP_MEAS_Z : g.kind == PG_H_Z ? OP_H_Z : g.kind == PG_MEAS_F ? OP_MEAS_F : OP_H_F;
+        zmasks(g.zmask, rb, op);
+        uint64_t f = g.fmask;
+        while (f) {
+          const int q = __builtin_ctzll(f);
+          f &= f - 1;
+          op.fr |= 1u << bitref(q, rb).idx;
+        }
+        op.ph = (uint8_t)g.ph;
+        op.c = g.c;
+        break;
+      }
+    }
+    return op;
+  }
+
+  // Emits one pass.  'mod' items modify the state(s) and keep their order;
+  // 'ro' items are read-only terms measured after all of 'mod'.
+  void emit(const std::vector<const PGate*>& mod, const std::vector<const PGate*>& ro, int flags,
+            int c_low, int src_pass_index) {
+    const bool loads = flags & (PF_LOAD_A | PF_LOAD_B);
+    const bool stores = flags & (PF_STORE_A | PF_STORE_B);
+    const int lo_load = loads ? c_low : 0;
+    const int lo_store = stores ? c_low : 0;
+
+    std::vector<StageBuild> sb;
+    std::vector<const PGate*> pending = mod;
+    bool first = true;
+    while (!pending.empty()) {
+      StageBuild s;
+      std::vector<char> blocked(n, 0);
+      std::vector<const PGate*> rest;
+      for (const PGate* g : pending) {
+        int qs[2];
+        const int k = order_qubits(*g, qs);
+        bool b = false;
+        for (int t = 0; t < k; ++t) b |= blocked[qs[t]] != 0;
+        if (!b && try_place(*g, s.rb, r, first ? lo_load : 0, lidx)) {
+          s.items.push_back(g);
+        } else {
+          for (int t = 0; t < k; ++t) blocked[qs[t]] = 1;
+          rest.push_back(g);
+        }
+      }
+      fill_rb(s.rb, r, m, first ? lo_load : 0);
+      sb.push_back(std::move(s));
+      pending.swap(rest);
+      first = false;
+    }
+    if (sb.empty()) {
+      StageBuild s;
+      fill_rb(s.rb, r, m, lo_load);
+      sb.push_back(std::move(s));
+    }
+    int store_rel = -1;
+    if (stores) {
+      bool ok = true;
+      for (int k : sb.back().rb) ok &= k >= lo_store;
+      if (!ok) {
+        StageBuild s;
+        fill_rb(s.rb, r, m, lo_store);
+        sb.push_back(std::move(s));
+      }
+      store_rel = (int)sb.size() - 1;
+    }
+    // read-only terms: the last stage first, then new stages
+    std::vector<const PGate*> left;
+    for (const PGate* g : ro) {
+      std::vector<int> rb = sb.back().rb;
+      if (try_place(*g, rb, r, 0, lidx) && rb.size() == sb.back().rb.size()) sb.back().items.push_back(g);
+      else left.push_back(g);
+    }
+    while (!left.empty()) {
+      StageBuild s;
+      std::vector<const PGate*> rest;
+      for (const PGate* g : left) {
+        if (try_place(*g, s.rb, r, 0, lidx)) s.items.push_back(g);
+        else rest.push_back(g);
+      }
+      fill_rb(s.rb, r, m, 0);
+      sb.push_back(std::move(s));
+      left.swap(rest);
+    }
+
+    PassDesc pd;
+    std::memset(&pd, 0, sizeof(pd));
+    pd.n = n;
+    pd.m = m;
+    pd.r = r;
+    pd.flags = flags;
+    pd.stage_begin = (int)plan.stages.size();
+    pd.meas_index = -1;
+    pd.store_stage = store_rel >= 0 ? pd.stage_begin + store_rel : -1;
+    for (int k = 0; k < m; ++k) pd.lpos[k] = (uint8_t)L[k];
+    {
+      int j = 0;
+      for (int q = 0; q < n; ++q)
+        if (lidx[q] < 0) pd.npos[j++] = (uint8_t)q;
+    }
+    bool any_meas = false;
+    int gmin = 1 << 30, gcount = 0;
+    const int pass_no = (int)plan.passes.size();
+    for (int si = 0; si < (int)sb.size(); ++si) {
+      StageDesc st;
+      std::memset(&st, 0, sizeof(st));
+      const auto& rb = sb[si].rb;
+      for (int j = 0; j < r; ++j) st.rb[j] = (uint8_t)rb[j];
+      {
+        int t = 0;
+        for (int k = 0; k < m; ++k)
+          if (!rb_has(rb, k)) st.tb[t++] = (uint8_t)k;
+      }
+      st.op_begin = (int)plan.ops.size();
+      for (const PGate* g : sb[si].items) {
+        DevOp op = to_devop(*g, rb);
+        if (g->kind == PG_GRAD) {
+          op.slot = plan.n_gslots++;
+          gmin = std::min(gmin, op.slot);
+          ++gcount;
+          plan.gslot_param.push_back(g->slot);  // a gradient probe's slot field holds its parameter index
+        }
+        if (g->kind == PG_MEAS_Z || g->kind == PG_MEAS_F) any_meas = true;
+        for (int src : g->srcs) {
+          plan.order.push_back(pass_no);
+          plan.order.push_back(si);
+          plan.order.push_back((int)plan.ops.size() - st.op_begin);
+          plan.order.push_back(src);
+        }
+        plan.ops.push_back(op);
+      }
+      st.op_end = (int)plan.ops.size();
+      plan.stages.push_back(st);
+    }
+    pd.stage_end = (int)plan.stages.size();
+    if (any_meas) {
+      pd.flags |= PF_MEASURE;
+      pd.meas_index = plan.n_meas++;
+    }
+    if (gcount) {
+      pd.flags |= PF_GRAD;
+      pd.grad_begin = gmin;
+      pd.grad_count = gcount;
+    }
+    (void)src_pass_index;
+    plan.passes.push_back(pd);
+  }
+};
+
+// Split gates into passes; returns the local masks and applied gate lists.
+void split_passes(int n, int m, int c_low, const std::vector<PGate>& G, int max_grad, std::vector<uint64_t>& Ls,
+                  std::vector<std::vector<int>>& applied_lists) {
+  std::vector<int> pending;
+  for (int i = 0; i < (int)G.size(); ++i)
+    if (!is_term(G[i])) pending.push_back(i);
+  const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  const uint64_t base = (1ull << c_low) - 1;
+  while (!pending.empty()) {
+    std::vector<uint64_t> cands;
+    if (n <= m) {
+      cands.push_back(all);
+    } else {
+      cands.push_back(grow_candidate(G, pending, base, n, m));
+      const int w = m - c_low;
+      for (int s = c_low; s + w <= n; ++s) cands.push_back(base | (((1ull << w) - 1) << s));
+    }
+    double best = -1;
+    uint64_t bestL = cands[0];
+    for (uint64_t L : cands) {
+      const double sc = scan_pass(G, pending, L, n, max_grad, nullptr);
+      if (sc > best + 1e-9) {
+        best = sc;
+        bestL = L;
+      }
+    }
+    std::vector<int> applied;
+    scan_pass(G, pending, bestL, n, max_grad, &applied);
+    if (applied.empty()) break;  // cannot happen: the first pending gate is always applicable
+    std::vector<int> rest;
+    size_t a = 0;
+    for (int idx : pending) {
+      if (a < applied.size() && applied[a] == idx) ++a;
+      else rest.push_back(idx);
+    }
+    Ls.push_back(bestL);
+    applied_lists.push_back(std::move(applied));
+    pending.swap(rest);
+  }
+}
+
+// Measurement-only (or H-apply) passes for flip terms not covered yet.
+void cover_terms(int n, int m, int c_low, const std::vector<const PGate*>& terms, std::vector<uint64_t>& Ls,
+                 std::vector<std::vector<const PGate*>>& groups) {
+  std::vector<const PGate*> left = terms;
+  const uint64_t base = (1ull << c_low) - 1;
+  while (!left.empty()) {
+    uint64_t L = n <= m ? (n >= 64 ? ~0ull : ((1ull << n) - 1)) : base;
+    std::vector<const PGate*> grp, rest;
+    for (const PGate* g : left) {
+      if (popcount64(L | g->fmask) <= m) {
+        L |= g->fmask;
+        grp.push_back(g);
+      } else {
+        rest.push_back(g);
+      }
+    }
+    for (int q = 0; q < n && popcount64(L) < m; ++q) L |= 1ull << q;
+    Ls.push_back(L);
+    groups.push_back(grp);
+    left.swap(rest);
+  }
+}
+
+int check_terms(const std::vector<PGate>& terms, int r, std::string& err) {
+  for (const PGate& t : terms)
+    if (popcount64(t.fmask) > r) {
+      err = "a Pauli term with more than " + std::to_string(r) + " X/Y factors is not supported";
+      return -1;
+    }
+  return 0;
+}
+
+}  // namespace
+
+int plan_forward(int n, const std::vector<PGate>& gates, const std::vector<PGate>& meas, const PlanOptions& o,
+                 Plan& plan, std::string& err) {
+  if (n > kMaxQubits) {
+    err = "dense mode supports at most 40 qubits";
+    return -1;
+  }
+  plan.n = n;
+  plan.m = std::min(n, o.m_max);
+  plan.r = std::min(o.r, plan.m);
+  const int m = plan.m, r = plan.r;
+  const int c_low = n <= m ? 0 : std::min(o.c_low, m - r);
+  if (check_terms(meas, r, err)) return -1;
+
+  std::vector<uint64_t> Ls;
+  std::vector<std::vector<int>> lists;
+  split_passes(n, m, c_low, gates, 1 << 30, Ls, lists);
+  if (Ls.empty()) {
+    Ls.push_back(n <= m ? ((1ull << n) - 1) : ((1ull << m) - 1));
+    lists.emplace_back();
+  }
+  // terms measured in the final gate pass vs. extra read-only passes
+  std::vector<const PGate*> fin, extra;
+  for (const PGate& t : meas) {
+    if ((t.fmask & ~Ls.back()) == 0) fin.push_back(&t);
+    else extra.push_back(&t);
+  }
+  std::vector<uint64_t> mLs;
+  std::vector<std::vector<const PGate*>> mgroups;
+  cover_terms(n, m, c_low, extra, mLs, mgroups);
+
+  const int np = (int)Ls.size();
+  for (int p = 0; p < np; ++p) {
+    int flags = (p == 0 && o.init) ? PF_INIT : PF_LOAD_A;
+    const bool last = p == np - 1;
+    if (!last || o.store_final || !mLs.empty()) flags |= PF_STORE_A;
+    PassEmitter em(plan, n, m, r, Ls[p]);
+    std::vector<const PGate*> mod;
+    for (int idx : lists[p]) mod.push_back(&gates[idx]);
+    em.emit(mod, last ? fin : std::vector<const PGate*>{}, flags, c_low, p);
+  }
+  for (size_t k = 0; k < mLs.size(); ++k) {
+    PassEmitter em(plan, n, m, r, mLs[k]);
+    em.emit({}, mgroups[k], PF_LOAD_A, c_low, -1);
+    ++plan.meas_passes;
+  }
+  return 0;
+}
+
+int plan_happly(int n, const std::vector<PGate>& hterms, const PlanOptions& o, Plan& plan, std::string& err) {
+  if (n > kMaxQubits) {
+    err = "dense mode supports at most 40 qubits";
+    return -1;
+  }
+  plan.n = n;
+  plan.m = std::min(n, o.m_max);
+  plan.r = std::min(o.r, plan.m);
+  const int m = plan.m, r = plan.r;
+  const int c_low = n <= m ? 0 : std::min(o.c_low, m - r);
+  if (check_terms(hterms, r, err)) return -1;
+  std::vector<const PGate*> diag, flips;
+  for (const PGate& t : hterms) (t.fmask ? flips : diag).push_back(&t);
+  std::vector<uint64_t> Ls;
+  std::vector<std::vector<const PGate*>> groups;
+  cover_terms(n, m, c_low, flips, Ls, groups);
+  if (Ls.empty()) {
+    Ls.push_back(n <= m ? ((1ull << n) - 1) : ((1ull << m) - 1));
+    groups.emplace_back();
+  }
+  for (size_t p = 0; p < Ls.size(); ++p) {
+    std::vector<const PGate*> mod = groups[p];
+    if (p == 0) mod.insert(mod.begin(), diag.begin(), diag.end());
+    const int flags = (p == 0 ? (PF_ZERO_B | PF_LOAD_A) : (PF_LOAD_A | PF_LOAD_B)) | PF_STORE_B;
+    PassEmitter em(plan, n, m, r, Ls[p]);
+    em.emit(mod, {}, flags, c_low, (int)p);
+  }
+  return 0;
+}
+
+int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, Plan& plan, std::string& err) {
+  if (n > kMaxQubits) {
+    err = "dense mode supports at most 40 qubits";
+    return -1;
+  }
+  plan.n = n;
+  plan.m = std::min(n, o.m_max);
+  plan.r = std::min(o.r, plan.m);
+  const int m = plan.m, r = plan.r;
+  const int c_low = n <= m ? 0 : std::min(o.c_low, m - r);
+  std::vector<uint64_t> Ls;
+  std::vector<std::vector<int>> lists;
+  split_passes(n, m, c_low, gates, o.max_grad, Ls, lists);
+  if (Ls.empty()) {  // no gates: one pass that changes nothing
+    Ls.push_back(n <= m ? ((1ull << n) - 1) : ((1ull << m) - 1));
+    lists.emplace_back();
+  }
+  const int np = (int)Ls.size();
+  for (int p = 0; p < np; ++p) {
+    int flags = PF_LOAD_A | PF_LOAD_B;
+    if (p != np - 1) flags |= PF_STORE_A | PF_STORE_B;
+    PassEmitter em(plan, n, m, r, Ls[p]);
+    std::vector<const PGate*> mod;
+    for (int idx : lists[p]) mod.push_back(&gates[idx]);
+    em.emit(mod, {}, flags, c_low, p);
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// light cones
+// ---------------------------------------------------------------------------
+
+void light_cone(const CircuitDesc& c, const std::vector<int>& support, std::vector<int>& set,
+                std::vector<int>& gates) {
+  std::vector<char> in(c.n, 0);
+  for (int q : support) in[q] = 1;
+  gates.clear();
+  for (int g = (int)c.gates.size() - 1; g >= 0; --g) {
+    const Gate& x = c.gates[g];
+    if (x.kind == G_CZ || x.kind == G_CNOT) {
+      if (in[x.q0] || in[x.q1]) {
+        in[x.q0] = in[x.q1] = 1;
+        gates.push_back(g);
+      }
+    } else if (in[x.q0]) {
+      gates.push_back(g);
+    }
+  }
+  std::reverse(gates.begin(), gates.end());
+  set.clear();
+  for (int q = 0; q < c.n; ++q)
+    if (in[q]) set.push_back(q);
+}
+
+// ---------------------------------------------------------------------------
+// coefficients
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct M2 {
+  cd a[2][2];
+};
+
+M2 mul(const M2& x, const M2& y) {
+  M2 z;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) z.a[i][j] = x.a[i][0] * y.a[0][j] + x.a[i][1] * y.a[1][j];
+  return z;
+}
+
+M2 gate_m2(const Gate& g, const double* th) {
+  M2 u;
+  if (g.kind == G_U1) {
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) u.a[i][j] = cd(g.mat[(i * 2 + j) * 2], g.mat[(i * 2 + j) * 2 + 1]);
+    return u;
+  }
+  const double t = g.param >= 0 ? th[g.param] : g.angle;
+  const double c = std::cos(0.5 * t), s = std::sin(0.5 * t);
+  switch (g.kind) {
+    case G_RX:  // cos(t/2) I - i sin(t/2) X
+      u.a[0][0] = c; u.a[0][1] = cd(0, -s); u.a[1][0] = cd(0, -s); u.a[1][1] = c;
+      break;
+    case G_RY:  // cos(t/2) I - i sin(t/2) Y
+      u.a[0][0] = c; u.a[0][1] = -s; u.a[1][0] = s; u.a[1][1] = c;
+      break;
+    default:    // RZ: cos(t/2) I - i sin(t/2) Z
+      u.a[0][0] = cd(c, -s); u.a[0][1] = 0; u.a[1][0] = 0; u.a[1][1] = cd(c, s);
+      break;
+  }
+  return u;
+}
+
+}  // namespace
+
+template <class T>
+void build_coefficients(const CircuitDesc& c, const std::vector<PGate>& slots, const double* params, int batch,
+                        int64_t row_stride, T* out) {
+  for (int b = 0; b < batch; ++b) {
+    const double* th = params ? params + (size_t)b * c.n_params : nullptr;
+    T* row = out + (size_t)b * row_stride;
+    for (size_t s = 0; s < slots.size(); ++s) {
+      const PGate& p = slots[s];
+      M2 M;
+      M.a[0][0] = 1; M.a[0][1] = 0; M.a[1][0] = 0; M.a[1][1] = 1;
+      for (int g : p.srcs) M = mul(gate_m2(c.gates[g], th), M);
+      if (p.inverse) {
+        M2 h;
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) h.a[i][j] = std::conj(M.a[j][i]);
+        M = h;
+      }
+      T* o = row + s * 8;
+      for (int k = 0; k < 8; ++k) o[k] = 0;
+      if (p.kind == PG_RY) {
+        o[0] = (T)M.a[0][0].real();
+        o[1] = (T)M.a[1][0].real();
+      } else if (p.kind == PG_PHASE) {
+        o[0] = (T)M.a[0][0].real(); o[1] = (T)M.a[0][0].imag();
+        o[2] = (T)M.a[1][1].real(); o[3] = (T)M.a[1][1].imag();
+      } else {
+        o[0] = (T)M.a[0][0].real(); o[1] = (T)M.a[0][0].imag();
+        o[2] = (T)M.a[0][1].real(); o[3] = (T)M.a[0][1].imag();
+        o[4] = (T)M.a[1][0].real(); o[5] = (T)M.a[1][0].imag();
+        o[6] = (T)M.a[1][1].real(); o[7] = (T)M.a[1][1].imag();
+      }
+    }
+  }
+}
+
+template void build_coefficients<float>(const CircuitDesc&, const std::vector<PGate>&, const double*, int, int64_t,
+                                        float*);
+template void build_coefficients<double>(const CircuitDesc&, const std::vector<PGate>&, const double*, int, int64_t,
+                                         double*);
+
+uint64_t structure_hash(const CircuitDesc& c, const std::vector<Term>& terms, int extra) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ull;
+  };
+  mix((uint64_t)c.n);
+  mix((uint64_t)c.n_params);
+  mix((uint64_t)extra);
+  for (const Gate& g : c.gates) {
+    mix((uint64_t)g.kind | ((uint64_t)(uint32_t)g.q0 << 8));
+    mix((uint64_t)(uint32_t)g.q1 | ((uint64_t)(uint32_t)g.param << 32));
+  }
+  mix(0xabcdefull);
+  for (const Term& t : terms) {
+    uint64_t cb;
+    std::memcpy(&cb, &t.c, 8);
+    mix(cb);
+    for (auto [q, L] : t.ops) mix(((uint64_t)(uint32_t)q << 8) | (uint8_t)L);
+    mix(0x55ull);
+  }
+  return h;
+}
+
+}  // namespace qsim

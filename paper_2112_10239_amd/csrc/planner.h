@@ -1,0 +1,108 @@
+// Host-side planning: gate lists -> passes -> stages -> device ops, light
+// cones, and per-row gate coefficients.  Integer work plus fp64 trigonometry;
+// no device calls.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qsim_types.h"
+
+namespace qsim {
+
+enum GateKind { G_RX = 0, G_RY = 1, G_RZ = 2, G_CZ = 3, G_CNOT = 4, G_U1 = 5 };
+
+// A gate of the user's circuit (validated copy).
+struct Gate {
+  int kind, q0, q1, param;
+  double angle;
+  double mat[8];  // U1 only
+};
+
+struct Term {
+  double c = 0;
+  std::vector<std::pair<int, char>> ops;  // (qubit, 'X'|'Y'|'Z'); empty = identity
+};
+
+struct CircuitDesc {
+  int n = 0, n_params = 0;
+  std::vector<Gate> gates;
+};
+
+// Planner-level operation ("pgate"): a fused gate, a gradient probe, or a
+// measurement / H-apply term.
+enum PGKind { PG_U, PG_RY, PG_X, PG_PHASE, PG_CZ, PG_GRAD, PG_MEAS_Z, PG_MEAS_F, PG_H_Z, PG_H_F };
+
+struct PGate {
+  int kind = PG_U;
+  int q = -1;    // target / diagonal qubit / first CZ qubit
+  int q2 = -1;   // control / second CZ qubit
+  int slot = -1; // coefficient slot, or gradient slot for PG_GRAD
+  int gen = 0;   // PG_GRAD generator: 'X', 'Y' or 'Z'
+  bool inverse = false;   // coefficient = adjoint of the product
+  std::vector<int> srcs;  // source gates, in application order
+  uint64_t fmask = 0, zmask = 0;  // terms: flip (X|Y) and sign (Y|Z) masks, physical
+  int ph = 0;                     // terms: i^ph
+  double c = 0;                   // terms: coefficient
+};
+
+struct Plan {
+  int n = 0, m = 0, r = 0;
+  std::vector<PassDesc> passes;
+  std::vector<StageDesc> stages;
+  std::vector<DevOp> ops;
+  std::vector<PGate> slots;       // coefficient slot specs (index = slot)
+  int n_meas = 0;                 // measurement partial columns
+  int n_gslots = 0;               // gradient slots
+  std::vector<int> gslot_param;   // gradient slot -> parameter index
+  double const_term = 0;          // identity terms, added on the host
+  std::vector<int32_t> order;     // (pass, stage, op, source gate) quadruples
+  int meas_passes = 0;
+};
+
+enum PlanMode { PM_FWD = 0, PM_ADJ = 1 };
+
+struct PlanOptions {
+  int m_max = 14;       // tile qubits
+  int r = 4;            // register bits per stage
+  int c_low = 6;        // always-local low bits for coalesced HBM access
+  bool init = true;     // first pass generates |0...0>
+  bool store_final = true;  // keep the final state in HBM
+  bool fuse = true;     // fuse runs of single-qubit gates on one qubit
+  int max_grad = kMaxGradPerPass;  // gradient probes per pass
+};
+
+// Validation; returns "" when fine.
+std::string validate_circuit(const CircuitDesc& c);
+std::string validate_terms(const std::vector<Term>& t, int n);
+
+// Preprocess the circuit into forward pgates (fused) with coefficient slots.
+void forward_pgates(const CircuitDesc& c, bool fuse, std::vector<PGate>& out, std::vector<PGate>& slots);
+// Reverse sweep for the adjoint method: for every gate from last to first a
+// gradient probe (parameterised rotations) followed by the inverse gate.
+void adjoint_pgates(const CircuitDesc& c, std::vector<PGate>& out, std::vector<PGate>& slots,
+                    std::vector<int>& gslot_param);
+// Measurement (PG_MEAS_*) or H-apply (PG_H_*) pgates for the non-identity terms.
+// 'relabel' (optional) maps circuit qubits to the plan's qubits.
+void term_pgates(const std::vector<Term>& terms, bool happly, std::vector<PGate>& out, double& const_term,
+                 const std::vector<int>* relabel = nullptr);
+
+// Forward plan with measurement of 'meas' at the end (meas may be empty).
+int plan_forward(int n, const std::vector<PGate>& gates, const std::vector<PGate>& meas, const PlanOptions& o,
+                 Plan& plan, std::string& err);
+// Dual-state plans: lambda = H psi, then the adjoint sweep with gradient probes.
+int plan_happly(int n, const std::vector<PGate>& hterms, const PlanOptions& o, Plan& plan, std::string& err);
+int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, Plan& plan, std::string& err);
+
+// Canonical light cone of one term: ascending qubits and in-cone gate indices.
+void light_cone(const CircuitDesc& c, const std::vector<int>& support, std::vector<int>& set,
+                std::vector<int>& gates);
+
+// Per-row coefficient table for the slots, T = float or double; 8 values per slot.
+template <class T>
+void build_coefficients(const CircuitDesc& c, const std::vector<PGate>& slots, const double* params, int batch,
+                        int64_t row_stride, T* out);
+
+uint64_t structure_hash(const CircuitDesc& c, const std::vector<Term>& terms, int extra);
+
+}  // namespace qsim

@@ -1,0 +1,113 @@
+// Device-visible plan descriptors shared by the host planner and the HIP kernels.
+//
+// A state of n qubits is processed in *passes*.  A pass splits the 2^n
+// amplitudes into tiles of 2^m amplitudes that share the values of the n-m
+// "non-local" index bits; every tile is read from HBM once, transformed on
+// chip and written back once.  Inside a tile, a local index l in [0, 2^m)
+// has bit k at physical position lpos[k].
+//
+// A pass is a sequence of *stages*.  In a stage every thread holds 2^r
+// amplitudes in registers that differ in the r "register bits" rb[] (local
+// indices); the thread's own local index bits are tb[] (the other m-r local
+// indices, ascending).  Ops of a stage act on register bits (non-diagonal
+// gates, flips) or on any bit (diagonal gates, measurement signs).  Between
+// stages the tile is exchanged through LDS; the first stage reads from HBM
+// (or generates |0...0>) and the last stage writes to HBM.
+#pragma once
+#include <stdint.h>
+
+namespace qsim {
+
+enum OpType : uint8_t {
+  OP_NONE = 0,
+  OP_U = 1,       // general 2x2 on register bit j (coef: u00,u01,u10,u11 complex), optional control
+  OP_RY = 2,      // real rotation [[c,-s],[s,c]] on register bit j (coef: c, s), optional control
+  OP_X = 3,       // Pauli X on register bit j, optional control (CNOT)
+  OP_PHASE = 4,   // diag(d0, d1) on bit (ck,cb) (coef: d0, d1 complex)
+  OP_CZ = 5,      // multiply by -1 when bits (ck,cb) and (ck2,cb2) are both 1
+  OP_MEAS_Z = 6,  // acc += c * sum_i (-1)^{z(i)} |a_i|^2
+  OP_MEAS_F = 7,  // acc += c * Re( i^ph * sum_i (-1)^{z(i)} conj(a_{i^f}) a_i )
+  OP_GRAD_X = 8,  // g[slot] += Im sum_i conj(b_i) a_{i^J}
+  OP_GRAD_Y = 9,  // g[slot] += Im sum_i conj(b_i) (-i)(-1)^{bit_J(i)} a_{i^J}
+  OP_GRAD_Z = 10, // g[slot] += Im sum_i conj(b_i) (-1)^{bit(i)} a_i   (bit = (ck,cb))
+  OP_H_Z = 11,    // b_i += c (-1)^{z(i)} a_i
+  OP_H_F = 12,    // b_i += c i^ph (-1)^{z(i^f)} a_{i^f}
+};
+
+// Bit reference kinds for controls, diagonal bits and z-masks.
+enum BitKind : uint8_t { BK_NONE = 0, BK_REG = 1, BK_THREAD = 2, BK_TILE = 3 };
+
+struct DevOp {
+  uint8_t type;
+  uint8_t j;          // register bit (0..r-1) for non-diagonal ops
+  uint8_t ck, cb;     // control bit / diagonal bit: kind and index (register bit, local index, or physical pos)
+  uint8_t ck2, cb2;   // second diagonal bit (CZ)
+  uint8_t ph;         // phase exponent: multiply by i^ph (measurement / H-apply)
+  uint8_t pad;
+  int32_t slot;       // coefficient slot (gates) or gradient slot (OP_GRAD_*)
+  uint32_t rz;        // z-mask over register bits
+  uint32_t tz;        // z-mask over the thread's local-index bits
+  uint32_t fr;        // flip mask over register bits (OP_MEAS_F, OP_H_F)
+  uint64_t pz;        // z-mask over physical (tile) bits
+  double c;           // term coefficient (measurement / H-apply)
+};
+static_assert(sizeof(DevOp) == 40, "DevOp layout");
+
+constexpr int kMaxLocal = 16;
+constexpr int kMaxQubits = 40;
+constexpr int kMaxGradPerPass = 128;
+
+struct StageDesc {
+  int32_t op_begin, op_end;
+  uint8_t rb[8];          // register bits as local indices
+  uint8_t tb[kMaxLocal];  // thread bits as local indices, ascending (m - r used)
+};
+static_assert(sizeof(StageDesc) == 32, "StageDesc layout");
+
+enum PassFlags : int32_t {
+  PF_INIT = 1,      // first stage generates |0...0> instead of loading a
+  PF_LOAD_A = 2,    // load a (psi) from HBM in the first stage
+  PF_STORE_A = 4,   // store a in the last stage
+  PF_LOAD_B = 8,    // load b (lambda) in the first stage (dual kernels)
+  PF_STORE_B = 16,  // store b in the last stage (dual kernels)
+  PF_ZERO_B = 32,   // b starts at zero (H-apply)
+  PF_MEASURE = 64,  // write the block's measurement partial
+  PF_GRAD = 128,    // write the block's gradient partials
+};
+
+struct PassDesc {
+  int32_t n, m, r, flags;
+  int32_t stage_begin, stage_end;
+  int32_t meas_index;     // measurement partial column (PF_MEASURE)
+  int32_t grad_begin;     // first gradient slot of this pass (PF_GRAD)
+  int32_t grad_count;     // number of gradient slots used by this pass
+  int32_t store_stage;    // absolute stage index after whose ops a (and b) are stored
+  uint8_t lpos[kMaxLocal];   // physical bit of local index k
+  uint8_t npos[kMaxQubits];  // physical bits of the non-local index, ascending (n - m used)
+};
+
+// One light cone (or one small whole circuit) run by a single workgroup.
+struct ConeDesc {
+  int32_t pass_begin, pass_end;  // into the pass array
+  int32_t coef_begin;            // first coefficient slot of this cone
+  int32_t out_index;             // partial column written by this cone's measurement
+  int64_t scratch_off;           // amplitude offset of the cone's state in scratch (s > m only)
+  int32_t n;                     // cone qubits
+  int32_t pad;
+};
+
+// One request's pass inside a multi-request launch (serving): blocks
+// [tile_begin, tile_begin + 2^(n-m)) of the launch run this pass.
+struct PassItem {
+  const PassDesc* pass;
+  const StageDesc* stages;
+  const DevOp* ops;
+  void* A;
+  void* B;
+  const void* coef;
+  double* meas;        // [n_meas][tiles] of this request
+  double* grad;        // [n_gslots][tiles] of this request
+  int64_t tile_begin;
+};
+
+}  // namespace qsim

@@ -1,0 +1,386 @@
+"""ctypes binding of libqsim (include/qsim.h): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels and host
+planner.  The functions keep the C names without the ``qsim_`` prefix.  If
+the shared library has not been built, importing this module raises, so no
+caller can silently fall back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsim.so")
+
+OK, PENDING = 0, 1
+EINVAL, ENOMEM, ETOOBIG, EAGAIN, ENOTFOUND, EDEVICE, ECANCELED, ESHUTDOWN = -1, -2, -3, -4, -5, -6, -7, -8
+C64, C128 = 0, 1
+MODE_AUTO, MODE_DENSE, MODE_LIGHTCONE = 0, 1, 2
+RX, RY, RZ, CZ, CNOT, U1 = 0, 1, 2, 3, 4, 5
+
+
+class QsimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint8), ("pad", ctypes.c_uint8 * 3), ("q0", ctypes.c_int32),
+                ("q1", ctypes.c_int32), ("param", ctypes.c_int32), ("angle", ctypes.c_double),
+                ("mat", ctypes.POINTER(ctypes.c_double))]
+
+
+class Circuit(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32), ("n_params", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("gates", ctypes.POINTER(Gate))]
+
+
+class Hamiltonian(ctypes.Structure):
+    _fields_ = [("n_terms", ctypes.c_int32), ("pad", ctypes.c_int32), ("coeff", ctypes.POINTER(ctypes.c_double)),
+                ("term_off", ctypes.POINTER(ctypes.c_int32)), ("qubits", ctypes.POINTER(ctypes.c_int32)),
+                ("paulis", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_queue", ctypes.c_int32), ("cone_cap", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("circuit", ctypes.POINTER(Circuit)), ("params", ctypes.POINTER(ctypes.c_double)),
+                ("H", ctypes.POINTER(Hamiltonian)), ("want_grad", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "rejected", "cancelled", "failed", "steps",
+                                                "launches", "inflight_bytes", "peak_inflight_bytes", "queued",
+                                                "running")]
+
+
+assert ctypes.sizeof(Gate) == 32 and ctypes.sizeof(Circuit) == 24 and ctypes.sizeof(Hamiltonian) == 40
+
+EXPORTS = [
+    "qsim_init", "qsim_finalize", "qsim_strerror", "qsim_last_error", "qsim_create_state", "qsim_destroy_state",
+    "qsim_apply_layer", "qsim_expect", "qsim_state_to_host", "qsim_state_device_ptr", "qsim_expect_circuit",
+    "qsim_expect_grad", "qsim_lightcone_sets", "qsim_plan_dense", "qsim_submit", "qsim_poll", "qsim_cancel",
+    "qsim_server_stats_get", "qsim_timing_enable", "qsim_timing_get",
+]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libqsim.so is not built ({LIB_PATH}); run __graft_entry__.build() or "
+                          "python paper_2112_10239_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, V = ctypes.POINTER, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    sig = {
+        "qsim_init": (I, [P(Options), P(V)]),
+        "qsim_finalize": (None, [V]),
+        "qsim_strerror": (ctypes.c_char_p, [I]),
+        "qsim_last_error": (ctypes.c_char_p, [V]),
+        "qsim_create_state": (I, [V, I, I, I, V, V, P(V)]),
+        "qsim_destroy_state": (I, [V]),
+        "qsim_apply_layer": (I, [V, P(Gate), I, P(D), I]),
+        "qsim_expect": (I, [V, P(Hamiltonian), P(D)]),
+        "qsim_state_to_host": (I, [V, V]),
+        "qsim_state_device_ptr": (I, [V, P(V)]),
+        "qsim_expect_circuit": (I, [V, P(Circuit), P(D), I, P(Hamiltonian), I, I, V, P(D), P(V)]),
+        "qsim_expect_grad": (I, [V, P(Circuit), P(D), I, P(Hamiltonian), I, V, V, P(D), P(D)]),
+        "qsim_lightcone_sets": (I, [P(Circuit), P(Hamiltonian), P(ctypes.c_int32), P(ctypes.c_int32), I]),
+        "qsim_plan_dense": (I, [P(Circuit), P(Hamiltonian), I, P(ctypes.c_int64), P(ctypes.c_int32), I]),
+        "qsim_submit": (I, [V, P(Request), P(ctypes.c_uint64)]),
+        "qsim_poll": (I, [V, ctypes.c_uint64, P(D), P(D)]),
+        "qsim_cancel": (I, [V, ctypes.c_uint64]),
+        "qsim_server_stats_get": (I, [V, P(ServerStats)]),
+        "qsim_timing_enable": (I, [V, I]),
+        "qsim_timing_get": (I, [V, P(D), P(D), P(ctypes.c_int32), P(ctypes.c_int32), I, P(I)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def strerror(code: int) -> str:
+    return lib.qsim_strerror(code).decode()
+
+
+# ---------------------------------------------------------------------------
+# marshalling of circuits and Hamiltonians
+# ---------------------------------------------------------------------------
+
+class CCircuit:
+    """A ctypes view of a gate list; keeps the backing arrays alive."""
+
+    def __init__(self, n: int, gates: np.ndarray, n_params: int, mats: dict | None = None):
+        self._mats = {}
+        g = gates
+        arr = (Gate * max(1, len(g)))()
+        for i in range(len(g)):
+            e = arr[i]
+            e.kind = int(g["kind"][i])
+            e.q0 = int(g["q0"][i])
+            e.q1 = int(g["q1"][i])
+            e.param = int(g["param"][i])
+            e.angle = float(g["angle"][i])
+            if mats and i in mats:
+                m = np.asarray(mats[i], dtype=np.complex128).reshape(2, 2)
+                buf = np.empty(8, dtype=np.float64)
+                buf[0::2] = m.real.ravel()
+                buf[1::2] = m.imag.ravel()
+                self._mats[i] = buf
+                e.mat = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._arr = arr
+        self.c = Circuit(n, len(g), n_params, 0, arr)
+        self.n, self.n_params = n, n_params
+
+    @classmethod
+    def of(cls, circ) -> "CCircuit":
+        """From any object with ``n``, ``gates`` (structured array), ``n_params`` and ``mats``."""
+        return cls(circ.n, circ.gates, circ.n_params, getattr(circ, "mats", None))
+
+
+class CHamiltonian:
+    def __init__(self, coeff, term_off, qubits, paulis):
+        self._coeff = np.ascontiguousarray(coeff, dtype=np.float64)
+        self._off = np.ascontiguousarray(term_off, dtype=np.int32)
+        self._q = np.ascontiguousarray(qubits, dtype=np.int32)
+        self._p = np.ascontiguousarray(paulis, dtype=np.uint8)
+        if self._q.size == 0:
+            self._q = np.zeros(1, dtype=np.int32)
+            self._p = np.zeros(1, dtype=np.uint8)
+        if self._coeff.size == 0:
+            self._coeff = np.zeros(1)
+        self.h = Hamiltonian(len(term_off) - 1, 0, self._coeff.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             self._off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             self._q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             self._p.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+
+    @classmethod
+    def of(cls, H) -> "CHamiltonian":
+        return cls(H.coeff, H.term_off, H.qubits, H.paulis)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _params(theta, rows: int, n_params: int) -> np.ndarray:
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(rows, n_params) if n_params else np.zeros((rows, 1))
+    return th
+
+
+# ---------------------------------------------------------------------------
+# host-only calls
+# ---------------------------------------------------------------------------
+
+def lightcone_sets(circ, H):
+    cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
+    T = ch.h.n_terms
+    cap = max(1, T * circ.n)
+    off = np.zeros(T + 1, dtype=np.int32)
+    qs = np.zeros(cap, dtype=np.int32)
+    rc = lib.qsim_lightcone_sets(ctypes.byref(cc.c), ctypes.byref(ch.h),
+                                 off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 qs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cap)
+    if rc != OK:
+        raise QsimError(rc, "qsim_lightcone_sets: " + strerror(rc))
+    return [qs[off[t]:off[t + 1]].copy() for t in range(T)]
+
+
+def plan_dense(circ, H=None, dtype: int = C64):
+    """(info dict, order array [G', 4] of (pass, stage, op, gate)) for a dense plan."""
+    cc = CCircuit.of(circ)
+    ch = CHamiltonian.of(H) if H is not None else None
+    info = np.zeros(4, dtype=np.int64)
+    cap = max(1, circ.n_gates)
+    order = np.zeros(cap * 4, dtype=np.int32)
+    rc = lib.qsim_plan_dense(ctypes.byref(cc.c), ctypes.byref(ch.h) if ch else None, dtype,
+                             info.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                             order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cap)
+    if rc != OK:
+        raise QsimError(rc, "qsim_plan_dense: " + strerror(rc))
+    d = dict(passes=int(info[0]), stages=int(info[1]), ops=int(info[2]), meas_passes=int(info[3]))
+    return d, order.reshape(-1, 4)[: circ.n_gates].copy()
+
+
+# ---------------------------------------------------------------------------
+# context
+# ---------------------------------------------------------------------------
+
+class Context:
+    """A libqsim context on one HIP device (device=-1: host-only, simulated serving)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_queue: int = 0, cone_cap: int = 0):
+        self._lib = lib
+        opt = Options(device, max_queue, cone_cap, 0, hbm_budget_bytes)
+        p = ctypes.c_void_p()
+        rc = lib.qsim_init(ctypes.byref(opt), ctypes.byref(p))
+        if rc != OK:
+            raise QsimError(rc, "qsim_init: " + strerror(rc))
+        self.ptr = p
+
+    def close(self):
+        if self.ptr:
+            self._lib.qsim_finalize(self.ptr)
+            self.ptr = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def last_error(self) -> str:
+        return lib.qsim_last_error(self.ptr).decode()
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise QsimError(rc, f"{what}: {strerror(rc)}: {self.last_error()}")
+
+    # -- one-call evaluation ----------------------------------------------------
+    def expect_circuit(self, circ, H, theta, mode: int = MODE_AUTO, dtype: int = C64, stream=None, keep=False):
+        """<H> for theta [P] (float) or [B, P] ([B]); keep=True also returns a State."""
+        th = np.asarray(theta, dtype=np.float64)
+        single = th.ndim <= 1
+        rows = 1 if single else th.shape[0]
+        th = _params(th, rows, circ.n_params)
+        cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
+        out = np.zeros(rows)
+        kp = ctypes.c_void_p()
+        rc = lib.qsim_expect_circuit(self.ptr, ctypes.byref(cc.c), _dptr(th), rows, ctypes.byref(ch.h), mode, dtype,
+                                     stream, _dptr(out), ctypes.byref(kp) if keep else None)
+        self._check(rc, "qsim_expect_circuit")
+        val = float(out[0]) if single else out
+        if keep:
+            return val, State._wrap(self, kp, circ.n, rows, dtype)
+        return val
+
+    def expect_grad(self, circ, H, theta, dtype: int = C64, stream=None, saved=None, want_E=True):
+        """(E [B], grad [B, P]) by the adjoint method; theta [P] or [B, P]."""
+        th = np.asarray(theta, dtype=np.float64)
+        single = th.ndim <= 1
+        rows = 1 if single else th.shape[0]
+        th = _params(th, rows, circ.n_params)
+        cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
+        E = np.zeros(rows)
+        g = np.zeros((rows, max(1, circ.n_params)))
+        rc = lib.qsim_expect_grad(self.ptr, ctypes.byref(cc.c), _dptr(th), rows, ctypes.byref(ch.h), dtype, stream,
+                                  saved.ptr if saved is not None else None, _dptr(E) if want_E else None, _dptr(g))
+        self._check(rc, "qsim_expect_grad")
+        g = g[:, : circ.n_params]
+        if single:
+            return float(E[0]), g[0]
+        return E, g
+
+    # -- states -------------------------------------------------------------------
+    def create_state(self, n: int, batch: int = 1, dtype: int = C64, dev_buf=None, stream=None) -> "State":
+        p = ctypes.c_void_p()
+        rc = lib.qsim_create_state(self.ptr, n, batch, dtype, dev_buf, stream, ctypes.byref(p))
+        self._check(rc, "qsim_create_state")
+        return State._wrap(self, p, n, batch, dtype)
+
+    # -- per-launch timing -----------------------------------------------------------
+    def timing_enable(self, on: bool = True):
+        self._check(lib.qsim_timing_enable(self.ptr, int(on)), "qsim_timing_enable")
+
+    def timing_get(self, cap: int = 1 << 16):
+        """Records of timed launches: dict of arrays ms, bytes, flags, kind."""
+        ms = np.zeros(cap)
+        by = np.zeros(cap)
+        fl = np.zeros(cap, dtype=np.int32)
+        kd = np.zeros(cap, dtype=np.int32)
+        cnt = ctypes.c_int()
+        self._check(lib.qsim_timing_get(self.ptr, _dptr(ms), _dptr(by), fl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                        kd.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cap, ctypes.byref(cnt)),
+                    "qsim_timing_get")
+        k = cnt.value
+        return dict(ms=ms[:k], bytes=by[:k], flags=fl[:k], kind=kd[:k])
+
+    # -- serving ------------------------------------------------------------------
+    def submit(self, circ, H, theta, want_grad: bool = False) -> int:
+        cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1)
+        if th.size == 0:
+            th = np.zeros(1)
+        req = Request(ctypes.pointer(cc.c), _dptr(th), ctypes.pointer(ch.h), int(want_grad), 0)
+        t = ctypes.c_uint64()
+        rc = lib.qsim_submit(self.ptr, ctypes.byref(req), ctypes.byref(t))
+        if rc != OK:
+            raise QsimError(rc, f"qsim_submit: {strerror(rc)}: {self.last_error()}")
+        return int(t.value)
+
+    def poll(self, ticket: int, n_params: int = 0):
+        """(status, E, grad or None)."""
+        E = np.zeros(1)
+        g = np.zeros(max(1, n_params))
+        rc = lib.qsim_poll(self.ptr, ctypes.c_uint64(ticket), _dptr(E), _dptr(g))
+        return rc, float(E[0]), (g[:n_params] if n_params else None)
+
+    def cancel(self, ticket: int) -> int:
+        return lib.qsim_cancel(self.ptr, ctypes.c_uint64(ticket))
+
+    def server_stats(self) -> dict:
+        s = ServerStats()
+        self._check(lib.qsim_server_stats_get(self.ptr, ctypes.byref(s)), "qsim_server_stats_get")
+        return {k: int(getattr(s, k)) for k, _ in ServerStats._fields_}
+
+
+class State:
+    """A batch of device states (qsim_create_state)."""
+
+    @classmethod
+    def _wrap(cls, ctx, p, n, batch, dtype):
+        s = cls.__new__(cls)
+        s.ctx, s.ptr, s.n, s.batch, s.dtype = ctx, p, n, batch, dtype
+        return s
+
+    def destroy(self):
+        if self.ptr:
+            lib.qsim_destroy_state(self.ptr)
+            self.ptr = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def apply_layer(self, gates: np.ndarray, params=None, n_params: int = 0, mats=None):
+        cc = CCircuit(self.n, gates, n_params, mats)
+        th = None
+        if n_params:
+            th = np.ascontiguousarray(params, dtype=np.float64).reshape(self.batch, n_params)
+        rc = lib.qsim_apply_layer(self.ptr, cc._arr, len(gates), _dptr(th) if th is not None else None, n_params)
+        self.ctx._check(rc, "qsim_apply_layer")
+
+    def expect(self, H) -> np.ndarray:
+        ch = CHamiltonian.of(H)
+        out = np.zeros(self.batch)
+        self.ctx._check(lib.qsim_expect(self.ptr, ctypes.byref(ch.h), _dptr(out)), "qsim_expect")
+        return out
+
+    def to_host(self) -> np.ndarray:
+        dt = np.complex64 if self.dtype == C64 else np.complex128
+        out = np.empty((self.batch, 1 << self.n), dtype=dt)
+        self.ctx._check(lib.qsim_state_to_host(self.ptr, out.ctypes.data_as(ctypes.c_void_p)), "qsim_state_to_host")
+        return out
+
+    def device_ptr(self) -> int:
+        p = ctypes.c_void_p()
+        self.ctx._check(lib.qsim_state_device_ptr(self.ptr, ctypes.byref(p)), "qsim_state_device_ptr")
+        return int(p.value or 0)

@@ -1,0 +1,341 @@
+"""GPU parity: libqsim (HIP, gfx950) against the CPU oracle on the same seeded inputs.
+
+Tolerances: complex64 results within 1e-5 * sum|coeff| of the complex128
+oracle, complex128 results within 1e-10 * sum|coeff|; light-cone qubit sets
+bit-exact.  Every call goes through the C-ABI (ctypes binding).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-5
+TOL128 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import paper_2112_10239_amd as Q
+
+    return Q
+
+
+@pytest.fixture(scope="module")
+def eng(Q):
+    ctx = Q.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def tol(H, dtype):
+    return (TOL64 if dtype == 0 else TOL128) * max(1.0, H.abs_coeff_sum())
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# --- closed forms through the library -------------------------------------------
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_single_qubit_closed_forms(Q, eng, dtype):
+    say("closed forms dtype", dtype)
+    b = W.GateListBuilder(1)
+    b.rot(W.RY, 0)
+    b.rot(W.RZ, 0)
+    c = b.build()
+    for t, p in [(0.3, 0.7), (1.2, -2.5), (-2.0, 3.0)]:
+        for L, want in (("X", math.sin(t) * math.cos(p)), ("Y", math.sin(t) * math.sin(p)), ("Z", math.cos(t))):
+            H = W.Hamiltonian.from_terms([(1.0, [(0, L)])])
+            got = eng.expect_circuit(c, H, [t, p], mode=Q.MODE_DENSE, dtype=dtype)
+            assert abs(got - want) <= (2e-6 if dtype == 0 else 1e-12), (L, got, want)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 15, 17])
+def test_ghz(Q, eng, n):
+    say("ghz", n)
+    b = W.GateListBuilder(n)
+    b.rot(W.RY, 0, fixed_angle=math.pi / 2)
+    for i in range(n - 1):
+        b.two(W.CNOT, i, i + 1)
+    c = b.build()
+    terms = [(1.0, [(0, "Z"), (n - 1, "Z")]), (1.0, [(i, "X") for i in range(n)]) if n <= 4 else (0.0, [(0, "Z")]),
+             (1.0, [(n // 2, "Z")]), (1.0, [(n - 1, "X")])]
+    H = W.Hamiltonian.from_terms(terms)
+    vals = [eng.expect_circuit(c, W.Hamiltonian.from_terms([t]), [], mode=Q.MODE_DENSE) for t in terms]
+    assert vals[0] == pytest.approx(1.0, abs=1e-6)
+    if n <= 4:
+        assert vals[1] == pytest.approx(1.0, abs=1e-6)
+    assert vals[2] == pytest.approx(0.0, abs=1e-6)
+    assert vals[3] == pytest.approx(0.0, abs=1e-6)
+    assert eng.expect_circuit(c, H, [], mode=Q.MODE_DENSE) == pytest.approx(sum(t[0] * v for t, v in zip(terms, vals)),
+                                                                           abs=1e-6)
+
+
+# --- the small named workload in complex128 -----------------------------------------
+
+def test_ring_maxcut_n10_c128(Q, eng, oracle_mod):
+    w = W.small_ring_maxcut()
+    say("ring maxcut n10 c128")
+    want = oracle_mod.expect(w.circuit, w.H, w.theta)
+    got = eng.expect_circuit(w.circuit, w.H, w.theta, mode=Q.MODE_DENSE, dtype=Q.C128)
+    assert abs(got - want) <= tol(w.H, 1), (got, want)
+    got64 = eng.expect_circuit(w.circuit, w.H, w.theta, mode=Q.MODE_DENSE, dtype=Q.C64)
+    assert abs(got64 - want) <= tol(w.H, 0)
+
+
+# --- dense brickwork family ---------------------------------------------------------
+
+@pytest.mark.parametrize("n,depth", [(6, 3), (10, 20), (14, 10), (15, 8), (16, 12), (19, 6), (20, 20)])
+def test_dense_tfim_family(Q, eng, oracle_mod, n, depth):
+    say("dense tfim", n, depth)
+    c = W.brickwork_ry_rz_cnot(n, depth)
+    H = W.tfim(n, 1.0)
+    th = W.angles(c.n_params, [2, 1, n, depth])
+    want = oracle_mod.expect(c, H, th)
+    got = eng.expect_circuit(c, H, th, mode=Q.MODE_DENSE)
+    assert abs(got - want) <= tol(H, 0), (got, want)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_circuits_all_kinds(Q, eng, oracle_mod, seed):
+    rng = np.random.default_rng([20, seed])
+    n = int(rng.integers(1, 19))
+    c = W.random_circuit(n, int(rng.integers(1, 120)), rng)
+    th = W.angles(max(c.n_params, 1), [20, seed, 1])[: c.n_params]
+    H = W.random_hamiltonian(n, 12, rng, max_weight=min(n, 4))
+    say("random", seed, "n", n, "gates", c.n_gates)
+    want = oracle_mod.expect(c, H, th)
+    for dtype in (0, 1):
+        got = eng.expect_circuit(c, H, th, mode=Q.MODE_DENSE, dtype=dtype)
+        assert abs(got - want) <= tol(H, dtype), (dtype, got, want)
+
+
+@pytest.mark.parametrize("n", [1, 4, 9, 16, 18])
+def test_amplitudes(Q, eng, oracle_mod, n):
+    say("amplitudes", n)
+    rng = np.random.default_rng([21, n])
+    c = W.random_circuit(n, 60, rng)
+    th = W.angles(max(c.n_params, 1), [21, n])[: c.n_params]
+    psi_o = oracle_mod.statevector(c, th)
+    st = eng.create_state(n, batch=1, dtype=Q.C128)
+    st.apply_layer(c.gates, th, c.n_params, mats=c.mats)
+    psi = st.to_host()[0]
+    st.destroy()
+    np.testing.assert_allclose(psi, psi_o, atol=1e-12)
+
+
+def test_batched_rows_and_layers(Q, eng, oracle_mod):
+    n, depth, B = 12, 4, 5
+    c = W.brickwork_ry_rz_cnot(n, depth)
+    H = W.tfim(n, 0.5)
+    th = np.stack([W.angles(c.n_params, [22, b]) for b in range(B)])
+    say("batched rows")
+    want = oracle_mod.expect(c, H, th)
+    got = eng.expect_circuit(c, H, th, mode=Q.MODE_DENSE)
+    np.testing.assert_allclose(got, want, atol=tol(H, 0))
+    # same circuit applied layer by layer through the stateful interface
+    st = eng.create_state(n, batch=B)
+    per_layer = len(c.gates) // depth
+    ppl = c.n_params // depth
+    for layer in range(depth):
+        g = c.gates[layer * per_layer:(layer + 1) * per_layer].copy()
+        g["param"] = np.where(g["param"] >= 0, g["param"] - layer * ppl, -1)
+        st.apply_layer(g, th[:, layer * ppl:(layer + 1) * ppl], ppl)
+    np.testing.assert_allclose(st.expect(H), want, atol=tol(H, 0))
+    st.destroy()
+
+
+def test_edge_cases(Q, eng, oracle_mod):
+    say("edge cases")
+    c = W.brickwork_ry_cz(7, 2)
+    th = W.angles(c.n_params, [23])
+    # empty Hamiltonian, identity only
+    assert eng.expect_circuit(c, W.Hamiltonian.from_terms([]), th, mode=Q.MODE_DENSE) == 0.0
+    assert eng.expect_circuit(c, W.Hamiltonian.from_terms([(2.5, [])]), th, mode=Q.MODE_DENSE) == 2.5
+    # no gates
+    e = W.GateListBuilder(5).build()
+    assert eng.expect_circuit(e, W.tfim(5, 1.0), [], mode=Q.MODE_DENSE) == pytest.approx(5.0, abs=1e-6)
+    # invalid inputs are rejected with EINVAL
+    bad = W.GateListBuilder(3)
+    bad.two(W.CZ, 1, 1)
+    with pytest.raises(Q.QsimError) as ei:
+        eng.expect_circuit(bad.build(), W.tfim(3, 1.0), [], mode=Q.MODE_DENSE)
+    assert ei.value.code == -1
+
+
+# --- light cones ---------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [8, 12, 14])
+def test_lightcone_equals_dense(Q, eng, oracle_mod, n):
+    say("lightcone vs dense", n)
+    c = W.brickwork_ry_cz(n, 4)
+    H = W.maxcut(W.random_regular3(n, np.random.default_rng([24, n])))
+    th = W.angles(c.n_params, [24, n, 1])
+    want = oracle_mod.expect(c, H, th)
+    lc = eng.expect_circuit(c, H, th, mode=Q.MODE_LIGHTCONE)
+    de = eng.expect_circuit(c, H, th, mode=Q.MODE_DENSE)
+    assert abs(lc - want) <= tol(H, 0)
+    assert abs(de - want) <= tol(H, 0)
+
+
+def test_lightcone_random_terms(Q, eng, oracle_mod):
+    rng = np.random.default_rng(25)
+    n = 13
+    c = W.random_circuit(n, 70, rng)
+    th = W.angles(max(c.n_params, 1), [25])[: c.n_params]
+    H = W.random_hamiltonian(n, 10, rng, max_weight=3)
+    say("lightcone random terms")
+    want = oracle_mod.expect(c, H, th)
+    assert abs(eng.expect_circuit(c, H, th, mode=Q.MODE_LIGHTCONE) - want) <= tol(H, 0)
+
+
+def test_lightcone_n500_vs_oracle(Q, eng, oracle_mod):
+    w = W.lightcone_maxcut()
+    say("lightcone n500")
+    sets = Q.lightcone_sets(w.circuit, w.H)
+    ref = oracle_mod.lightcone_sets(w.circuit, w.H)
+    assert all(np.array_equal(a, b) for a, b in zip(sets, ref))
+    want, _ = oracle_mod.expect_lightcone(w.circuit, w.H, w.theta)
+    got = eng.expect_circuit(w.circuit, w.H, w.theta, mode=Q.MODE_LIGHTCONE)
+    assert abs(got - want) <= tol(w.H, 0), (got, want)
+
+
+def test_lightcone_clifford_n500(Q, eng):
+    from tests import pinlib
+
+    w = W.lightcone_maxcut()
+    th = pinlib.clifford_angles(w.circuit.n_params, np.random.default_rng([11, 500]))
+    say("lightcone clifford n500")
+    want = pinlib.clifford_expect(w.circuit, w.H, th)
+    got = eng.expect_circuit(w.circuit, w.H, th, mode=Q.MODE_LIGHTCONE)
+    assert abs(got - want) <= 1e-3, (got, want)
+
+
+def test_product_state_n30_dense(Q, eng):
+    """No entanglers at n=30: closed form sum cos cos + h sum sin cos (dense 8 GiB state)."""
+    n = 30
+    b = W.GateListBuilder(n)
+    for q in range(n):
+        b.rot(W.RY, q)
+    for q in range(n):
+        b.rot(W.RZ, q)
+    c = b.build()
+    th = W.angles(2 * n, [99, n])
+    want = sum(math.cos(th[i]) * math.cos(th[(i + 1) % n]) for i in range(n)) + sum(
+        math.sin(th[i]) * math.cos(th[n + i]) for i in range(n))
+    say("product state n30")
+    got = eng.expect_circuit(c, W.tfim(n, 1.0), th, mode=Q.MODE_DENSE)
+    assert abs(got - want) <= 1e-5 * 60
+
+
+def test_clifford_n30_dense(Q, eng):
+    """Dense n=30 brickwork with Clifford angles against Heisenberg propagation (exact integers)."""
+    from tests import pinlib
+
+    w = W.dense_tfim()
+    th = pinlib.clifford_angles(w.circuit.n_params, np.random.default_rng([26, 30]))
+    want = pinlib.clifford_expect(w.circuit, w.H, th)
+    say("clifford n30 dense")
+    got = eng.expect_circuit(w.circuit, w.H, th, mode=Q.MODE_DENSE)
+    assert abs(got - want) <= 1e-5 * 60, (got, want)
+
+
+# --- gradients -------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_grad_random_vs_psr(Q, eng, oracle_mod, seed):
+    rng = np.random.default_rng([27, seed])
+    n = int(rng.integers(2, 15))
+    c = W.random_circuit(n, 50, rng, p_fixed=0.1)
+    th = W.angles(max(c.n_params, 1), [27, seed])[: c.n_params]
+    H = W.random_hamiltonian(n, 8, rng, max_weight=min(n, 3))
+    say("grad random", seed, n, c.n_params)
+    psr = oracle_mod.grad_psr(c, H, th)
+    E, g = eng.expect_grad(c, H, th)
+    assert abs(E - oracle_mod.expect(c, H, th)) <= tol(H, 0)
+    np.testing.assert_allclose(g, psr, atol=tol(H, 0))
+
+
+def test_grad_tfim_batch_subset(Q, eng, oracle_mod):
+    """The batched n=20 workload: rows 0-1 on a subset of parameters, shift rule and FD (h=1e-3)."""
+    w = W.batched_grad_tfim(batch=8)
+    c, H = w.circuit, w.H
+    say("grad tfim n20 batch 8")
+    E, g = eng.expect_grad(c, H, w.theta)
+    idx = np.array([0, 7, 19, 20, 39, 200, 321, 399], dtype=np.int32)
+    for row in (0, 1):
+        psr = oracle_mod.grad_psr(c, H, w.theta[row], idx)
+        np.testing.assert_allclose(g[row, idx], psr, atol=tol(H, 0))
+        fd = oracle_mod.grad_fd(c, H, w.theta[row], 1e-3, idx) * (1e-3 / math.sin(1e-3))
+        np.testing.assert_allclose(g[row, idx], fd, atol=tol(H, 0))
+    np.testing.assert_allclose(E[:2], oracle_mod.expect(c, H, w.theta[:2]), atol=tol(H, 0))
+
+
+def test_grad_saved_state_matches(Q, eng):
+    w = W.batched_grad_tfim(batch=3, n=12, depth=4)
+    E0, st = eng.expect_circuit(w.circuit, w.H, w.theta, mode=Q.MODE_DENSE, keep=True)
+    E1, g1 = eng.expect_grad(w.circuit, w.H, w.theta, saved=st)
+    st.destroy()
+    E2, g2 = eng.expect_grad(w.circuit, w.H, w.theta)
+    np.testing.assert_allclose(E1, E0, atol=1e-9)
+    np.testing.assert_allclose(E2, E0, atol=1e-9)
+    np.testing.assert_allclose(g1, g2, atol=1e-9)
+
+
+def test_autograd_function(Q, eng, oracle_mod):
+    import torch
+
+    from paper_2112_10239_amd.autograd import expectation
+
+    w = W.batched_grad_tfim(batch=3, n=10, depth=3)
+    theta = torch.tensor(w.theta, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    E = expectation(theta, eng, w.circuit, w.H)
+    (E * torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device="cuda:0")).sum().backward()
+    for row, wt in enumerate((1.0, -2.0, 0.5)):
+        psr = oracle_mod.grad_psr(w.circuit, w.H, w.theta[row])
+        np.testing.assert_allclose(theta.grad[row].cpu().numpy(), wt * psr, atol=tol(w.H, 0) * 2)
+
+
+# --- serving ---------------------------------------------------------------------------
+
+def test_serving_alone_equals_mix(Q, eng, oracle_mod):
+    reqs = [W.serving_request(r, n_range=(12, 18), depth_range=(4, 8)) for r in range(24)]
+    say("serving mix")
+    alone = {}
+    for r in reqs[:6]:
+        t = eng.submit(r.circuit, r.H, r.theta, r.want_grad)
+        while True:
+            st, E, g = eng.poll(t, r.circuit.n_params)
+            if st != 1:
+                break
+        assert st == 0
+        alone[r.rid] = (E, g)
+    tickets = [(r, eng.submit(r.circuit, r.H, r.theta, r.want_grad)) for r in reqs]
+    res = {}
+    pending = dict((t, r) for r, t in tickets)
+    while pending:
+        for t, r in list(pending.items()):
+            st, E, g = eng.poll(t, r.circuit.n_params)
+            if st == 1:
+                continue
+            assert st == 0, st
+            res[r.rid] = (E, g)
+            del pending[t]
+    for rid, (E, g) in alone.items():
+        assert res[rid][0] == pytest.approx(E, abs=1e-12)
+        if g is not None:
+            np.testing.assert_allclose(res[rid][1], g, atol=1e-12)
+    for r in reqs[:8]:
+        want = oracle_mod.expect(r.circuit, r.H, r.theta)
+        assert abs(res[r.rid][0] - want) <= tol(r.H, 0)
+        if r.want_grad:
+            idx = np.arange(0, r.circuit.n_params, max(1, r.circuit.n_params // 6), dtype=np.int32)
+            psr = oracle_mod.grad_psr(r.circuit, r.H, r.theta, idx)
+            np.testing.assert_allclose(res[r.rid][1][idx], psr, atol=tol(r.H, 0))
