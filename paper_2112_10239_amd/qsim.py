@@ -72,6 +72,13 @@ EXPORTS = [
 
 
 def _load():
+    # torch ships its own HIP runtime (same soname as the system one).  Loading
+    # torch first makes this library bind to that runtime, so one process never
+    # holds two HIP runtimes and torch's streams and device pointers are valid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libqsim.so is not built ({LIB_PATH}); run __graft_entry__.build() or "
                           "python paper_2112_10239_amd/build.py")

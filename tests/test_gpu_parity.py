@@ -284,9 +284,11 @@ def test_grad_saved_state_matches(Q, eng):
     E1, g1 = eng.expect_grad(w.circuit, w.H, w.theta, saved=st)
     st.destroy()
     E2, g2 = eng.expect_grad(w.circuit, w.H, w.theta)
-    np.testing.assert_allclose(E1, E0, atol=1e-9)
-    np.testing.assert_allclose(E2, E0, atol=1e-9)
-    np.testing.assert_allclose(g1, g2, atol=1e-9)
+    # E1 is re-measured from the kept state with a different tiling: same value up to fp32 summation order
+    np.testing.assert_allclose(E1, E0, atol=tol(w.H, 0))
+    # the same plans on the same inputs give the same bits
+    np.testing.assert_array_equal(E2, E0)
+    np.testing.assert_array_equal(g1, g2)
 
 
 def test_autograd_function(Q, eng, oracle_mod):
