@@ -209,6 +209,12 @@ int qsim_submit(qsim_ctx* ctx, const qsim_request* req, uint64_t* ticket);
  * for it, grad[n_params] are written and the ticket is consumed.  A failed or
  * cancelled request returns its error code and is consumed.  Thread-safe. */
 int qsim_poll(qsim_ctx* ctx, uint64_t ticket, double* E, double* grad);
+/* qsim_poll that also writes times[0..2] (if times != NULL): the qsim_clock()
+ * seconds at which the request was submitted, admitted to the device and
+ * completed.  Thread-safe. */
+int qsim_poll_timed(qsim_ctx* ctx, uint64_t ticket, double* E, double* grad, double* times);
+/* Monotonic clock in seconds used for the serving timestamps. */
+double qsim_clock(void);
 /* Cancel a queued or running request.  Thread-safe. */
 int qsim_cancel(qsim_ctx* ctx, uint64_t ticket);
 int qsim_server_stats_get(qsim_ctx* ctx, qsim_server_stats* out);

@@ -206,17 +206,63 @@ static void cache_put(qsim_ctx* ctx, uint64_t key, std::shared_ptr<DevPlan> p) {
   ctx->plans[key] = std::move(p);
 }
 
+// Plan of the gates alone, cached by circuit structure.
+static std::shared_ptr<DevPlan> gate_plan(qsim_ctx* ctx, const CircuitDesc& c, int c128, bool init, bool store_final,
+                                          int& rc) {
+  const int extra = 0x500 | c128 | (init << 1) | (store_final << 2);
+  const uint64_t key = structure_hash(c, {}, extra);
+  if (auto p = cache_get(ctx, key)) return p;
+  auto dp = std::make_shared<DevPlan>();
+  std::vector<PGate> pg;
+  forward_pgates(c, true, pg, dp->plan.slots);
+  PlanOptions o = fwd_options(c128);
+  o.init = init;
+  o.store_final = store_final;
+  std::string err;
+  if (plan_forward(c.n, pg, {}, o, dp->plan, err)) {
+    set_error(ctx, err);
+    rc = QSIM_EINVAL;
+    return nullptr;
+  }
+  hipError_t e = dp->upload(ctx->mock);
+  if (e != hipSuccess) {
+    rc = hip_fail(ctx, e, "plan upload");
+    return nullptr;
+  }
+  cache_put(ctx, key, dp);
+  return dp;
+}
+
 std::shared_ptr<DevPlan> get_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
                                         int c128, bool init, bool store_final, bool measure, int& rc) {
   rc = QSIM_OK;
-  const int extra = 0x100 | c128 | (init << 1) | (store_final << 2) | (measure << 3);
-  const uint64_t key = structure_hash(c, measure ? terms : std::vector<Term>{}, extra);
-  if (auto p = cache_get(ctx, key)) return p;
-  auto dp = std::make_shared<DevPlan>();
-  std::vector<PGate> pg, meas;
-  forward_pgates(c, true, pg, dp->plan.slots);
+  std::vector<PGate> meas;
   double cst = 0;
   if (measure) term_pgates(terms, false, meas, cst);
+  bool diag = true;
+  for (const PGate& t : meas) diag &= t.fmask == 0;
+  if (!measure || meas.empty() || diag) {
+    // gates from the structure cache, diagonal terms appended to its last stage
+    auto gp = gate_plan(ctx, c, c128, init, store_final, rc);
+    if (!gp) return nullptr;
+    if (meas.empty() && cst == 0.0) return gp;
+    auto dp = std::make_shared<DevPlan>();
+    dp->plan = gp->plan;
+    append_diag_measure(dp->plan, meas);
+    dp->plan.const_term = cst;
+    hipError_t e = dp->upload(ctx->mock);
+    if (e != hipSuccess) {
+      rc = hip_fail(ctx, e, "plan upload");
+      return nullptr;
+    }
+    return dp;
+  }
+  const int extra = 0x100 | c128 | (init << 1) | (store_final << 2) | (measure << 3);
+  const uint64_t key = structure_hash(c, terms, extra);
+  if (auto p = cache_get(ctx, key)) return p;
+  auto dp = std::make_shared<DevPlan>();
+  std::vector<PGate> pg;
+  forward_pgates(c, true, pg, dp->plan.slots);
   PlanOptions o = fwd_options(c128);
   o.init = init;
   o.store_final = store_final;

@@ -723,6 +723,22 @@ int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, P
   return 0;
 }
 
+void append_diag_measure(Plan& plan, const std::vector<PGate>& meas) {
+  if (meas.empty() || plan.passes.empty()) return;
+  PassDesc& pd = plan.passes.back();
+  StageDesc& st = plan.stages.back();
+  uint64_t L = 0;
+  for (int k = 0; k < pd.m; ++k) L |= 1ull << pd.lpos[k];
+  PassEmitter em(plan, pd.n, pd.m, pd.r, L);
+  std::vector<int> rb(st.rb, st.rb + pd.r);
+  for (const PGate& g : meas) plan.ops.push_back(em.to_devop(g, rb));
+  st.op_end = (int)plan.ops.size();
+  if (!(pd.flags & PF_MEASURE)) {
+    pd.flags |= PF_MEASURE;
+    pd.meas_index = plan.n_meas++;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // light cones
 // ---------------------------------------------------------------------------

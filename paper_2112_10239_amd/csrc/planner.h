@@ -94,6 +94,11 @@ int plan_forward(int n, const std::vector<PGate>& gates, const std::vector<PGate
 int plan_happly(int n, const std::vector<PGate>& hterms, const PlanOptions& o, Plan& plan, std::string& err);
 int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, Plan& plan, std::string& err);
 
+// Add diagonal measurement terms (PG_MEAS_Z) to the last stage of a plan that
+// ends with all gates applied; marks the last pass PF_MEASURE.  Lets a plan of
+// the gates alone be shared by requests that differ only in a diagonal H.
+void append_diag_measure(Plan& plan, const std::vector<PGate>& meas);
+
 // Canonical light cone of one term: ascending qubits and in-cone gate indices.
 void light_cone(const CircuitDesc& c, const std::vector<int>& support, std::vector<int>& set,
                 std::vector<int>& gates);

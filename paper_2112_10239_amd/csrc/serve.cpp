@@ -14,11 +14,11 @@ constexpr size_t kMaxRunning = 512;
 
 enum Phase { PH_FWD = 0, PH_HAPPLY = 1, PH_ADJ = 2, PH_DONE = 3 };
 
+}  // namespace
+
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
-
-}  // namespace
 
 struct SReq {
   uint64_t ticket = 0;
@@ -43,6 +43,7 @@ struct SReq {
   std::vector<float> h_coef_f, h_coef_a;
   std::vector<double> h_res;
   int passes_done = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -175,6 +176,7 @@ int Server::submit(const qsim_request* rq, uint64_t* ticket) {
   }
   r->ticket = next_ticket_++;
   *ticket = r->ticket;
+  r->t_submit = now_s();
   queue_.push_back(r.get());
   all_.emplace(r->ticket, std::move(r));
   st_.submitted++;
@@ -182,13 +184,18 @@ int Server::submit(const qsim_request* rq, uint64_t* ticket) {
   return QSIM_OK;
 }
 
-int Server::poll(uint64_t ticket, double* E, double* grad) {
+int Server::poll(uint64_t ticket, double* E, double* grad, double* times) {
   std::lock_guard<std::mutex> g(mu_);
   auto it = all_.find(ticket);
   if (it == all_.end()) return QSIM_ENOTFOUND;
   SReq* r = it->second.get();
   if (!r->done) return QSIM_PENDING;
   const int status = r->status;
+  if (times) {
+    times[0] = r->t_submit;
+    times[1] = r->t_admit;
+    times[2] = r->t_done;
+  }
   if (status == QSIM_OK) {
     if (E) *E = r->E;
     if (grad && r->want_grad) std::memcpy(grad, r->grad.data(), sizeof(double) * r->grad.size());
@@ -207,6 +214,7 @@ int Server::cancel(uint64_t ticket) {
   if (q != queue_.end()) {
     queue_.erase(q);
     r->done = true;
+    r->t_done = now_s();
     r->status = QSIM_ECANCELED;
     st_.cancelled++;
   }
@@ -394,6 +402,7 @@ void Server::loop() {
         running_.push_back(r);
         inflight_ += r->footprint;
         peak_ = std::max(peak_, inflight_);
+        r->t_admit = now_s();
         fresh.push_back(r);
       }
       run = running_;
@@ -450,6 +459,7 @@ void Server::loop() {
       }
       inflight_ -= r->footprint;
       release(r);
+      r->t_done = now_s();
       r->done = true;
       running_.erase(std::find(running_.begin(), running_.end(), r));
     }
@@ -493,8 +503,15 @@ int qsim_submit(qsim_ctx* ctx, const qsim_request* req, uint64_t* ticket) {
 
 int qsim_poll(qsim_ctx* ctx, uint64_t ticket, double* E, double* grad) {
   if (!ctx) return QSIM_EINVAL;
-  return server_of(ctx)->poll(ticket, E, grad);
+  return server_of(ctx)->poll(ticket, E, grad, nullptr);
 }
+
+int qsim_poll_timed(qsim_ctx* ctx, uint64_t ticket, double* E, double* grad, double* times) {
+  if (!ctx) return QSIM_EINVAL;
+  return server_of(ctx)->poll(ticket, E, grad, times);
+}
+
+double qsim_clock(void) { return qsim::now_s(); }
 
 int qsim_cancel(qsim_ctx* ctx, uint64_t ticket) {
   if (!ctx) return QSIM_EINVAL;

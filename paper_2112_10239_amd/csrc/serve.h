@@ -44,7 +44,7 @@ class Server {
   Server(qsim_ctx* ctx, bool mock);
   ~Server();
   int submit(const qsim_request* r, uint64_t* ticket);
-  int poll(uint64_t ticket, double* E, double* grad);
+  int poll(uint64_t ticket, double* E, double* grad, double* times);
   int cancel(uint64_t ticket);
   void stats(qsim_server_stats* out);
 

@@ -67,7 +67,7 @@ EXPORTS = [
     "qsim_init", "qsim_finalize", "qsim_strerror", "qsim_last_error", "qsim_create_state", "qsim_destroy_state",
     "qsim_apply_layer", "qsim_expect", "qsim_state_to_host", "qsim_state_device_ptr", "qsim_expect_circuit",
     "qsim_expect_grad", "qsim_lightcone_sets", "qsim_plan_dense", "qsim_submit", "qsim_poll", "qsim_cancel",
-    "qsim_server_stats_get", "qsim_timing_enable", "qsim_timing_get",
+    "qsim_server_stats_get", "qsim_timing_enable", "qsim_timing_get", "qsim_poll_timed", "qsim_clock",
 ]
 
 
@@ -104,6 +104,8 @@ def _load():
         "qsim_cancel": (I, [V, ctypes.c_uint64]),
         "qsim_server_stats_get": (I, [V, P(ServerStats)]),
         "qsim_timing_enable": (I, [V, I]),
+        "qsim_poll_timed": (I, [V, ctypes.c_uint64, P(D), P(D), P(D)]),
+        "qsim_clock": (D, []),
         "qsim_timing_get": (I, [V, P(D), P(D), P(ctypes.c_int32), P(ctypes.c_int32), I, P(I)]),
     }
     for name, (res, args) in sig.items():
@@ -114,6 +116,11 @@ def _load():
 
 
 lib = _load()
+
+
+def clock() -> float:
+    """The library's monotonic clock (seconds), the timeline of serving timestamps."""
+    return float(lib.qsim_clock())
 
 
 def strerror(code: int) -> str:
@@ -320,7 +327,10 @@ class Context:
 
     # -- serving ------------------------------------------------------------------
     def submit(self, circ, H, theta, want_grad: bool = False) -> int:
-        cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
+        return self.submit_prepared(CCircuit.of(circ), CHamiltonian.of(H), theta, want_grad)
+
+    def submit_prepared(self, cc: "CCircuit", ch: "CHamiltonian", theta, want_grad: bool = False) -> int:
+        """Submit with marshalled inputs (the library deep-copies them)."""
         th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1)
         if th.size == 0:
             th = np.zeros(1)
@@ -337,6 +347,14 @@ class Context:
         g = np.zeros(max(1, n_params))
         rc = lib.qsim_poll(self.ptr, ctypes.c_uint64(ticket), _dptr(E), _dptr(g))
         return rc, float(E[0]), (g[:n_params] if n_params else None)
+
+    def poll_timed(self, ticket: int, n_params: int = 0):
+        """(status, E, grad or None, (t_submit, t_admit, t_done)) on the qsim_clock() timeline."""
+        E = np.zeros(1)
+        g = np.zeros(max(1, n_params))
+        t = np.zeros(3)
+        rc = lib.qsim_poll_timed(self.ptr, ctypes.c_uint64(ticket), _dptr(E), _dptr(g), _dptr(t))
+        return rc, float(E[0]), (g[:n_params] if n_params else None), tuple(float(x) for x in t)
 
     def cancel(self, ticket: int) -> int:
         return lib.qsim_cancel(self.ptr, ctypes.c_uint64(ticket))
