@@ -2,6 +2,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 namespace qsim {
@@ -63,16 +64,35 @@ static double pass_bytes(const PassDesc& p, int rows, int c128) {
   return amps * k * (c128 ? 16.0 : 8.0);
 }
 
+// Tuning knobs read once from the environment (for A/B measurements):
+// QSIM_FWD_R = register bits of complex64 forward passes (4 or 5, default 5),
+// QSIM_ABSORB = 0 disables CNOT exit permutations.
+static int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
 PlanOptions fwd_options(int c128) {
+  static const int r64 = env_int("QSIM_FWD_R", 5) == 4 ? 4 : 5;
+  static const bool absorb = env_int("QSIM_ABSORB", 1) != 0;
   PlanOptions o;
   o.m_max = c128 ? 13 : 14;
-  o.r = 4;
+  o.r = c128 ? 4 : r64;
   o.c_low = 6;
+  o.absorb = absorb;
+  return o;
+}
+
+PlanOptions cone_options(int c128) {
+  PlanOptions o = fwd_options(c128);
+  o.r = 4;  // the cone kernel keeps 16 amplitudes per thread
   return o;
 }
 
 PlanOptions dual_options(int c128) {
+  static const bool absorb = env_int("QSIM_ABSORB", 1) != 0;
   PlanOptions o;
+  o.absorb = absorb;
   o.m_max = c128 ? 12 : 13;
   o.r = c128 ? 3 : 4;
   o.c_low = 6;
@@ -347,7 +367,7 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
   if (auto p = cache_get(ctx, key)) return p;
   auto dp = std::make_shared<DevPlan>();
   Plan& all = dp->plan;
-  const PlanOptions base = fwd_options(c128);
+  const PlanOptions base = cone_options(c128);
   const int cap = ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20;
   std::vector<int> relabel(c.n, -1);
   for (const Term& t : terms) {

@@ -170,5 +170,6 @@ void timing_collect(qsim_ctx* ctx);  // after a stream sync
 // Tile options per state precision and kernel kind.
 PlanOptions fwd_options(int c128);
 PlanOptions dual_options(int c128);
+PlanOptions cone_options(int c128);
 
 }  // namespace qsim

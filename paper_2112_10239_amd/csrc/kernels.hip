@@ -171,30 +171,36 @@ __device__ __forceinline__ void ap_cz(cpx<T>* a, const BitSel& b1, const BitSel&
   }
 }
 
-// sum_i (-1)^{z(i)} |a_i|^2 ; z(i) = parity(i & rz) xor par
+// sum_i (-1)^{parity(i & rz)} p_i with p_i = |a_i|^2
 template <class T, int R>
-__device__ __forceinline__ double meas_z(const cpx<T>* a, uint32_t rz, uint32_t par) {
+__device__ __forceinline__ T meas_zp(const T* p, uint32_t rz) {
   T s = 0;
 #pragma unroll
-  for (int i = 0; i < (1 << R); ++i) {
-    const T p = a[i].x * a[i].x + a[i].y * a[i].y;
-    s += sgn<T>(__popc((uint32_t)i & rz) & 1) * p;
-  }
-  return par ? -(double)s : (double)s;
+  for (int i = 0; i < (1 << R); ++i) s += sgn<T>(__popc((uint32_t)i & rz) & 1) * p[i];
+  return s;
 }
 
-// Re( i^ph * sum_y (-1)^{z(y)} conj(a_{y^F}) a_y )
+// Re( i^ph * (-1)^par * sum_y (-1)^{parity(y & rz)} conj(a_{y^F}) a_y ).  The two
+// members of a pair (y, y^F) contribute g z + g' conj(z) with z = conj(a_{y^F}) a_y,
+// and g' = g or -g for every pair alike, so each pair costs one real product.
 template <class T, int R, int F>
 __device__ __forceinline__ double meas_f(const cpx<T>* a, uint32_t rz, uint32_t par, uint32_t ph) {
-  T sr = 0, si = 0;
+  const bool same = !(__popc((uint32_t)F & rz) & 1);
+  T acc = 0;
+  if (same) {
 #pragma unroll
-  for (int i = 0; i < (1 << R); ++i) {
-    const int k = i ^ F;
-    const T g = sgn<T>(__popc((uint32_t)i & rz) & 1);
-    sr += g * (a[k].x * a[i].x + a[k].y * a[i].y);
-    si += g * (a[k].x * a[i].y - a[k].y * a[i].x);
+    for (int i = 0; i < (1 << R); ++i) {
+      const int k = i ^ F;
+      if (i < k) acc += sgn<T>(__popc((uint32_t)i & rz) & 1) * (a[k].x * a[i].x + a[k].y * a[i].y);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) {
+      const int k = i ^ F;
+      if (i < k) acc += sgn<T>(__popc((uint32_t)i & rz) & 1) * (a[k].x * a[i].y - a[k].y * a[i].x);
+    }
   }
-  double vr = sr, vi = si;
+  double vr = same ? 2.0 * (double)acc : 0.0, vi = same ? 0.0 : 2.0 * (double)acc;
   if (par) {
     vr = -vr;
     vi = -vi;
@@ -270,35 +276,117 @@ __device__ __forceinline__ T grad_z(const cpx<T>* a, const cpx<T>* b, const BitS
 // one tile of one pass
 // ---------------------------------------------------------------------------
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations,
+// not for its outstanding HBM loads, so a prefetch of the next tile stays in
+// flight across the exchanges of the current one.
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <class T, int R, bool DUAL>
-__device__ __forceinline__ double run_tile(const PassDesc* __restrict__ P, const StageDesc* __restrict__ SD,
-                           const DevOp* __restrict__ OPS, cpx<T>* __restrict__ A, cpx<T>* __restrict__ B,
-                           const T* __restrict__ coef, uint64_t tile, cpx<T>* lds, double* red, double* gacc,
-                           double* __restrict__ grad_out, int64_t grad_stride) {
+struct TileRegs {
+  cpx<T> a[1 << R];
+  cpx<T> b[DUAL ? (1 << R) : 1];
+};
+
+__device__ __forceinline__ uint64_t tile_base(const PassDesc* __restrict__ P, uint64_t tile) {
+  uint64_t base = 0;
+  const int nn = P->n - P->m;
+  for (int k = 0; k < nn; ++k)
+    if ((tile >> k) & 1) base |= 1ull << P->npos[k];
+  return base;
+}
+
+// Thread-local part of stage S's local index (thread bits deposited into tb).
+template <int R>
+__device__ __forceinline__ uint32_t thread_local_index(const StageDesc* __restrict__ S, int m, int tid) {
+  uint32_t tl = 0;
+  for (int k = 0; k < m - R; ++k) tl |= ((uint32_t)(tid >> k) & 1u) << S->tb[k];
+  return tl;
+}
+
+// Global offsets (physical index bits) of stage S: per-thread part and per-register-bit parts.
+template <int R>
+__device__ __forceinline__ uint64_t stage_gaddr(const PassDesc* __restrict__ P, const StageDesc* __restrict__ S,
+                                                int tid, uint64_t base, uint64_t* gr) {
+  const int m = P->m;
+  uint64_t gt = base;
+  for (int k = 0; k < m - R; ++k)
+    if ((tid >> k) & 1) gt |= 1ull << P->lpos[S->tb[k]];
+#pragma unroll
+  for (int j = 0; j < R; ++j) gr[j] = 1ull << P->lpos[S->rb[j]];
+  return gt;
+}
+
+// First stage of a tile: load a (and b) from HBM, or generate |0...0>.
+template <class T, int R, bool DUAL>
+__device__ __forceinline__ void tile_load(const PassDesc* __restrict__ P, const StageDesc* __restrict__ S0,
+                                          const cpx<T>* __restrict__ A, const cpx<T>* __restrict__ B, uint64_t base,
+                                          TileRegs<T, R, DUAL>& t) {
   constexpr int NR = 1 << R;
-  const int n = P->n, m = P->m, flags = P->flags;
+  const int m = P->m, flags = P->flags;
+  const int tid = threadIdx.x;
+  const bool active = tid < (1 << (m - R));
+  const bool ld_a = (flags & PF_LOAD_A) != 0, ld_b = DUAL && (flags & PF_LOAD_B) != 0;
+  cpx<T> z;
+  z.x = 0;
+  z.y = 0;
+  if (ld_a || ld_b) {
+    uint64_t gr[R];
+    const uint64_t gt = stage_gaddr<R>(P, S0, tid, base, gr);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      uint64_t g = gt;
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if ((i >> j) & 1) g |= gr[j];
+      t.a[i] = (ld_a && active) ? A[g] : z;
+      if constexpr (DUAL) t.b[i] = (ld_b && active) ? B[g] : z;
+    }
+  } else {
+    const uint32_t tl = thread_local_index<R>(S0, m, tid);
+    uint32_t rl[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) rl[j] = 1u << S0->rb[j];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      uint32_t o = tl;
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if ((i >> j) & 1) o |= rl[j];
+      t.a[i] = z;
+      if ((flags & PF_INIT) && active && base == 0 && o == 0u) t.a[i].x = T(1);
+      if constexpr (DUAL) t.b[i] = z;
+    }
+  }
+}
+
+// All stages of a tile whose first-stage registers are loaded: ops, LDS
+// exchanges (with exit permutations), the store, and the block's partial sums.
+template <class T, int R, bool DUAL>
+__device__ __forceinline__ double tile_run(const PassDesc* __restrict__ P, const StageDesc* __restrict__ SD,
+                                           const DevOp* __restrict__ OPS, cpx<T>* __restrict__ A,
+                                           cpx<T>* __restrict__ B, const T* __restrict__ coef, uint64_t base,
+                                           TileRegs<T, R, DUAL>& t, cpx<T>* lds, double* red, double* gacc,
+                                           double* __restrict__ grad_out, int64_t grad_stride) {
+  constexpr int NR = 1 << R;
+  const int m = P->m, flags = P->flags;
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const bool active = tid < (1 << (m - R));
   const int lane = tid & 63, wave = tid >> 6, nwaves = (nthr + 63) >> 6;
   const uint32_t tsize = 1u << m;
-  uint64_t base = 0;
-  for (int k = 0; k < n - m; ++k)
-    if ((tile >> k) & 1) base |= 1ull << P->npos[k];
+  cpx<T>* a = t.a;
+  cpx<T>* b = t.b;
   const int gcount = DUAL ? P->grad_count : 0;
   const int gbegin = DUAL ? P->grad_begin : 0;
   if (DUAL && (flags & PF_GRAD)) {
     for (int k = tid; k < nwaves * gcount; k += nthr) gacc[k] = 0.0;
-    __syncthreads();
+    lds_sync();
   }
-  cpx<T> a[NR];
-  cpx<T> b[DUAL ? NR : 1];
   double acc = 0.0;
   const int s0 = P->stage_begin, s1 = P->stage_end, sst = P->store_stage;
   for (int s = s0; s < s1; ++s) {
     const StageDesc* S = SD + s;
-    uint32_t tl = 0;
-    for (int k = 0; k < m - R; ++k) tl |= ((uint32_t)(tid >> k) & 1u) << S->tb[k];
+    const uint32_t tl = thread_local_index<R>(S, m, tid);
     uint32_t rl[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) rl[j] = 1u << S->rb[j];
@@ -309,36 +397,7 @@ __device__ __forceinline__ double run_tile(const PassDesc* __restrict__ P, const
         if ((i >> j) & 1) o |= rl[j];
       return o;
     };
-    auto gaddr = [&](uint64_t* gr) __attribute__((always_inline)) {  // per-thread global part; per-register parts in gr
-      uint64_t gt = base;
-      for (int k = 0; k < m - R; ++k)
-        if ((tid >> k) & 1) gt |= 1ull << P->lpos[S->tb[k]];
-#pragma unroll
-      for (int j = 0; j < R; ++j) gr[j] = 1ull << P->lpos[S->rb[j]];
-      return gt;
-    };
-    if (s == s0) {
-      const bool ld_a = (flags & PF_LOAD_A) != 0, ld_b = DUAL && (flags & PF_LOAD_B) != 0;
-      uint64_t gr[R];
-      const uint64_t gt = gaddr(gr);
-#pragma unroll
-      for (int i = 0; i < NR; ++i) {
-        uint64_t g = gt;
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-          if ((i >> j) & 1) g |= gr[j];
-        cpx<T> z;
-        z.x = 0;
-        z.y = 0;
-        if (ld_a) {
-          a[i] = active ? A[g] : z;
-        } else {
-          a[i] = z;
-          if ((flags & PF_INIT) && active && base == 0 && (tl | roff(i)) == 0u) a[i].x = T(1);
-        }
-        if constexpr (DUAL) b[i] = (ld_b && active) ? B[g] : z;
-      }
-    } else {
+    if (s != s0) {
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
         cpx<T> z;
@@ -380,8 +439,12 @@ __device__ __forceinline__ double run_tile(const PassDesc* __restrict__ P, const
         ap_cz<T, R>(a, c1, c2);
         if constexpr (DUAL) ap_cz<T, R>(b, c1, c2);
       } else if (type == OP_MEAS_Z) {
+        T p[NR];  // |a_i|^2
+#pragma unroll
+        for (int i = 0; i < NR; ++i) p[i] = a[i].x * a[i].x + a[i].y * a[i].y;
         const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
-        acc += op.c * meas_z<T, R>(a, op.rz, par);
+        const double v = (double)meas_zp<T, R>(p, op.rz);
+        acc += op.c * (par ? -v : v);
       } else if (type == OP_MEAS_F) {
         const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
         for_mask<NR>(op.fr, [&](auto FC) __attribute__((always_inline)) {
@@ -417,7 +480,7 @@ __device__ __forceinline__ double run_tile(const PassDesc* __restrict__ P, const
     if (s == sst) {
       const bool st_a = (flags & PF_STORE_A) != 0, st_b = DUAL && (flags & PF_STORE_B) != 0;
       uint64_t gr[R];
-      const uint64_t gt = gaddr(gr);
+      const uint64_t gt = stage_gaddr<R>(P, S, tid, base, gr);
       if (active) {
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
@@ -433,70 +496,125 @@ __device__ __forceinline__ double run_tile(const PassDesc* __restrict__ P, const
       }
     }
     if (s + 1 < s1) {
-      __syncthreads();
+      lds_sync();
       if (active) {
+        if (S->has_perm) {
+          // write every amplitude to its image under the stage's exit permutation
+          uint32_t w = 0;
+          for (int k = 0; k < m - R; ++k)
+            if ((tid >> k) & 1) w ^= S->tcol[k];
+          for (int j = 0; j < (int)S->n_aff; ++j)
+            if ((base >> S->aff_pos[j]) & 1) w ^= S->aff_mask[j];
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-          const uint32_t l = swz(tl | roff(i));
-          lds[l] = a[i];
-          if constexpr (DUAL) lds[tsize + l] = b[i];
+          for (int i = 0; i < NR; ++i) {
+            const uint32_t l = swz(w ^ (uint32_t)S->preg[i]);
+            lds[l] = a[i];
+            if constexpr (DUAL) lds[tsize + l] = b[i];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < NR; ++i) {
+            const uint32_t l = swz(tl | roff(i));
+            lds[l] = a[i];
+            if constexpr (DUAL) lds[tsize + l] = b[i];
+          }
         }
       }
-      __syncthreads();
+      lds_sync();
     }
   }
   double total = 0.0;
   if (flags & PF_MEASURE) {
     const double v = wave_sum(acc);
     if (lane == 0) red[wave] = v;
-    __syncthreads();
+    lds_sync();
     if (tid == 0)
       for (int w = 0; w < nwaves; ++w) total += red[w];
-    __syncthreads();
+    lds_sync();
   }
   if (DUAL && (flags & PF_GRAD)) {
-    __syncthreads();
+    lds_sync();
     for (int k = tid; k < gcount; k += nthr) {
       double sum = 0.0;
       for (int w = 0; w < nwaves; ++w) sum += gacc[w * gcount + k];
       grad_out[(int64_t)(gbegin + k) * grad_stride] = sum;
     }
-    __syncthreads();
+    lds_sync();
   }
   return total;
 }
 
 constexpr int kRedSlots = 16;
 
-// Threads per workgroup: 2^(m-r).  Single-state complex64 tiles go up to
-// m = 14 (1024 threads); dual-state and complex128 tiles up to m = 13.
-template <class T, bool DUAL>
+// Threads per workgroup: 2^(m-r).  Tiles hold at most 2^14 complex64
+// amplitudes of one state (128 KiB of LDS), 2^13 of two states or of one
+// complex128 state, 2^12 of two complex128 states.
+template <class T, int R, bool DUAL>
 constexpr int pass_max_threads() {
-  return (DUAL || sizeof(T) == 8) ? 512 : 1024;
+  constexpr int mmax = sizeof(T) == 4 ? (DUAL ? 13 : 14) : (DUAL ? 12 : 13);
+  return (1 << (mmax - R)) < 1024 ? (1 << (mmax - R)) : 1024;
 }
 
-template <class T, int R, bool DUAL>
-__global__ __launch_bounds__((pass_max_threads<T, DUAL>())) void k_pass(const PassDesc* __restrict__ P, const StageDesc* __restrict__ SD,
-                                               const DevOp* __restrict__ OPS, cpx<T>* A, cpx<T>* B,
-                                               int64_t row_stride, const T* __restrict__ coef,
-                                               int64_t coef_row_stride, double* meas, int n_meas, double* grad,
-                                               int n_gslots) {
+// Dense pass over rows x 2^(n-m) tiles.  Workgroups are persistent: each one
+// walks tiles w, w + gridDim.x, ...  With PF, it issues the HBM loads of its
+// next tile before working on the current one, so the loads overlap the
+// register and LDS work (a 2^14-amplitude tile fills a CU's LDS, leaving no
+// second workgroup to overlap with); this needs twice the data registers.
+template <class T, int R, bool DUAL, bool PF>
+__global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass(
+    const PassDesc* __restrict__ P, const StageDesc* __restrict__ SD, const DevOp* __restrict__ OPS, cpx<T>* A,
+    cpx<T>* B, int64_t row_stride, const T* __restrict__ coef, int64_t coef_row_stride, double* meas, int n_meas,
+    double* grad, int n_gslots, int64_t rows) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int m = P->m;
+  const int m = P->m, sh = P->n - m;
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
   double* red = reinterpret_cast<double*>(smem + ((size_t)(DUAL ? 2 : 1) * sizeof(cpx<T>) << m));
   double* gacc = red + kRedSlots;
-  const uint64_t tile = blockIdx.x;
-  const int64_t tiles = gridDim.x;
-  const int64_t row = blockIdx.y;
-  double* gout = (DUAL && grad) ? grad + row * n_gslots * tiles + (int64_t)tile : nullptr;
-  const double v = run_tile<T, R, DUAL>(P, SD, OPS, A + row * row_stride, DUAL ? B + row * row_stride : nullptr,
-                                        coef + row * coef_row_stride, tile, lds, red, gacc, gout, tiles);
-  if ((P->flags & PF_MEASURE) && threadIdx.x == 0) meas[(row * n_meas + P->meas_index) * tiles + (int64_t)tile] = v;
+  const int64_t tiles = 1ll << sh;
+  const int64_t total = tiles * rows;
+  const StageDesc* S0 = SD + P->stage_begin;
+  int64_t w = blockIdx.x;
+  if (w >= total) return;
+  TileRegs<T, R, DUAL> cur;
+  int64_t row = w >> sh;
+  uint64_t tile = (uint64_t)(w & (tiles - 1));
+  uint64_t base = tile_base(P, tile);
+  tile_load<T, R, DUAL>(P, S0, A + row * row_stride, DUAL ? B + row * row_stride : nullptr, base, cur);
+  while (true) {
+    const int64_t wn = w + gridDim.x;
+    const bool more = wn < total;
+    const int64_t rown = wn >> sh;
+    const uint64_t tilen = (uint64_t)(wn & (tiles - 1));
+    const uint64_t basen = more ? tile_base(P, tilen) : 0;
+    if constexpr (PF) {
+      TileRegs<T, R, DUAL> nxt;
+      if (more)
+        tile_load<T, R, DUAL>(P, S0, A + rown * row_stride, DUAL ? B + rown * row_stride : nullptr, basen, nxt);
+      double* gout = (DUAL && grad) ? grad + row * n_gslots * tiles + (int64_t)tile : nullptr;
+      const double v = tile_run<T, R, DUAL>(P, SD, OPS, A + row * row_stride, DUAL ? B + row * row_stride : nullptr,
+                                            coef + row * coef_row_stride, base, cur, lds, red, gacc, gout, tiles);
+      if ((P->flags & PF_MEASURE) && threadIdx.x == 0)
+        meas[(row * n_meas + P->meas_index) * tiles + (int64_t)tile] = v;
+      if (!more) break;
+      cur = nxt;
+    } else {
+      double* gout = (DUAL && grad) ? grad + row * n_gslots * tiles + (int64_t)tile : nullptr;
+      const double v = tile_run<T, R, DUAL>(P, SD, OPS, A + row * row_stride, DUAL ? B + row * row_stride : nullptr,
+                                            coef + row * coef_row_stride, base, cur, lds, red, gacc, gout, tiles);
+      if ((P->flags & PF_MEASURE) && threadIdx.x == 0)
+        meas[(row * n_meas + P->meas_index) * tiles + (int64_t)tile] = v;
+      if (!more) break;
+      tile_load<T, R, DUAL>(P, S0, A + rown * row_stride, DUAL ? B + rown * row_stride : nullptr, basen, cur);
+    }
+    w = wn;
+    row = rown;
+    tile = tilen;
+    base = basen;
+  }
 }
 
 template <class T, int R, bool DUAL>
-__global__ __launch_bounds__((pass_max_threads<T, DUAL>())) void k_pass_multi(const PassItem* __restrict__ items,
+__global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass_multi(const PassItem* __restrict__ items,
                                                                              int n_items, int m_max) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
@@ -513,30 +631,38 @@ __global__ __launch_bounds__((pass_max_threads<T, DUAL>())) void k_pass_multi(co
   const PassDesc* P = it.pass;
   const int64_t tiles = 1ll << (P->n - P->m);
   const uint64_t tile = (uint64_t)(b - it.tile_begin);
+  const uint64_t base = tile_base(P, tile);
   double* gout = (DUAL && it.grad) ? it.grad + (int64_t)tile : nullptr;
-  const double v = run_tile<T, R, DUAL>(P, it.stages, it.ops, reinterpret_cast<cpx<T>*>(it.A),
-                                        reinterpret_cast<cpx<T>*>(it.B), reinterpret_cast<const T*>(it.coef), tile,
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(it.A);
+  cpx<T>* B = reinterpret_cast<cpx<T>*>(it.B);
+  TileRegs<T, R, DUAL> t;
+  tile_load<T, R, DUAL>(P, it.stages + P->stage_begin, A, B, base, t);
+  const double v = tile_run<T, R, DUAL>(P, it.stages, it.ops, A, B, reinterpret_cast<const T*>(it.coef), base, t,
                                         lds, red, gacc, gout, tiles);
   if ((P->flags & PF_MEASURE) && threadIdx.x == 0) it.meas[(int64_t)P->meas_index * tiles + (int64_t)tile] = v;
 }
 
 template <class T, int R>
-__global__ __launch_bounds__((pass_max_threads<T, false>())) void k_cones(const ConeDesc* __restrict__ cones, const int32_t* __restrict__ order,
-                                                const PassDesc* __restrict__ P, const StageDesc* __restrict__ SD,
-                                                const DevOp* __restrict__ OPS, cpx<T>* scratch,
-                                                const T* __restrict__ coef, double* out, int m_max) {
+__global__ __launch_bounds__((pass_max_threads<T, R, false>())) void k_cones(
+    const ConeDesc* __restrict__ cones, const int32_t* __restrict__ order, const PassDesc* __restrict__ P,
+    const StageDesc* __restrict__ SD, const DevOp* __restrict__ OPS, cpx<T>* scratch, const T* __restrict__ coef,
+    double* out, int m_max) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
   double* red = reinterpret_cast<double*>(smem + (sizeof(cpx<T>) << m_max));
   const ConeDesc cd = cones[order[blockIdx.x]];
   double total = 0.0;
+  cpx<T>* st = scratch + cd.scratch_off;
+  const T* cf = coef + (int64_t)cd.coef_begin * 8;
   for (int p = cd.pass_begin; p < cd.pass_end; ++p) {
     const PassDesc* pp = P + p;
     const int64_t tiles = 1ll << (pp->n - pp->m);
     for (int64_t t = 0; t < tiles; ++t) {
-      total += run_tile<T, R, false>(pp, SD, OPS, scratch + cd.scratch_off, nullptr,
-                                     coef + (int64_t)cd.coef_begin * 8, (uint64_t)t, lds, red, nullptr, nullptr, 0);
-      __syncthreads();
+      const uint64_t base = tile_base(pp, (uint64_t)t);
+      TileRegs<T, R, false> regs;
+      tile_load<T, R, false>(pp, SD + pp->stage_begin, st, nullptr, base, regs);
+      total += tile_run<T, R, false>(pp, SD, OPS, st, nullptr, cf, base, regs, lds, red, nullptr, nullptr, 0);
+      lds_sync();
     }
     // the next pass reads what other waves of this workgroup stored
     __threadfence();
@@ -580,28 +706,50 @@ hipError_t allow_lds(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
-template <class T, int R, bool DUAL>
+int device_cus() {
+  static int cus = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || v <= 0)
+      v = 256;
+    return v;
+  }();
+  return cus;
+}
+
+template <class T, int R, bool DUAL, bool PF>
 hipError_t launch_pass_t(const PassLaunch& L, hipStream_t stream) {
   const int m = L.h_pass->m, n = L.h_pass->n;
   const size_t lds = pass_lds_bytes(m, sizeof(T) == 8, DUAL);
-  auto kern = k_pass<T, R, DUAL>;
+  auto kern = k_pass<T, R, DUAL, PF>;
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = std::max(64, 1 << (m - R));
-  dim3 grid((unsigned)(1ull << (n - m)), (unsigned)L.rows);
-  hipLaunchKernelGGL(kern, grid, dim3(threads), lds, stream, L.d_pass, L.d_stages, L.d_ops,
+  // persistent workgroups: as many as fit on the device at once (LDS and thread limits)
+  const int per_cu = std::max(1, std::min((int)((size_t)max_lds_bytes() / lds), 2048 / threads));
+  const int64_t total = (int64_t)L.rows << (n - m);
+  const int64_t grid = std::min<int64_t>(total, (int64_t)device_cus() * per_cu);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, stream, L.d_pass, L.d_stages, L.d_ops,
                      reinterpret_cast<cpx<T>*>(L.A), reinterpret_cast<cpx<T>*>(L.B), L.row_stride,
-                     reinterpret_cast<const T*>(L.coef), L.coef_row_stride, L.meas, L.n_meas, L.grad, L.n_gslots);
+                     reinterpret_cast<const T*>(L.coef), L.coef_row_stride, L.meas, L.n_meas, L.grad, L.n_gslots,
+                     (int64_t)L.rows);
   return hipGetLastError();
 }
 
+// Register bits per thread by precision and kind; the 32-register complex64
+// single-state variant prefetches (its 512 threads leave 256 VGPRs each).
 template <class T, bool DUAL>
 hipError_t launch_pass_r(const PassLaunch& L, hipStream_t stream) {
   switch (L.h_pass->r) {
-    case 1: return launch_pass_t<T, 1, DUAL>(L, stream);
-    case 2: return launch_pass_t<T, 2, DUAL>(L, stream);
-    case 3: return launch_pass_t<T, 3, DUAL>(L, stream);
-    case 4: return launch_pass_t<T, 4, DUAL>(L, stream);
+    case 1: return launch_pass_t<T, 1, DUAL, false>(L, stream);
+    case 2: return launch_pass_t<T, 2, DUAL, false>(L, stream);
+    case 3: return launch_pass_t<T, 3, DUAL, false>(L, stream);
+    case 4:
+      if constexpr (DUAL && sizeof(T) == 8) return hipErrorInvalidValue;
+      else return launch_pass_t<T, 4, DUAL, DUAL && sizeof(T) == 4>(L, stream);
+    case 5:
+      if constexpr (DUAL || sizeof(T) == 8) return hipErrorInvalidValue;
+      else return launch_pass_t<T, 5, false, true>(L, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -635,9 +783,11 @@ hipError_t launch_multi_t(const PassItem* items, int n_items, int64_t total, int
 hipError_t launch_pass_multi(const PassItem* d_items, int n_items, int64_t total_tiles, int m_max, int r, int c128,
                              int dual, hipStream_t stream) {
   if (n_items == 0) return hipSuccess;
-  if (r != 4 || c128) return hipErrorInvalidValue;  // serving runs complex64 with 16 registers per thread
-  return dual ? launch_multi_t<float, 4, true>(d_items, n_items, total_tiles, m_max, stream)
-              : launch_multi_t<float, 4, false>(d_items, n_items, total_tiles, m_max, stream);
+  if (c128) return hipErrorInvalidValue;  // serving runs complex64
+  if (dual && r == 4) return launch_multi_t<float, 4, true>(d_items, n_items, total_tiles, m_max, stream);
+  if (!dual && r == 4) return launch_multi_t<float, 4, false>(d_items, n_items, total_tiles, m_max, stream);
+  if (!dual && r == 5) return launch_multi_t<float, 5, false>(d_items, n_items, total_tiles, m_max, stream);
+  return hipErrorInvalidValue;
 }
 
 size_t pass_lds_bytes(int m, int c128, int dual) {

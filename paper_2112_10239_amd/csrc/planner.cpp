@@ -268,7 +268,23 @@ uint64_t grow_candidate(const std::vector<PGate>& G, const std::vector<int>& pen
 struct StageBuild {
   std::vector<int> rb;  // local indices
   std::vector<const PGate*> items;
+  std::vector<const PGate*> perm;  // CNOTs applied as the stage's exit permutation, in order
 };
+
+// Relative costs used to choose between stage layouts (one LDS exchange of the
+// tile versus register ops), in units of one general 2x2 op.
+constexpr double kCostExchange = 2.0;
+double op_cost(const PGate& g) {
+  switch (g.kind) {
+    case PG_U: return 1.0;
+    case PG_RY: return 0.6;
+    case PG_X: return 0.5;
+    case PG_PHASE: return 0.6;
+    case PG_CZ: return 0.3;
+    case PG_GRAD: return 0.6;
+    default: return 0.3;
+  }
+}
 
 bool rb_has(const std::vector<int>& rb, int k) { return std::find(rb.begin(), rb.end(), k) != rb.end(); }
 
@@ -313,6 +329,8 @@ struct PassEmitter {
   int n, m, r;
   std::vector<int> L;     // physical qubits, ascending
   std::vector<int> lidx;  // physical -> local index (-1 = non-local)
+
+  bool allow_absorb = true;
 
   PassEmitter(Plan& p, int n_, int m_, int r_, uint64_t Lmask) : plan(p), n(n_), m(m_), r(r_), lidx(n_, -1) {
     for (int q = 0; q < n; ++q)
@@ -409,28 +427,35 @@ struct PassEmitter {
     return op;
   }
 
-  // Emits one pass.  'mod' items modify the state(s) and keep their order;
-  // 'ro' items are read-only terms measured after all of 'mod'.
-  void emit(const std::vector<const PGate*>& mod, const std::vector<const PGate*>& ro, int flags,
-            int c_low, int src_pass_index) {
-    const bool loads = flags & (PF_LOAD_A | PF_LOAD_B);
-    const bool stores = flags & (PF_STORE_A | PF_STORE_B);
+  // Splits the pass's items into stages.  With 'absorb', a CNOT whose qubits
+  // no earlier item of the stage still needs is taken out of the op stream
+  // and applied as part of the stage's exit permutation; later items on its
+  // qubits move to the next stage.
+  std::vector<StageBuild> build_stages(const std::vector<const PGate*>& mod, const std::vector<const PGate*>& ro,
+                                       bool loads, bool stores, int c_low, bool absorb, int& store_rel) const {
     const int lo_load = loads ? c_low : 0;
     const int lo_store = stores ? c_low : 0;
-
     std::vector<StageBuild> sb;
     std::vector<const PGate*> pending = mod;
     bool first = true;
     while (!pending.empty()) {
       StageBuild s;
-      std::vector<char> blocked(n, 0);
+      std::vector<char> blocked(n, 0), permuted(n, 0);
       std::vector<const PGate*> rest;
       for (const PGate* g : pending) {
         int qs[2];
         const int k = order_qubits(*g, qs);
-        bool b = false;
-        for (int t = 0; t < k; ++t) b |= blocked[qs[t]] != 0;
-        if (!b && try_place(*g, s.rb, r, first ? lo_load : 0, lidx)) {
+        bool b = false, pt = false;
+        for (int t = 0; t < k; ++t) {
+          b |= blocked[qs[t]] != 0;
+          pt |= permuted[qs[t]] != 0;
+        }
+        if (!b && absorb && g->kind == PG_X) {
+          s.perm.push_back(g);
+          for (int t = 0; t < k; ++t) permuted[qs[t]] = 1;
+          continue;
+        }
+        if (!b && !pt && try_place(*g, s.rb, r, first ? lo_load : 0, lidx)) {
           s.items.push_back(g);
         } else {
           for (int t = 0; t < k; ++t) blocked[qs[t]] = 1;
@@ -447,7 +472,13 @@ struct PassEmitter {
       fill_rb(s.rb, r, m, lo_load);
       sb.push_back(std::move(s));
     }
-    int store_rel = -1;
+    // a permutation is realised at an exchange: give the last one a stage to land in
+    if (!sb.back().perm.empty()) {
+      StageBuild s;
+      fill_rb(s.rb, r, m, lo_store);
+      sb.push_back(std::move(s));
+    }
+    store_rel = -1;
     if (stores) {
       bool ok = true;
       for (int k : sb.back().rb) ok &= k >= lo_store;
@@ -475,6 +506,90 @@ struct PassEmitter {
       fill_rb(s.rb, r, m, 0);
       sb.push_back(std::move(s));
       left.swap(rest);
+    }
+    return sb;
+  }
+
+  static double stages_cost(const std::vector<StageBuild>& sb) {
+    double c = kCostExchange * (double)(sb.size() - 1);
+    for (const StageBuild& s : sb)
+      for (const PGate* g : s.items) c += op_cost(*g);
+    return c;
+  }
+
+  // Fill the exit permutation of a stage from its CNOT run.
+  void fill_perm(const StageBuild& s, StageDesc& st) const {
+    st.has_perm = 0;
+    st.n_aff = 0;
+    // identity images by default (used when has_perm == 0 only for clarity)
+    std::vector<uint32_t> col(m);
+    for (int k = 0; k < m; ++k) col[k] = 1u << k;
+    std::vector<std::pair<int, uint32_t>> aff;  // (physical non-local bit, image mask)
+    auto lbit = [&](uint32_t v, int c) { return (v >> c) & 1u; };
+    for (const PGate* g : s.perm) {
+      const int t = lidx[g->q];     // target is local
+      const int cq = g->q2;         // control: local or non-local
+      const int c = lidx[cq];
+      for (int k = 0; k < m; ++k)
+        if (c >= 0 && lbit(col[k], c)) col[k] ^= 1u << t;
+      for (auto& a : aff)
+        if (c >= 0 && lbit(a.second, c)) a.second ^= 1u << t;
+      if (c < 0) {
+        bool found = false;
+        for (auto& a : aff)
+          if (a.first == cq) {
+            a.second ^= 1u << t;
+            found = true;
+          }
+        if (!found) aff.push_back({cq, 1u << t});
+      }
+    }
+    if (s.perm.empty()) return;
+    st.has_perm = 1;
+    int t = 0;
+    for (int k = 0; k < m; ++k)
+      if (!rb_has(s.rb, k)) st.tcol[t++] = (uint16_t)col[k];
+    for (int i = 0; i < (1 << r); ++i) {
+      uint32_t v = 0;
+      for (int j = 0; j < r; ++j)
+        if ((i >> j) & 1) v ^= col[s.rb[j]];
+      st.preg[i] = (uint16_t)v;
+    }
+    for (auto& a : aff)
+      if (a.second) {
+        st.aff_pos[st.n_aff] = (uint8_t)a.first;
+        st.aff_mask[st.n_aff] = (uint16_t)a.second;
+        ++st.n_aff;
+      }
+  }
+
+  // Emits one pass.  'mod' items modify the state(s) and keep their order;
+  // 'ro' items are read-only terms measured after all of 'mod'.
+  void emit(const std::vector<const PGate*>& mod, const std::vector<const PGate*>& ro, int flags,
+            int c_low, int src_pass_index) {
+    const bool loads = flags & (PF_LOAD_A | PF_LOAD_B);
+    const bool stores = flags & (PF_STORE_A | PF_STORE_B);
+    int store_rel = -1, store_rel2 = -1;
+    std::vector<StageBuild> sb = build_stages(mod, ro, loads, stores, c_low, false, store_rel);
+    bool can_absorb = allow_absorb && m <= 16;
+    for (const PGate* g : mod)
+      if (g->kind == PG_X && lidx[g->q2] < 0) {
+        int na = 0;  // count distinct non-local controls (affine terms)
+        std::vector<int> seen;
+        for (const PGate* h : mod)
+          if (h->kind == PG_X && lidx[h->q2] < 0 && std::find(seen.begin(), seen.end(), h->q2) == seen.end()) {
+            seen.push_back(h->q2);
+            ++na;
+          }
+        can_absorb &= na <= kMaxAffine;
+        break;
+      }
+    if (can_absorb) {
+      std::vector<StageBuild> sb2 = build_stages(mod, ro, loads, stores, c_low, true, store_rel2);
+      if (stages_cost(sb2) < stages_cost(sb)) {
+        sb.swap(sb2);
+        store_rel = store_rel2;
+      }
     }
 
     PassDesc pd;
@@ -524,6 +639,14 @@ struct PassEmitter {
         plan.ops.push_back(op);
       }
       st.op_end = (int)plan.ops.size();
+      fill_perm(sb[si], st);
+      for (const PGate* g : sb[si].perm)
+        for (int src : g->srcs) {
+          plan.order.push_back(pass_no);
+          plan.order.push_back(si);
+          plan.order.push_back(st.op_end - st.op_begin);  // after the stage's ops
+          plan.order.push_back(src);
+        }
       plan.stages.push_back(st);
     }
     pd.stage_end = (int)plan.stages.size();
@@ -652,6 +775,7 @@ int plan_forward(int n, const std::vector<PGate>& gates, const std::vector<PGate
     const bool last = p == np - 1;
     if (!last || o.store_final || !mLs.empty()) flags |= PF_STORE_A;
     PassEmitter em(plan, n, m, r, Ls[p]);
+    em.allow_absorb = o.absorb;
     std::vector<const PGate*> mod;
     for (int idx : lists[p]) mod.push_back(&gates[idx]);
     em.emit(mod, last ? fin : std::vector<const PGate*>{}, flags, c_low, p);
@@ -716,6 +840,7 @@ int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, P
     int flags = PF_LOAD_A | PF_LOAD_B;
     if (p != np - 1) flags |= PF_STORE_A | PF_STORE_B;
     PassEmitter em(plan, n, m, r, Ls[p]);
+    em.allow_absorb = o.absorb;
     std::vector<const PGate*> mod;
     for (int idx : lists[p]) mod.push_back(&gates[idx]);
     em.emit(mod, {}, flags, c_low, p);

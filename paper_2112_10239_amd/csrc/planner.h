@@ -70,6 +70,7 @@ struct PlanOptions {
   bool store_final = true;  // keep the final state in HBM
   bool fuse = true;     // fuse runs of single-qubit gates on one qubit
   int max_grad = kMaxGradPerPass;  // gradient probes per pass
+  bool absorb = true;   // allow CNOT runs as stage exit permutations
 };
 
 // Validation; returns "" when fine.

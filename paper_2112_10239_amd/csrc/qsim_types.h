@@ -57,12 +57,24 @@ constexpr int kMaxLocal = 16;
 constexpr int kMaxQubits = 40;
 constexpr int kMaxGradPerPass = 128;
 
+constexpr int kMaxRegBits = 5;
+constexpr int kMaxAffine = 8;
+
+// A stage may end with a permutation of the tile: a run of CNOTs whose
+// qubits are local (controls may also be non-local index bits) is a GF(2)
+// affine map l -> M l + b(tile) on the local index, applied by writing each
+// amplitude to its image in LDS at the exchange that ends the stage.
 struct StageDesc {
   int32_t op_begin, op_end;
-  uint8_t rb[8];          // register bits as local indices
-  uint8_t tb[kMaxLocal];  // thread bits as local indices, ascending (m - r used)
+  uint8_t rb[8];            // register bits as local indices
+  uint8_t tb[kMaxLocal];    // thread bits as local indices, ascending (m - r used)
+  uint16_t has_perm, n_aff; // exit permutation present; affine terms used
+  uint16_t tcol[kMaxLocal]; // M applied to thread bit k
+  uint16_t preg[1 << kMaxRegBits];  // M applied to register offset i
+  uint8_t aff_pos[kMaxAffine];      // physical non-local bit of affine term j
+  uint16_t aff_mask[kMaxAffine];    // xor into the image when that bit is 1
 };
-static_assert(sizeof(StageDesc) == 32, "StageDesc layout");
+static_assert(sizeof(StageDesc) == 156, "StageDesc layout");
 
 enum PassFlags : int32_t {
   PF_INIT = 1,      // first stage generates |0...0> instead of loading a

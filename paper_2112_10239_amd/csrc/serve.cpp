@@ -152,8 +152,8 @@ int Server::submit(const qsim_request* rq, uint64_t* ticket) {
   int rc = to_circuit(ctx_, rq->circuit, r->c);
   if (rc) return rc;
   if ((rc = to_terms(ctx_, rq->H, r->c.n, r->terms))) return rc;
-  if (r->c.n > 30 || r->c.n < 4) {
-    set_error(ctx_, "serving takes dense requests of 4 to 30 qubits");
+  if (r->c.n > 30 || r->c.n < 6) {
+    set_error(ctx_, "serving takes dense requests of 6 to 30 qubits");
     return QSIM_EINVAL;
   }
   if (r->c.n_params > 0 && !rq->params) {
@@ -306,7 +306,7 @@ void Server::release(SReq* r) {
 bool Server::step(std::vector<SReq*>& run) {
   std::vector<PassItem> single, dual;
   int64_t tiles_s = 0, tiles_d = 0;
-  int m_s = 4, m_d = 4;
+  int m_s = 4, m_d = 4, r_s = 0, r_d = 0;
   for (SReq* r : run) {
     r->ended = -1;
     if (r->failed || r->cancelled || r->phase == PH_DONE) continue;
@@ -327,11 +327,13 @@ bool Server::step(std::vector<SReq*>& run) {
       it.tile_begin = tiles_s;
       tiles_s += tiles;
       m_s = std::max(m_s, P.m);
+      r_s = P.r;
       single.push_back(it);
     } else {
       it.tile_begin = tiles_d;
       tiles_d += tiles;
       m_d = std::max(m_d, P.m);
+      r_d = P.r;
       dual.push_back(it);
     }
     r->passes_done++;
@@ -348,8 +350,8 @@ bool Server::step(std::vector<SReq*>& run) {
   std::memcpy(ws_.h_out.p, items_.data(), bytes);
   if (hipMemcpyAsync(d_items_.p, ws_.h_out.p, bytes, hipMemcpyHostToDevice, stream_) != hipSuccess) return false;
   const PassItem* d = reinterpret_cast<const PassItem*>(d_items_.p);
-  if (launch_pass_multi(d, (int)single.size(), tiles_s, m_s, 4, 0, 0, stream_) != hipSuccess) return false;
-  if (launch_pass_multi(d + single.size(), (int)dual.size(), tiles_d, m_d, 4, 0, 1, stream_) != hipSuccess)
+  if (launch_pass_multi(d, (int)single.size(), tiles_s, m_s, r_s, 0, 0, stream_) != hipSuccess) return false;
+  if (launch_pass_multi(d + single.size(), (int)dual.size(), tiles_d, m_d, r_d, 0, 1, stream_) != hipSuccess)
     return false;
   st_.launches += (single.empty() ? 0 : 1) + (dual.empty() ? 0 : 1);
   // reductions of requests whose phase ended in this step
