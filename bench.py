@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -162,6 +164,109 @@ def bench_small(Q, W, reps=200):
                 evals_per_s=reps / (t1 - t0))
 
 
+def _serving_trace(W, Q, rate, duration, seed_offset=0):
+    """Requests of the serving stream with Poisson arrival times, marshalled ahead of time."""
+    arr = W.poisson_arrivals(rate, duration, seed=(5, 3 + seed_offset))
+    reqs = [W.serving_request(r + 100000 * seed_offset, a) for r, a in enumerate(arr)]
+    prep = [(Q.qsim.CCircuit.of(r.circuit), Q.qsim.CHamiltonian.of(r.H), np.ascontiguousarray(r.theta), r.want_grad)
+            for r in reqs]
+    return reqs, prep
+
+
+def _serve_run(Q, reqs, prep, budget, max_queue):
+    """Open-loop run through the continuous-batching server; latency = completion - scheduled arrival."""
+    ctx = Q.Context(0, hbm_budget_bytes=budget, max_queue=max_queue)
+    # warm the plan cache and the device pool with one request per (n, depth) shape
+    seen = {}
+    for r, p in zip(reqs, prep):
+        if (r.n, r.depth, r.want_grad) not in seen:
+            seen[(r.n, r.depth, r.want_grad)] = ctx.submit_prepared(*p)
+    for t in seen.values():
+        while ctx.poll(t)[0] == 1:
+            time.sleep(0.0005)
+    t0 = Q.qsim.clock() + 0.05
+    pending = {}
+    rejected = 0
+    lat, done_t = [], []
+    i = 0
+    nreq = len(reqs)
+    while i < nreq or pending:
+        now = Q.qsim.clock()
+        while i < nreq and t0 + reqs[i].arrival_s <= now:
+            try:
+                tk = ctx.submit_prepared(*prep[i])
+                pending[tk] = t0 + reqs[i].arrival_s
+            except Q.QsimError as e:
+                if e.code != Q.qsim.EAGAIN:
+                    raise
+                rejected += 1
+            i += 1
+        for tk in list(pending.keys())[:256]:
+            st, E, g, ts = ctx.poll_timed(tk)
+            if st == 1:
+                continue
+            if st == 0:
+                lat.append(ts[2] - pending[tk])
+                done_t.append(ts[2])
+            del pending[tk]
+        if i < nreq:
+            time.sleep(max(0.0, min(0.0005, t0 + reqs[i].arrival_s - Q.qsim.clock())))
+    stats = ctx.server_stats()
+    ctx.close()
+    lat = np.asarray(lat)
+    span = (max(done_t) - t0) if done_t else float("nan")
+    return dict(offered=nreq, completed=int(lat.size), rejected_eagain=rejected,
+                achieved_per_s=lat.size / span if done_t else 0.0,
+                p50_ms=float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+                p99_ms=float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+                steps=stats["steps"], launches=stats["launches"],
+                peak_inflight_GiB=stats["peak_inflight_bytes"] / 2**30)
+
+
+def _plain_run(Q, reqs, max_requests):
+    """The same trace one request at a time (submit, wait, next) through the synchronous calls."""
+    ctx = Q.Context(0)
+    svc = []
+    for r in reqs[:max_requests]:
+        t = time.perf_counter()
+        if r.want_grad:
+            ctx.expect_grad(r.circuit, r.H, r.theta)
+        else:
+            ctx.expect_circuit(r.circuit, r.H, r.theta, mode=Q.MODE_DENSE)
+        svc.append(time.perf_counter() - t)
+    ctx.close()
+    svc = np.asarray(svc)
+    # FIFO single server on the recorded service times and the scheduled arrivals
+    arr = np.asarray([r.arrival_s for r in reqs[:max_requests]])
+    fin = np.zeros_like(arr)
+    t = 0.0
+    for k in range(len(arr)):
+        t = max(t, arr[k]) + svc[k]
+        fin[k] = t
+    lat = fin - arr
+    return dict(requests=len(svc), capacity_per_s=len(svc) / svc.sum(), mean_service_ms=float(svc.mean() * 1e3),
+                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3))
+
+
+def bench_serving(Q, W, duration, rate=2000.0, plain_cap=400):
+    log(f"[serving] generating {rate:.0f}/s x {duration:.1f} s")
+    reqs, prep = _serving_trace(W, Q, rate, duration)
+    budget = 64 << 30
+    served = _serve_run(Q, reqs, prep, budget, 4096)
+    log(f"[serving] served {served['completed']}/{served['offered']}; plain path on {plain_cap}")
+    plain = _plain_run(Q, reqs, plain_cap)
+    out = dict(workload=f"Poisson {rate:.0f} req/s for {duration:.1f} s; n~U{{12..28}}, depth~U{{4..16}}, "
+                        "RY+CZ brickwork MaxCut, 50% with gradient; complex64; 64 GiB budget",
+               served=served, plain=plain)
+    half = 0.5 * served["achieved_per_s"]
+    if half > 1:
+        log(f"[serving] second run at {half:.0f}/s")
+        reqs2, prep2 = _serving_trace(W, Q, half, min(max(duration, 2.0), 2000.0 / half), seed_offset=1)
+        out["served_at_half_capacity"] = dict(rate=half, **_serve_run(Q, reqs2, prep2, budget, 4096))
+        out["plain_at_half_capacity"] = _plain_run(Q, reqs2, min(plain_cap, len(reqs2)))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,7 +274,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--serving", type=float, default=0.0, help="seconds of Poisson arrivals for the serving run")
+    ap.add_argument("--serving", type=float, default=1.0, help="seconds of Poisson arrivals (0 = skip serving)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported by this build "
@@ -203,9 +308,7 @@ def main():
         line["extras"] = {"lightcone": bench_lightcone(Q, W), "gradient": bench_grad(Q, W),
                           "small_c128": bench_small(Q, W)}
     if args.serving > 0:
-        import serve_bench
-
-        line.setdefault("extras", {})["serving"] = serve_bench.run(Q, W, args.serving)
+        line.setdefault("extras", {})["serving"] = bench_serving(Q, W, args.serving)
     print(json.dumps(line), flush=True)
 
 

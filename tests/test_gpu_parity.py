@@ -341,3 +341,18 @@ def test_serving_alone_equals_mix(Q, eng, oracle_mod):
             idx = np.arange(0, r.circuit.n_params, max(1, r.circuit.n_params // 6), dtype=np.int32)
             psr = oracle_mod.grad_psr(r.circuit, r.H, r.theta, idx)
             np.testing.assert_allclose(res[r.rid][1][idx], psr, atol=tol(r.H, 0))
+
+
+def test_ring_maxcut_golden_fixture(Q, eng):
+    """The library against the stored oracle fixture (complex128 energy and shift-rule gradient)."""
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "ring_maxcut_n10_d4.json")) as f:
+        gold = json.load(f)
+    w = W.small_ring_maxcut()
+    E = eng.expect_circuit(w.circuit, w.H, w.theta, mode=Q.MODE_DENSE, dtype=Q.C128)
+    assert abs(E - gold["E"]) <= TOL128 * 15
+    E2, g = eng.expect_grad(w.circuit, w.H, w.theta, dtype=Q.C128)
+    assert abs(E2 - gold["E"]) <= TOL128 * 15
+    np.testing.assert_allclose(g, gold["grad_psr"], atol=TOL128 * 15)

@@ -348,3 +348,16 @@ def test_invalid_inputs_rejected(oracle_mod):
         oracle_mod.expect(c, one([(1.0, [(5, "Z")])]), [0.1])
     with pytest.raises(ValueError):
         oracle_mod.expect(c, one([(1.0, [(0, "Z"), (0, "X")])]), [0.1])
+
+
+def test_golden_ring_maxcut_regenerates(oracle_mod):
+    """The stored fixture matches what the oracle computes now (guards silent oracle changes)."""
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "ring_maxcut_n10_d4.json")) as f:
+        gold = json.load(f)
+    w = W.small_ring_maxcut()
+    assert w.edges.tolist() == gold["edges"]
+    assert oracle_mod.expect(w.circuit, w.H, w.theta) == pytest.approx(gold["E"], abs=1e-13)
+    np.testing.assert_allclose(oracle_mod.grad_psr(w.circuit, w.H, w.theta), gold["grad_psr"], atol=1e-12)
