@@ -81,18 +81,30 @@ def bench_dense(Q, W, steps, warmup):
     dense = rec["kind"] == 0
     ms = rec["ms"][dense]
     by = rec["bytes"][dense]
+    fl = rec["flops"][dense]
     launches = len(ms)
     avg_ms = float(ms.sum() / launches)
     avg_bytes = float(by.sum() / launches)
-    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    avg_flops = float(fl.sum() / launches)
+    gbs = avg_bytes / (avg_ms * 1e-3) / 1e9
+    tflops = avg_flops / (avg_ms * 1e-3) / 1e12
     gate = (rec["flags"][dense] & 6) == 6  # passes that load and store the state
     gate_gbs = float(by[gate].sum() / (ms[gate].sum() * 1e-3) / 1e9) if gate.any() else None
-    return dict(value=steps / (t1 - t0), ms_per_step=(t1 - t0) / steps * 1e3, E=E, plan=info,
-                roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                              frac=achieved / HBM_PEAK_GBS, traffic=load_traffic("dense_pass_n30"),
-                              kernel="k_pass<float, 4, false>", launches_per_step=launches / steps,
-                              avg_launch_ms=avg_ms, algorithmic_bytes_per_launch=avg_bytes,
-                              load_store_passes_GBs=gate_gbs))
+    ctx = Q.Context(0)
+    copy_ms = ctx.copy_probe(8 << 30, reps=3)
+    ctx.close()
+    copy_gbs = 2 * (8 << 30) / (copy_ms * 1e-3) / 1e9
+    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tflops / FP32_PEAK_TFLOPS
+    # report the roof the kernel is closer to
+    if hbm_frac >= alu_frac:
+        roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm_frac)
+    else:
+        roof = dict(bound="alu", achieved=tflops, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=alu_frac)
+    roof.update(traffic=load_traffic("dense_pass_n30"), kernel="k_pass<float, 5, false, true>",
+                launches_per_step=launches / steps, avg_launch_ms=avg_ms, algorithmic_bytes_per_launch=avg_bytes,
+                algorithmic_flops_per_launch=avg_flops, hbm_GBs=gbs, hbm_frac=hbm_frac, alu_TFLOPs=tflops,
+                alu_frac=alu_frac, load_store_passes_GBs=gate_gbs, copy_kernel_GBs=copy_gbs)
+    return dict(value=steps / (t1 - t0), ms_per_step=(t1 - t0) / steps * 1e3, E=E, plan=info, roofline=roof)
 
 
 def cpu_baseline(W, n_sample=23):

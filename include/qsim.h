@@ -180,11 +180,20 @@ int qsim_plan_dense(const qsim_circuit* c, const qsim_hamiltonian* H, int dtype,
 int qsim_timing_enable(qsim_ctx* ctx, int on);
 /* Copy up to cap records of launches finished so far: ms[i] = kernel time in
  * milliseconds, bytes[i] = algorithmic HBM bytes of that launch (each amplitude
- * read and/or written once, per the pass's flags), flags[i] = the pass flags
- * (bit 1 generate |0...0>, 2 load psi, 4 store psi, 8 load lambda, 16 store
- * lambda, 64 measure, 128 gradient), kind[i] = 0 dense pass, 1 light-cone batch.
- * *count = number of records copied. */
-int qsim_timing_get(qsim_ctx* ctx, double* ms, double* bytes, int32_t* flags, int32_t* kind, int cap, int* count);
+ * read and/or written once, per the pass's flags), flops[i] = algorithmic
+ * floating-point operations (16 per amplitude per general 2x2 gate, 8 per real
+ * rotation, 6 per phase, 0 per CNOT/CZ, plus measurement terms), flags[i] = the
+ * pass flags (bit 1 generate |0...0>, 2 load psi, 4 store psi, 8 load lambda,
+ * 16 store lambda, 64 measure, 128 gradient), kind[i] = 0 dense pass, 1
+ * light-cone batch.  Any output pointer may be NULL.  *count = records copied. */
+int qsim_timing_get(qsim_ctx* ctx, double* ms, double* bytes, double* flops, int32_t* flags, int32_t* kind, int cap,
+                    int* count);
+
+/* Reference stream: copy 'bytes' (multiple of 16) between two device buffers
+ * with a plain vectorised copy kernel, 'reps' times on ctx's stream; *ms = mean
+ * kernel time (HIP events).  Gives the achievable HBM rate next to which the
+ * pass kernels are reported, and calibrates HBM byte counters. */
+int qsim_copy_probe(qsim_ctx* ctx, uint64_t bytes, int reps, double* ms);
 
 /* ---- serving (continuous batching) ----------------------------------------------- */
 

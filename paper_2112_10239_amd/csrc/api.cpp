@@ -365,17 +365,51 @@ int qsim_timing_enable(qsim_ctx* ctx, int on) {
   return QSIM_OK;
 }
 
-int qsim_timing_get(qsim_ctx* ctx, double* ms, double* bytes, int32_t* flags, int32_t* kind, int cap, int* count) {
+int qsim_timing_get(qsim_ctx* ctx, double* ms, double* bytes, double* flops, int32_t* flags, int32_t* kind, int cap,
+                    int* count) {
   if (!ctx || !count) return QSIM_EINVAL;
   std::lock_guard<std::mutex> g(ctx->api_mu);
   const int n = std::min<int>(cap, (int)ctx->tdone.size());
   for (int i = 0; i < n; ++i) {
     if (ms) ms[i] = ctx->tdone[i].ms;
     if (bytes) bytes[i] = ctx->tdone[i].bytes;
+    if (flops) flops[i] = ctx->tdone[i].flops;
     if (flags) flags[i] = ctx->tdone[i].flags;
     if (kind) kind[i] = ctx->tdone[i].kind;
   }
   *count = n;
+  return QSIM_OK;
+}
+
+int qsim_copy_probe(qsim_ctx* ctx, uint64_t bytes, int reps, double* ms) {
+  if (!ctx || !ms || bytes == 0 || bytes % 16 || reps < 1) return QSIM_EINVAL;
+  if (ctx->mock) return no_device(ctx);
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  void *src = nullptr, *dst = nullptr;
+  HIP_TRY(hipMalloc(&src, bytes), "copy source");
+  hipError_t e = hipMalloc(&dst, bytes);
+  if (e != hipSuccess) {
+    (void)hipFree(src);
+    return hip_fail(ctx, e, "copy destination");
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  e = hipMemsetAsync(src, 0, bytes, ctx->stream);
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = launch_copy(src, dst, bytes / 16, ctx->stream);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(src, dst, bytes / 16, ctx->stream);
+  if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipFree(src);
+  (void)hipFree(dst);
+  if (e != hipSuccess) return hip_fail(ctx, e, "copy probe");
+  *ms = t / reps;
   return QSIM_OK;
 }
 

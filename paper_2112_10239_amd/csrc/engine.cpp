@@ -24,11 +24,12 @@ int hip_fail(qsim_ctx* ctx, hipError_t e, const char* where) {
     if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
   } while (0)
 
-int timing_begin(qsim_ctx* ctx, hipStream_t st, double bytes, int flags, int kind) {
+int timing_begin(qsim_ctx* ctx, hipStream_t st, double bytes, int flags, int kind, double flops) {
   if (!ctx->timing) return -1;
   TimingRec r;
   if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
   r.bytes = bytes;
+  r.flops = flops;
   r.flags = flags;
   r.kind = kind;
   (void)hipEventRecord(r.a, st);
@@ -70,6 +71,32 @@ static double pass_bytes(const PassDesc& p, int rows, int c128) {
 static int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
   return v ? std::atoi(v) : dflt;
+}
+
+// Algorithmic floating-point operations per amplitude of one pass: 16 for a
+// general 2x2 complex matrix (two complex products and a sum per output), 8
+// for a real rotation, 6 for a diagonal phase, 0 for CNOT and CZ (sign or
+// permutation); measurements 3 for |a|^2 once per group, then 2 per diagonal
+// term and 4 per flip term; gradient probes 4; H-apply terms 4.
+static double pass_flops_per_amp(const Plan& P, const PassDesc& pd) {
+  double f = 0;
+  for (int s = pd.stage_begin; s < pd.stage_end; ++s) {
+    const StageDesc& st = P.stages[s];
+    for (int o = st.op_begin; o < st.op_end; ++o) {
+      const DevOp& op = P.ops[o];
+      switch (op.type) {
+        case OP_U: f += 16; break;
+        case OP_RY: f += 8; break;
+        case OP_PHASE: f += 6; break;
+        case OP_MEAS_ZS: f += 3 + 2.0 * op.slot; o += op.slot; break;
+        case OP_MEAS_F: f += 4; break;
+        case OP_GRAD_X: case OP_GRAD_Y: case OP_GRAD_Z: f += 4; break;
+        case OP_H_Z: case OP_H_F: f += 4; break;
+        default: break;
+      }
+    }
+  }
+  return f;
 }
 
 PlanOptions fwd_options(int c128) {
@@ -516,7 +543,8 @@ int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
     L.rows = rows;
     L.c128 = c128;
     L.dual = 0;
-    const int ti = timing_begin(ctx, st, pass_bytes(P.passes[p], rows, c128), P.passes[p].flags, 0);
+    const int ti = timing_begin(ctx, st, pass_bytes(P.passes[p], rows, c128), P.passes[p].flags, 0,
+                                pass_flops_per_amp(P, P.passes[p]) * (double)rows * (double)(1ull << P.n));
     HIP_TRY(launch_pass(L, st), "pass launch");
     timing_end(ctx, ti, st);
   }

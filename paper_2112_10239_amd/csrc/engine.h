@@ -104,7 +104,7 @@ class Server;  // serving loop (serve.cpp)
 namespace qsim {
 struct TimingRec {
   hipEvent_t a = nullptr, b = nullptr;
-  double bytes = 0, ms = 0;
+  double bytes = 0, ms = 0, flops = 0;
   int flags = 0, kind = 0;
 };
 }  // namespace qsim
@@ -163,7 +163,7 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
               hipStream_t st, double* out_host);
 
 // Launch bracketing for qsim_timing_*: returns the record index or -1.
-int timing_begin(qsim_ctx* ctx, hipStream_t st, double bytes, int flags, int kind);
+int timing_begin(qsim_ctx* ctx, hipStream_t st, double bytes, int flags, int kind, double flops = 0);
 void timing_end(qsim_ctx* ctx, int idx, hipStream_t st);
 void timing_collect(qsim_ctx* ctx);  // after a stream sync
 

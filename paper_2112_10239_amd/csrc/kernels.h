@@ -59,6 +59,9 @@ hipError_t launch_reduce_rows(const double* part, int rows, int64_t per_row, dou
 hipError_t launch_grad_scatter(const double* slot_total, int rows, int n_slots, const int32_t* p_off,
                                const int32_t* p_slots, int n_params, double* grad, hipStream_t stream);
 
+// Plain copy of n16 16-byte words (reference HBM stream).
+hipError_t launch_copy(const void* src, void* dst, uint64_t n16, hipStream_t stream);
+
 // Dynamic LDS bytes for a pass kernel with tile size 2^m.
 size_t pass_lds_bytes(int m, int c128, int dual);
 int max_lds_bytes();

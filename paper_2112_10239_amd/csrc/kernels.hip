@@ -445,6 +445,38 @@ __device__ __forceinline__ double tile_run(const PassDesc* __restrict__ P, const
         const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
         const double v = (double)meas_zp<T, R>(p, op.rz);
         acc += op.c * (par ? -v : v);
+      } else if (type == OP_MEAS_ZS) {
+        // W[k] = sum_i (-1)^{parity(i & k)} |a_i|^2 by an in-register Walsh-Hadamard transform;
+        // each term then reads W at its register mask.
+        T wt[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) wt[i] = a[i].x * a[i].x + a[i].y * a[i].y;
+#pragma unroll
+        for (int bb = 0; bb < R; ++bb) {
+#pragma unroll
+          for (int i = 0; i < NR; ++i) {
+            if (i & (1 << bb)) continue;
+            const T x = wt[i], y = wt[i | (1 << bb)];
+            wt[i] = x + y;
+            wt[i | (1 << bb)] = x - y;
+          }
+        }
+        const int nt = op.slot;
+        T part = 0;
+        for (int k = 1; k <= nt; ++k) {
+          const DevOp tr = OPS[o + k];
+          const uint32_t par = (__popc(tl & tr.tz) + __popcll(base & tr.pz)) & 1;
+          T wv = 0;
+          if (tr.rz == 0u) {
+            wv = wt[0];
+          } else {
+            for_mask<NR>(tr.rz, [&](auto KC) __attribute__((always_inline)) { wv = wt[decltype(KC)::value]; });
+          }
+          const T cc = (T)tr.c;
+          part += par ? -cc * wv : cc * wv;
+        }
+        acc += (double)part;
+        o += nt;
       } else if (type == OP_MEAS_F) {
         const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
         for_mask<NR>(op.fr, [&](auto FC) __attribute__((always_inline)) {
@@ -699,6 +731,11 @@ __global__ __launch_bounds__(256) void k_grad_scatter(const double* __restrict__
   grad[idx] = s;
 }
 
+__global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 template <class K>
 hipError_t allow_lds(K kernel, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
@@ -788,6 +825,13 @@ hipError_t launch_pass_multi(const PassItem* d_items, int n_items, int64_t total
   if (!dual && r == 4) return launch_multi_t<float, 4, false>(d_items, n_items, total_tiles, m_max, stream);
   if (!dual && r == 5) return launch_multi_t<float, 5, false>(d_items, n_items, total_tiles, m_max, stream);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_copy(const void* src, void* dst, uint64_t n16, hipStream_t stream) {
+  const uint64_t blocks = std::min<uint64_t>((n16 + 255) / 256, (uint64_t)device_cus() * 32);
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)std::max<uint64_t>(1, blocks)), dim3(256), 0, stream,
+                     reinterpret_cast<const float4*>(src), reinterpret_cast<float4*>(dst), n16);
+  return hipGetLastError();
 }
 
 size_t pass_lds_bytes(int m, int c128, int dual) {

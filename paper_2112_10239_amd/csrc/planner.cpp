@@ -510,6 +510,20 @@ struct PassEmitter {
     return sb;
   }
 
+  // One OP_MEAS_ZS followed by a record per diagonal term items[i0, i1).
+  void emit_zgroup(const std::vector<const PGate*>& items, size_t i0, size_t i1, const std::vector<int>& rb) {
+    DevOp head;
+    std::memset(&head, 0, sizeof(head));
+    head.type = OP_MEAS_ZS;
+    head.slot = (int)(i1 - i0);
+    plan.ops.push_back(head);
+    for (size_t k = i0; k < i1; ++k) {
+      DevOp rec = to_devop(*items[k], rb);
+      rec.type = OP_NONE;
+      plan.ops.push_back(rec);
+    }
+  }
+
   static double stages_cost(const std::vector<StageBuild>& sb) {
     double c = kCostExchange * (double)(sb.size() - 1);
     for (const StageBuild& s : sb)
@@ -621,7 +635,17 @@ struct PassEmitter {
           if (!rb_has(rb, k)) st.tb[t++] = (uint8_t)k;
       }
       st.op_begin = (int)plan.ops.size();
-      for (const PGate* g : sb[si].items) {
+      const auto& its = sb[si].items;
+      for (size_t ii = 0; ii < its.size(); ++ii) {
+        const PGate* g = its[ii];
+        if (g->kind == PG_MEAS_Z) {  // a run of diagonal terms becomes one grouped op
+          size_t jj = ii;
+          while (jj < its.size() && its[jj]->kind == PG_MEAS_Z) ++jj;
+          emit_zgroup(its, ii, jj, rb);
+          any_meas = true;
+          ii = jj - 1;
+          continue;
+        }
         DevOp op = to_devop(*g, rb);
         if (g->kind == PG_GRAD) {
           op.slot = plan.n_gslots++;
@@ -856,7 +880,9 @@ void append_diag_measure(Plan& plan, const std::vector<PGate>& meas) {
   for (int k = 0; k < pd.m; ++k) L |= 1ull << pd.lpos[k];
   PassEmitter em(plan, pd.n, pd.m, pd.r, L);
   std::vector<int> rb(st.rb, st.rb + pd.r);
-  for (const PGate& g : meas) plan.ops.push_back(em.to_devop(g, rb));
+  std::vector<const PGate*> items;
+  for (const PGate& g : meas) items.push_back(&g);
+  em.emit_zgroup(items, 0, items.size(), rb);
   st.op_end = (int)plan.ops.size();
   if (!(pd.flags & PF_MEASURE)) {
     pd.flags |= PF_MEASURE;

@@ -32,6 +32,8 @@ enum OpType : uint8_t {
   OP_GRAD_Z = 10, // g[slot] += Im sum_i conj(b_i) (-1)^{bit(i)} a_i   (bit = (ck,cb))
   OP_H_Z = 11,    // b_i += c (-1)^{z(i)} a_i
   OP_H_F = 12,    // b_i += c i^ph (-1)^{z(i^f)} a_{i^f}
+  OP_MEAS_ZS = 13,// group of diagonal terms: the next 'slot' ops are term records (rz, tz, pz, c);
+                  // acc += sum_t c_t (-1)^{thread/tile parity} W[rz_t], W = Walsh transform of |a_i|^2
 };
 
 // Bit reference kinds for controls, diagonal bits and z-masks.

@@ -68,6 +68,7 @@ EXPORTS = [
     "qsim_apply_layer", "qsim_expect", "qsim_state_to_host", "qsim_state_device_ptr", "qsim_expect_circuit",
     "qsim_expect_grad", "qsim_lightcone_sets", "qsim_plan_dense", "qsim_submit", "qsim_poll", "qsim_cancel",
     "qsim_server_stats_get", "qsim_timing_enable", "qsim_timing_get", "qsim_poll_timed", "qsim_clock",
+    "qsim_copy_probe",
 ]
 
 
@@ -106,7 +107,8 @@ def _load():
         "qsim_timing_enable": (I, [V, I]),
         "qsim_poll_timed": (I, [V, ctypes.c_uint64, P(D), P(D), P(D)]),
         "qsim_clock": (D, []),
-        "qsim_timing_get": (I, [V, P(D), P(D), P(ctypes.c_int32), P(ctypes.c_int32), I, P(I)]),
+        "qsim_copy_probe": (I, [V, ctypes.c_uint64, I, P(D)]),
+        "qsim_timing_get": (I, [V, P(D), P(D), P(D), P(ctypes.c_int32), P(ctypes.c_int32), I, P(I)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -316,14 +318,22 @@ class Context:
         """Records of timed launches: dict of arrays ms, bytes, flags, kind."""
         ms = np.zeros(cap)
         by = np.zeros(cap)
+        fp = np.zeros(cap)
         fl = np.zeros(cap, dtype=np.int32)
         kd = np.zeros(cap, dtype=np.int32)
         cnt = ctypes.c_int()
-        self._check(lib.qsim_timing_get(self.ptr, _dptr(ms), _dptr(by), fl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        self._check(lib.qsim_timing_get(self.ptr, _dptr(ms), _dptr(by), _dptr(fp),
+                                        fl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                         kd.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cap, ctypes.byref(cnt)),
                     "qsim_timing_get")
         k = cnt.value
-        return dict(ms=ms[:k], bytes=by[:k], flags=fl[:k], kind=kd[:k])
+        return dict(ms=ms[:k], bytes=by[:k], flops=fp[:k], flags=fl[:k], kind=kd[:k])
+
+    def copy_probe(self, nbytes: int, reps: int = 5) -> float:
+        """Mean milliseconds of a plain device copy of nbytes (read nbytes + write nbytes)."""
+        ms = ctypes.c_double()
+        self._check(lib.qsim_copy_probe(self.ptr, nbytes, reps, ctypes.byref(ms)), "qsim_copy_probe")
+        return ms.value
 
     # -- serving ------------------------------------------------------------------
     def submit(self, circ, H, theta, want_grad: bool = False) -> int:
