@@ -287,6 +287,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--serving", type=float, default=1.0, help="seconds of Poisson arrivals (0 = skip serving)")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="short run for HBM byte counters: one 8 GiB reference copy, then one dense evaluation")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported by this build "
@@ -295,6 +297,14 @@ def main():
     import paper_2112_10239_amd as Q
     import workloads as W
 
+    if args.counter_run:
+        ctx = Q.Context(0)
+        ms = ctx.copy_probe(8 << 30, reps=1)
+        w = W.dense_tfim()
+        E = ctx.expect_circuit(w.circuit, w.H, w.theta, mode=Q.MODE_DENSE)
+        ctx.close()
+        print(json.dumps({"copy_bytes_each_way": 8 << 30, "copy_ms": ms, "E": E}), flush=True)
+        return
     d = bench_dense(Q, W, args.steps, args.warmup)
     line = {
         "metric": "<H> evals/sec (dense n=30 TFIM, complex64) & % HBM peak of the gate-pass kernel",

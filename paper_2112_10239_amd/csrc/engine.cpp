@@ -2,6 +2,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <map>
 #include <cstdlib>
 #include <cstring>
 
@@ -397,6 +398,8 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
   const PlanOptions base = cone_options(c128);
   const int cap = ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20;
   std::vector<int> relabel(c.n, -1);
+  // coefficient slots shared by all cones: one per distinct (kind, source gates)
+  std::map<std::pair<int, std::vector<int>>, int> slot_id;
   for (const Term& t : terms) {
     if (t.ops.empty()) {
       all.const_term += t.c;
@@ -444,7 +447,7 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
     std::memset(&cd, 0, sizeof(cd));
     cd.pass_begin = (int)all.passes.size();
     cd.pass_end = cd.pass_begin + (int)cp.passes.size();
-    cd.coef_begin = (int)all.slots.size();
+    cd.coef_begin = 0;
     cd.out_index = (int)dp->cones.size();
     cd.n = s_eff;
     if (s_eff > cp.m) {
@@ -463,8 +466,21 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
       st.op_end += ob;
       all.stages.push_back(st);
     }
-    all.ops.insert(all.ops.end(), cp.ops.begin(), cp.ops.end());
-    all.slots.insert(all.slots.end(), slots.begin(), slots.end());
+    // map the cone's slots to the shared table
+    std::vector<int> remap(slots.size());
+    for (size_t k = 0; k < slots.size(); ++k) {
+      auto key = std::make_pair(slots[k].kind, slots[k].srcs);
+      auto it = slot_id.find(key);
+      if (it == slot_id.end()) {
+        it = slot_id.emplace(key, (int)all.slots.size()).first;
+        all.slots.push_back(slots[k]);
+      }
+      remap[k] = it->second;
+    }
+    for (DevOp op : cp.ops) {
+      if (op.type == OP_U || op.type == OP_RY || op.type == OP_PHASE) op.slot = remap[op.slot];
+      all.ops.push_back(op);
+    }
     dp->cone_m_max = std::max(dp->cone_m_max, cp.m);
     dp->cones.push_back(cd);
   }
