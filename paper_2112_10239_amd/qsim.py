@@ -238,6 +238,7 @@ class Context:
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_queue: int = 0, cone_cap: int = 0):
         self._lib = lib
         opt = Options(device, max_queue, cone_cap, 0, hbm_budget_bytes)
+        self._ticket_params = {}  # ticket -> n_params of its request (size of the gradient buffer)
         p = ctypes.c_void_p()
         rc = lib.qsim_init(ctypes.byref(opt), ctypes.byref(p))
         if rc != OK:
@@ -349,22 +350,31 @@ class Context:
         rc = lib.qsim_submit(self.ptr, ctypes.byref(req), ctypes.byref(t))
         if rc != OK:
             raise QsimError(rc, f"qsim_submit: {strerror(rc)}: {self.last_error()}")
+        self._ticket_params[int(t.value)] = (cc.n_params, bool(want_grad))
         return int(t.value)
 
+    def _grad_buffer(self, ticket: int):
+        n_params, want_grad = self._ticket_params.get(ticket, (0, False))
+        return np.zeros(max(1, n_params)), (n_params if want_grad else 0)
+
     def poll(self, ticket: int, n_params: int = 0):
-        """(status, E, grad or None)."""
+        """(status, E, grad or None); the gradient buffer is sized from the submitted request."""
         E = np.zeros(1)
-        g = np.zeros(max(1, n_params))
+        g, n = self._grad_buffer(ticket)
         rc = lib.qsim_poll(self.ptr, ctypes.c_uint64(ticket), _dptr(E), _dptr(g))
-        return rc, float(E[0]), (g[:n_params] if n_params else None)
+        if rc != PENDING:
+            self._ticket_params.pop(ticket, None)
+        return rc, float(E[0]), (g[:n] if n else None)
 
     def poll_timed(self, ticket: int, n_params: int = 0):
         """(status, E, grad or None, (t_submit, t_admit, t_done)) on the qsim_clock() timeline."""
         E = np.zeros(1)
-        g = np.zeros(max(1, n_params))
+        g, n = self._grad_buffer(ticket)
         t = np.zeros(3)
         rc = lib.qsim_poll_timed(self.ptr, ctypes.c_uint64(ticket), _dptr(E), _dptr(g), _dptr(t))
-        return rc, float(E[0]), (g[:n_params] if n_params else None), tuple(float(x) for x in t)
+        if rc != PENDING:
+            self._ticket_params.pop(ticket, None)
+        return rc, float(E[0]), (g[:n] if n else None), tuple(float(x) for x in t)
 
     def cancel(self, ticket: int) -> int:
         return lib.qsim_cancel(self.ptr, ctypes.c_uint64(ticket))

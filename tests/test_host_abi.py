@@ -185,3 +185,14 @@ ctx.close()
     assert out.returncode == 0, out.stderr
     res = eval(out.stdout.strip().splitlines()[-1])
     assert res.count(-2) == 1 and res.count(0) == 5
+
+
+def test_serving_poll_sizes_gradient_buffer(Q):
+    """Polling a gradient request without stating n_params still returns the whole gradient (regression:
+    the binding used to hand the library a one-element buffer)."""
+    ctx = Q.Context(-1, hbm_budget_bytes=1 << 32)
+    r = W.serving_request(3, n_range=(14, 14), depth_range=(10, 10))
+    t = ctx.submit(r.circuit, r.H, r.theta, True)
+    st, E, g = wait(ctx, t)
+    assert st == 0 and g is not None and g.shape == (r.circuit.n_params,)
+    ctx.close()
