@@ -124,23 +124,24 @@ def cpu_baseline(W, n_sample=23):
                        f"({dt:.2f} s), scaled by 2^{30 - n_sample} x gate-count ratio to n=30")
 
 
-def bench_lightcone(Q, W, reps=5):
+def bench_lightcone(Q, W, reps=20):
     import torch
 
     w = W.lightcone_maxcut()
-    ctx = Q.Context(0)
-    ctx.expect_circuit(w.circuit, w.H, w.theta, mode=Q.MODE_LIGHTCONE)
-    ctx.timing_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        E = ctx.expect_circuit(w.circuit, w.H, w.theta, mode=Q.MODE_LIGHTCONE)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    rec = ctx.timing_get()
-    ctx.close()
-    kms = float(rec["ms"][rec["kind"] == 1].mean())
-    return dict(workload="lightcone_maxcut_n500_d4 (750 cones, one launch)", evals_per_s=reps / (t1 - t0),
-                kernel_ms=kms, E=E)
+    out = dict(workload="lightcone_maxcut_n500_d4 (750 terms, one cone launch)")
+    for name, mode in (("canonical", Q.MODE_LIGHTCONE), ("factored", Q.MODE_LIGHTCONE_FACTORED)):
+        ctx = Q.Context(0)
+        ctx.expect_circuit(w.circuit, w.H, w.theta, mode=mode)
+        ctx.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            E = ctx.expect_circuit(w.circuit, w.H, w.theta, mode=mode)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rec = ctx.timing_get()
+        ctx.close()
+        out[name] = dict(evals_per_s=reps / (t1 - t0), cone_kernel_ms=float(rec["ms"][rec["kind"] == 1].mean()), E=E)
+    return out
 
 
 def bench_grad(Q, W, reps=2):

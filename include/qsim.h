@@ -59,7 +59,12 @@ extern "C" {
 
 enum { QSIM_RX = 0, QSIM_RY = 1, QSIM_RZ = 2, QSIM_CZ = 3, QSIM_CNOT = 4, QSIM_U1 = 5 };
 enum { QSIM_C64 = 0, QSIM_C128 = 1 };
-enum { QSIM_MODE_AUTO = 0, QSIM_MODE_DENSE = 1, QSIM_MODE_LIGHTCONE = 2 };
+/* LIGHTCONE: every term on its canonical cone.  LIGHTCONE_FACTORED: for Z-string
+ * terms, trailing diagonal gates (which commute with the term) are dropped and
+ * the term splits into factors whose remaining cones are disjoint (the
+ * expectation of a product over disjoint cones on |0...0> is the product of
+ * expectations); factors are shared between terms.  Both are exact. */
+enum { QSIM_MODE_AUTO = 0, QSIM_MODE_DENSE = 1, QSIM_MODE_LIGHTCONE = 2, QSIM_MODE_LIGHTCONE_FACTORED = 3 };
 
 /* One gate.  Rotations take theta[param] when param >= 0, else 'angle'.
  * Two-qubit gates use q0 and q1 (distinct); others use q0 only.  'mat' is read
@@ -138,8 +143,8 @@ int qsim_state_device_ptr(qsim_state* st, void** ptr);
 /* ---- one-call evaluation (Sec. 3: forward value) ----------------------------------- */
 
 /* out[b] = <psi(theta_b)|H|psi(theta_b)> for b < batch, theta_b = params + b*n_params
- * (host float64).  mode: dense state vector, per-term light cones (batch 1), or AUTO
- * (light cones when n > 30 or when all cones are far smaller than n).  If keep != NULL
+ * (host float64).  mode: dense state vector, per-term light cones, factored light
+ * cones, or AUTO (factored light cones when n > 30, else dense).  If keep != NULL
  * (dense mode only), the final states are returned in *keep for qsim_expect_grad. */
 int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
                         const qsim_hamiltonian* H, int mode, int dtype, void* stream, double* out,

@@ -248,17 +248,18 @@ int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* para
     set_error(ctx, "expect_circuit: params missing");
     return QSIM_EINVAL;
   }
-  if (mode == QSIM_MODE_AUTO) mode = (cd.n > 30 && !keep) ? QSIM_MODE_LIGHTCONE : QSIM_MODE_DENSE;
+  if (mode == QSIM_MODE_AUTO) mode = (cd.n > 30 && !keep) ? QSIM_MODE_LIGHTCONE_FACTORED : QSIM_MODE_DENSE;
   const int c128 = dtype == QSIM_C128;
   std::lock_guard<std::mutex> g(ctx->api_mu);
   HIP_TRY(hipSetDevice(ctx->device), "set device");
   hipStream_t st = pick_stream(ctx, stream);
-  if (mode == QSIM_MODE_LIGHTCONE) {
+  if (mode == QSIM_MODE_LIGHTCONE || mode == QSIM_MODE_LIGHTCONE_FACTORED) {
     if (keep) {
       set_error(ctx, "expect_circuit: keep is only available in dense mode");
       return QSIM_EINVAL;
     }
-    auto dp = get_cone_plan(ctx, cd, terms, c128, rc);
+    auto dp = mode == QSIM_MODE_LIGHTCONE ? get_cone_plan(ctx, cd, terms, c128, rc)
+                                          : get_factor_plan(ctx, cd, terms, c128, rc);
     if (!dp) return rc;
     for (int b = 0; b < batch; ++b) {
       rc = run_cones(ctx, ctx->ws, *dp, cd, params ? params + (size_t)b * cd.n_params : nullptr, c128, st, out + b);

@@ -2,6 +2,8 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <functional>
+#include <iterator>
 #include <map>
 #include <cstdlib>
 #include <cstring>
@@ -136,6 +138,9 @@ DevPlan::~DevPlan() {
   (void)hipFree(d_order);
   (void)hipFree(d_poff);
   (void)hipFree(d_pslots);
+  (void)hipFree(d_toff);
+  (void)hipFree(d_tfac);
+  (void)hipFree(d_tcoef);
 }
 
 template <class V>
@@ -156,6 +161,11 @@ hipError_t DevPlan::upload(bool mock) {
   if (!cones.empty()) {
     if ((e = upload_vec(cones, &d_cones)) != hipSuccess) return e;
     if ((e = upload_vec(order, &d_order)) != hipSuccess) return e;
+  }
+  if (factored) {
+    if ((e = upload_vec(t_off, &d_toff)) != hipSuccess) return e;
+    if ((e = upload_vec(t_fac, &d_tfac)) != hipSuccess) return e;
+    if ((e = upload_vec(t_coef, &d_tcoef)) != hipSuccess) return e;
   }
   if (plan.n_gslots > 0) {
     int np = 0;
@@ -388,31 +398,28 @@ std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, con
   return dp;
 }
 
-std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, int c128,
-                                       int& rc) {
-  rc = QSIM_OK;
-  const uint64_t key = structure_hash(c, terms, 0x400 | c128);
-  if (auto p = cache_get(ctx, key)) return p;
-  auto dp = std::make_shared<DevPlan>();
-  Plan& all = dp->plan;
-  const PlanOptions base = cone_options(c128);
-  const int cap = ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20;
-  std::vector<int> relabel(c.n, -1);
-  // coefficient slots shared by all cones: one per distinct (kind, source gates)
-  std::map<std::pair<int, std::vector<int>>, int> slot_id;
-  for (const Term& t : terms) {
-    if (t.ops.empty()) {
-      all.const_term += t.c;
-      continue;
-    }
+// Shared state while packing cones into one plan.
+struct ConePacker {
+  DevPlan& dp;
+  const CircuitDesc& c;
+  PlanOptions base;
+  int cap;
+  std::vector<int> relabel;
+  std::map<std::pair<int, std::vector<int>>, int> slot_id;  // shared coefficient table
+  ConePacker(DevPlan& d, const CircuitDesc& cc, int c128, int cap_) : dp(d), c(cc), base(cone_options(c128)), cap(cap_),
+                                                                      relabel(cc.n, -1) {}
+
+  // Adds one cone evaluating coefficient * <obs> on the gates not in 'skip';
+  // returns QSIM_OK or an error code (message in err).
+  int add(const Term& obs, const std::vector<char>* skip, std::string& err) {
+    Plan& all = dp.plan;
     std::vector<int> support, set, gates;
-    for (auto [q, L] : t.ops) support.push_back(q);
-    light_cone(c, support, set, gates);
+    for (auto [q, L] : obs.ops) support.push_back(q);
+    light_cone(c, support, set, gates, skip);
     const int s = (int)set.size();
     if (s > cap) {
-      set_error(ctx, "light cone of " + std::to_string(s) + " qubits exceeds the cap of " + std::to_string(cap));
-      rc = QSIM_ETOOBIG;
-      return nullptr;
+      err = "light cone of " + std::to_string(s) + " qubits exceeds the cap of " + std::to_string(cap);
+      return QSIM_ETOOBIG;
     }
     const int s_eff = std::max(s, 4);  // the cone kernel holds 16 amplitudes per thread
     for (int k = 0; k < s; ++k) relabel[set[k]] = k;
@@ -431,28 +438,23 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
       for (PGate& p : *v)
         for (int& src : p.srcs) src = gates[src];
     double cst = 0;
-    term_pgates({t}, false, meas, cst, &relabel);
+    term_pgates({obs}, false, meas, cst, &relabel);
+    for (int k = 0; k < s; ++k) relabel[set[k]] = -1;
     PlanOptions o = base;
     o.init = true;
     o.store_final = false;
     Plan cp;
-    std::string err;
-    if (plan_forward(s_eff, pg, meas, o, cp, err)) {
-      set_error(ctx, err);
-      rc = QSIM_EINVAL;
-      return nullptr;
-    }
-    for (int k = 0; k < s; ++k) relabel[set[k]] = -1;
+    if (plan_forward(s_eff, pg, meas, o, cp, err)) return QSIM_EINVAL;
     ConeDesc cd;
     std::memset(&cd, 0, sizeof(cd));
     cd.pass_begin = (int)all.passes.size();
     cd.pass_end = cd.pass_begin + (int)cp.passes.size();
     cd.coef_begin = 0;
-    cd.out_index = (int)dp->cones.size();
+    cd.out_index = (int)dp.cones.size();
     cd.n = s_eff;
     if (s_eff > cp.m) {
-      cd.scratch_off = dp->scratch_amps;
-      dp->scratch_amps += 1ll << s_eff;
+      cd.scratch_off = dp.scratch_amps;
+      dp.scratch_amps += 1ll << s_eff;
     }
     const int sb = (int)all.stages.size(), ob = (int)all.ops.size();
     for (PassDesc pd : cp.passes) {
@@ -466,7 +468,6 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
       st.op_end += ob;
       all.stages.push_back(st);
     }
-    // map the cone's slots to the shared table
     std::vector<int> remap(slots.size());
     for (size_t k = 0; k < slots.size(); ++k) {
       auto key = std::make_pair(slots[k].kind, slots[k].srcs);
@@ -481,23 +482,133 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
       if (op.type == OP_U || op.type == OP_RY || op.type == OP_PHASE) op.slot = remap[op.slot];
       all.ops.push_back(op);
     }
-    dp->cone_m_max = std::max(dp->cone_m_max, cp.m);
-    dp->cones.push_back(cd);
+    dp.cone_m_max = std::max(dp.cone_m_max, cp.m);
+    dp.cones.push_back(cd);
+    return QSIM_OK;
   }
+
   // largest cones first, so the tail of the launch holds the short ones
-  dp->order.resize(dp->cones.size());
-  for (int i = 0; i < (int)dp->order.size(); ++i) dp->order[i] = i;
-  std::stable_sort(dp->order.begin(), dp->order.end(), [&](int a, int b) {
-    const ConeDesc &x = dp->cones[a], &y = dp->cones[b];
-    const int ox = all.stages[all.passes[x.pass_end - 1].stage_end - 1].op_end -
-                   all.stages[all.passes[x.pass_begin].stage_begin].op_begin;
-    const int oy = all.stages[all.passes[y.pass_end - 1].stage_end - 1].op_end -
-                   all.stages[all.passes[y.pass_begin].stage_begin].op_begin;
-    if (x.n != y.n) return x.n > y.n;
-    return ox > oy;
-  });
-  all.n = c.n;
-  all.r = 4;
+  void finish() {
+    Plan& all = dp.plan;
+    dp.order.resize(dp.cones.size());
+    for (int i = 0; i < (int)dp.order.size(); ++i) dp.order[i] = i;
+    auto nops = [&](const ConeDesc& x) {
+      return all.stages[all.passes[x.pass_end - 1].stage_end - 1].op_end -
+             all.stages[all.passes[x.pass_begin].stage_begin].op_begin;
+    };
+    std::stable_sort(dp.order.begin(), dp.order.end(), [&](int a, int b) {
+      const ConeDesc &x = dp.cones[a], &y = dp.cones[b];
+      if (x.n != y.n) return x.n > y.n;
+      return nops(x) > nops(y);
+    });
+    all.n = c.n;
+    all.r = 4;
+  }
+};
+
+std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, int c128,
+                                       int& rc) {
+  rc = QSIM_OK;
+  const uint64_t key = structure_hash(c, terms, 0x400 | c128);
+  if (auto p = cache_get(ctx, key)) return p;
+  auto dp = std::make_shared<DevPlan>();
+  ConePacker pk(*dp, c, c128, ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20);
+  for (const Term& t : terms) {
+    if (t.ops.empty()) {
+      dp->plan.const_term += t.c;
+      continue;
+    }
+    std::string err;
+    if ((rc = pk.add(t, nullptr, err)) != QSIM_OK) {
+      set_error(ctx, err);
+      return nullptr;
+    }
+  }
+  pk.finish();
+  hipError_t e = dp->upload(ctx->mock);
+  if (e != hipSuccess) {
+    rc = hip_fail(ctx, e, "plan upload");
+    return nullptr;
+  }
+  cache_put(ctx, key, dp);
+  return dp;
+}
+
+std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
+                                         int c128, int& rc) {
+  rc = QSIM_OK;
+  const uint64_t key = structure_hash(c, terms, 0x600 | c128);
+  if (auto p = cache_get(ctx, key)) return p;
+  auto dp = std::make_shared<DevPlan>();
+  dp->factored = true;
+  ConePacker pk(*dp, c, c128, ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20);
+  const std::vector<char> drop = trailing_diagonal(c);
+  std::map<std::vector<int>, int> factor_id;  // (pruned flag, qubit*4 + letter ...) -> cone
+  auto factor = [&](const Term& obs, bool pruned, std::string& err, int& id) {
+    std::vector<int> k{pruned ? 1 : 0};
+    for (auto [q, L] : obs.ops) k.push_back(q * 4 + (L == 'X' ? 1 : L == 'Y' ? 2 : 3));
+    auto it = factor_id.find(k);
+    if (it != factor_id.end()) {
+      id = it->second;
+      return QSIM_OK;
+    }
+    id = (int)dp->cones.size();
+    const int r = pk.add(obs, pruned ? &drop : nullptr, err);
+    if (r == QSIM_OK) factor_id.emplace(k, id);
+    return r;
+  };
+  dp->t_off.push_back(0);
+  for (const Term& t : terms) {
+    if (t.ops.empty()) {
+      dp->plan.const_term += t.c;
+      continue;
+    }
+    bool zstring = true;
+    for (auto [q, L] : t.ops) zstring &= L == 'Z';
+    std::string err;
+    std::vector<std::vector<std::pair<int, char>>> parts;
+    if (!zstring) {
+      parts.push_back(t.ops);  // the whole term on its canonical cone
+    } else {
+      // pruned cone of each qubit; qubits whose cones meet share a factor
+      const int k = (int)t.ops.size();
+      std::vector<std::vector<int>> sets(k);
+      for (int i = 0; i < k; ++i) {
+        std::vector<int> gs;
+        light_cone(c, {t.ops[i].first}, sets[i], gs, &drop);
+      }
+      std::vector<int> root(k);
+      for (int i = 0; i < k; ++i) root[i] = i;
+      std::function<int(int)> find = [&](int x) { return root[x] == x ? x : root[x] = find(root[x]); };
+      for (int i = 0; i < k; ++i)
+        for (int j = i + 1; j < k; ++j) {
+          std::vector<int> inter;
+          std::set_intersection(sets[i].begin(), sets[i].end(), sets[j].begin(), sets[j].end(),
+                                std::back_inserter(inter));
+          if (!inter.empty()) root[find(i)] = find(j);
+        }
+      std::map<int, std::vector<std::pair<int, char>>> groups;
+      for (int i = 0; i < k; ++i) groups[find(i)].push_back(t.ops[i]);
+      for (auto& g : groups) {
+        std::sort(g.second.begin(), g.second.end());
+        parts.push_back(g.second);
+      }
+    }
+    for (auto& ops : parts) {
+      Term f;
+      f.c = 1.0;
+      f.ops = ops;
+      int id = 0;
+      if ((rc = factor(f, zstring, err, id)) != QSIM_OK) {
+        set_error(ctx, err);
+        return nullptr;
+      }
+      dp->t_fac.push_back(id);
+    }
+    dp->t_off.push_back((int32_t)dp->t_fac.size());
+    dp->t_coef.push_back(t.c);
+  }
+  pk.finish();
   hipError_t e = dp->upload(ctx->mock);
   if (e != hipSuccess) {
     rc = hip_fail(ctx, e, "plan upload");
@@ -695,8 +806,18 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
   HIP_TRY(launch_cones(L, st), "cone launch");
   timing_end(ctx, ti, st);
   HIP_TRY(ws.out.ensure(sizeof(double)), "result buffer");
-  HIP_TRY(launch_reduce_rows((const double*)ws.meas.p, 1, (int64_t)nc, P.const_term, (double*)ws.out.p, st),
-          "cone reduce");
+  if (dp.factored) {  // term values = coefficient x product of its factors, then the sum over terms
+    const int T = (int)dp.t_coef.size();
+    HIP_TRY(ws.slot_total.ensure(std::max(1, T) * sizeof(double)), "term values");
+    HIP_TRY(launch_term_products((const double*)ws.meas.p, dp.d_toff, dp.d_tfac, dp.d_tcoef, T,
+                                 (double*)ws.slot_total.p, st),
+            "term products");
+    HIP_TRY(launch_reduce_rows((const double*)ws.slot_total.p, 1, T, P.const_term, (double*)ws.out.p, st),
+            "term reduce");
+  } else {
+    HIP_TRY(launch_reduce_rows((const double*)ws.meas.p, 1, (int64_t)nc, P.const_term, (double*)ws.out.p, st),
+            "cone reduce");
+  }
   return fetch_out(ctx, ws, 1, st, out_host);
 }
 

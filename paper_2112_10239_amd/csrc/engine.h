@@ -77,6 +77,13 @@ struct DevPlan {
   // gradient scatter (CSR parameter -> gradient slots)
   int32_t* d_poff = nullptr;
   int32_t* d_pslots = nullptr;
+  // factored light cones: term t = t_coef[t] * prod of cone values t_fac[t_off[t] .. t_off[t+1])
+  bool factored = false;
+  std::vector<int32_t> t_off, t_fac;
+  std::vector<double> t_coef;
+  int32_t* d_toff = nullptr;
+  int32_t* d_tfac = nullptr;
+  double* d_tcoef = nullptr;
   ~DevPlan();
   hipError_t upload(bool mock);
 };
@@ -153,6 +160,10 @@ std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, con
                                         int c128, std::shared_ptr<DevPlan>& happly, int& rc);
 std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
                                        int c128, int& rc);
+// Light cones after dropping trailing diagonal gates (Z-string terms) and
+// splitting terms into factors with disjoint cones, shared across terms.
+std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
+                                         int c128, int& rc);
 
 // Run a dense plan on states A (and B) with 'rows' rows; coefficients from params.
 int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params, int rows,

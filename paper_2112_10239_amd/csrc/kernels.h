@@ -59,6 +59,10 @@ hipError_t launch_reduce_rows(const double* part, int rows, int64_t per_row, dou
 hipError_t launch_grad_scatter(const double* slot_total, int rows, int n_slots, const int32_t* p_off,
                                const int32_t* p_slots, int n_params, double* grad, hipStream_t stream);
 
+// tval[t] = coef[t] * prod_{k in [off[t], off[t+1])} fval[fac[k]] (in k order).
+hipError_t launch_term_products(const double* fval, const int32_t* off, const int32_t* fac, const double* coef, int T,
+                                double* tval, hipStream_t stream);
+
 // Plain copy of n16 16-byte words (reference HBM stream).
 hipError_t launch_copy(const void* src, void* dst, uint64_t n16, hipStream_t stream);
 

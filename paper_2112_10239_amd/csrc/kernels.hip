@@ -731,6 +731,16 @@ __global__ __launch_bounds__(256) void k_grad_scatter(const double* __restrict__
   grad[idx] = s;
 }
 
+__global__ __launch_bounds__(256) void k_term_products(const double* __restrict__ fval, const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ fac,
+                                                       const double* __restrict__ coef, int T, double* tval) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= T) return;
+  double v = coef[t];
+  for (int k = off[t]; k < off[t + 1]; ++k) v *= fval[fac[k]];
+  tval[t] = v;
+}
+
 __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, uint64_t n) {
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
@@ -825,6 +835,14 @@ hipError_t launch_pass_multi(const PassItem* d_items, int n_items, int64_t total
   if (!dual && r == 4) return launch_multi_t<float, 4, false>(d_items, n_items, total_tiles, m_max, stream);
   if (!dual && r == 5) return launch_multi_t<float, 5, false>(d_items, n_items, total_tiles, m_max, stream);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_term_products(const double* fval, const int32_t* off, const int32_t* fac, const double* coef, int T,
+                                double* tval, hipStream_t stream) {
+  if (T <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_term_products, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, stream, fval, off, fac, coef, T,
+                     tval);
+  return hipGetLastError();
 }
 
 hipError_t launch_copy(const void* src, void* dst, uint64_t n16, hipStream_t stream) {

@@ -895,11 +895,12 @@ void append_diag_measure(Plan& plan, const std::vector<PGate>& meas) {
 // ---------------------------------------------------------------------------
 
 void light_cone(const CircuitDesc& c, const std::vector<int>& support, std::vector<int>& set,
-                std::vector<int>& gates) {
+                std::vector<int>& gates, const std::vector<char>* skip) {
   std::vector<char> in(c.n, 0);
   for (int q : support) in[q] = 1;
   gates.clear();
   for (int g = (int)c.gates.size() - 1; g >= 0; --g) {
+    if (skip && (*skip)[g]) continue;
     const Gate& x = c.gates[g];
     if (x.kind == G_CZ || x.kind == G_CNOT) {
       if (in[x.q0] || in[x.q1]) {
@@ -914,6 +915,23 @@ void light_cone(const CircuitDesc& c, const std::vector<int>& support, std::vect
   set.clear();
   for (int q = 0; q < c.n; ++q)
     if (in[q]) set.push_back(q);
+}
+
+std::vector<char> trailing_diagonal(const CircuitDesc& c) {
+  std::vector<char> drop(c.gates.size(), 0), open(c.n, 1);
+  for (int g = (int)c.gates.size() - 1; g >= 0; --g) {
+    const Gate& x = c.gates[g];
+    const bool two = x.kind == G_CZ || x.kind == G_CNOT;
+    const bool diag = x.kind == G_RZ || x.kind == G_CZ;
+    const bool all_open = open[x.q0] && (!two || open[x.q1]);
+    if (diag && all_open) {
+      drop[g] = 1;
+    } else {
+      open[x.q0] = 0;
+      if (two) open[x.q1] = 0;
+    }
+  }
+  return drop;
 }
 
 // ---------------------------------------------------------------------------

@@ -101,8 +101,14 @@ int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, P
 void append_diag_measure(Plan& plan, const std::vector<PGate>& meas);
 
 // Canonical light cone of one term: ascending qubits and in-cone gate indices.
+// Gates with skip[g] != 0 (optional) are treated as absent.
 void light_cone(const CircuitDesc& c, const std::vector<int>& support, std::vector<int>& set,
-                std::vector<int>& gates);
+                std::vector<int>& gates, const std::vector<char>* skip = nullptr);
+
+// Gates that can be dropped for any diagonal (Z-string) observable: diagonal
+// gates (RZ, CZ) all of whose later gates on the same qubits are droppable too.
+// They commute with the observable and with each other, so they cancel in <P>.
+std::vector<char> trailing_diagonal(const CircuitDesc& c);
 
 // Per-row coefficient table for the slots, T = float or double; 8 values per slot.
 template <class T>

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libqsim.so")
 OK, PENDING = 0, 1
 EINVAL, ENOMEM, ETOOBIG, EAGAIN, ENOTFOUND, EDEVICE, ECANCELED, ESHUTDOWN = -1, -2, -3, -4, -5, -6, -7, -8
 C64, C128 = 0, 1
-MODE_AUTO, MODE_DENSE, MODE_LIGHTCONE = 0, 1, 2
+MODE_AUTO, MODE_DENSE, MODE_LIGHTCONE, MODE_LIGHTCONE_FACTORED = 0, 1, 2, 3
 RX, RY, RZ, CZ, CNOT, U1 = 0, 1, 2, 3, 4, 5
 
 

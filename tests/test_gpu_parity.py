@@ -356,3 +356,39 @@ def test_ring_maxcut_golden_fixture(Q, eng):
     E2, g = eng.expect_grad(w.circuit, w.H, w.theta, dtype=Q.C128)
     assert abs(E2 - gold["E"]) <= TOL128 * 15
     np.testing.assert_allclose(g, gold["grad_psr"], atol=TOL128 * 15)
+
+
+# --- factored light cones (trailing diagonal gates dropped, disjoint factors) -------------
+
+def test_factored_n500_vs_oracle(Q, eng, oracle_mod):
+    w = W.lightcone_maxcut()
+    say("factored lightcone n500")
+    want, _ = oracle_mod.expect_lightcone(w.circuit, w.H, w.theta)
+    got = eng.expect_circuit(w.circuit, w.H, w.theta, mode=Q.MODE_LIGHTCONE_FACTORED)
+    assert abs(got - want) <= tol(w.H, 0), (got, want)
+    # AUTO picks the factored mode above 30 qubits
+    assert eng.expect_circuit(w.circuit, w.H, w.theta) == pytest.approx(got, abs=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_factored_random_vs_dense(Q, eng, oracle_mod, seed):
+    rng = np.random.default_rng([28, seed])
+    n = int(rng.integers(5, 15))
+    c = W.random_circuit(n, 60, rng, kinds=(W.RX, W.RY, W.RZ, W.CZ, W.CNOT))
+    th = W.angles(max(c.n_params, 1), [28, seed])[: c.n_params]
+    letters = "Z" if seed % 2 == 0 else "XYZ"
+    H = W.random_hamiltonian(n, 10, rng, max_weight=3, letters=letters)
+    say("factored random", seed, n)
+    want = oracle_mod.expect(c, H, th)
+    assert abs(eng.expect_circuit(c, H, th, mode=Q.MODE_LIGHTCONE_FACTORED) - want) <= tol(H, 0)
+
+
+def test_factored_brickwork_clifford_n200(Q, eng):
+    from tests import pinlib
+
+    c = W.brickwork_ry_cz(200, 5)
+    H = W.maxcut(W.random_regular3(200, np.random.default_rng([29, 200])))
+    th = pinlib.clifford_angles(c.n_params, np.random.default_rng([29, 1]))
+    say("factored clifford n200")
+    want = pinlib.clifford_expect(c, H, th)
+    assert abs(eng.expect_circuit(c, H, th, mode=Q.MODE_LIGHTCONE_FACTORED) - want) <= 1e-3
