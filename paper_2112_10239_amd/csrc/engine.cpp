@@ -291,6 +291,55 @@ static std::shared_ptr<DevPlan> gate_plan(qsim_ctx* ctx, const CircuitDesc& c, i
   return dp;
 }
 
+int host_forward_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, bool store_final,
+                      Plan& out) {
+  int rc = QSIM_OK;
+  std::vector<PGate> meas;
+  double cst = 0;
+  term_pgates(terms, false, meas, cst);
+  bool diag = true;
+  for (const PGate& t : meas) diag &= t.fmask == 0;
+  if (diag) {
+    auto gp = gate_plan(ctx, c, 0, true, store_final, rc);
+    if (!gp) return rc;
+    out = gp->plan;
+    append_diag_measure(out, meas);
+    out.const_term = cst;
+    return QSIM_OK;
+  }
+  out = Plan();
+  std::vector<PGate> pg;
+  forward_pgates(c, true, pg, out.slots);
+  PlanOptions o = fwd_options(0);
+  o.store_final = store_final;
+  std::string err;
+  if (plan_forward(c.n, pg, meas, o, out, err)) {
+    set_error(ctx, err);
+    return QSIM_EINVAL;
+  }
+  out.const_term = cst;
+  return QSIM_OK;
+}
+
+int host_happly_plan(qsim_ctx* ctx, int n, const std::vector<Term>& terms, Plan& out) {
+  std::vector<PGate> ht;
+  double cst = 0;
+  term_pgates(terms, true, ht, cst);
+  if (cst != 0.0) {
+    PGate p;
+    p.kind = PG_H_Z;
+    p.c = cst;
+    ht.push_back(p);
+  }
+  out = Plan();
+  std::string err;
+  if (plan_happly(n, ht, dual_options(0), out, err)) {
+    set_error(ctx, err);
+    return QSIM_EINVAL;
+  }
+  return QSIM_OK;
+}
+
 std::shared_ptr<DevPlan> get_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
                                         int c128, bool init, bool store_final, bool measure, int& rc) {
   rc = QSIM_OK;
@@ -377,6 +426,12 @@ std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, con
       happly = dp;
     }
   }
+  return get_adjoint_plan(ctx, c, c128, rc);
+}
+
+std::shared_ptr<DevPlan> get_adjoint_plan(qsim_ctx* ctx, const CircuitDesc& c, int c128, int& rc) {
+  rc = QSIM_OK;
+  const PlanOptions o = dual_options(c128);
   const uint64_t key = structure_hash(c, {}, 0x200 | c128);
   if (auto p = cache_get(ctx, key)) return p;
   auto dp = std::make_shared<DevPlan>();

@@ -158,6 +158,12 @@ std::shared_ptr<DevPlan> get_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, con
                                         int c128, bool init, bool store_final, bool measure, int& rc);
 std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
                                         int c128, std::shared_ptr<DevPlan>& happly, int& rc);
+std::shared_ptr<DevPlan> get_adjoint_plan(qsim_ctx* ctx, const CircuitDesc& c, int c128, int& rc);
+// Host-only plans for the serving loop (complex64): the forward plan reuses
+// the structure-cached gate plan and appends this H's measurement.
+int host_forward_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, bool store_final,
+                      Plan& out);
+int host_happly_plan(qsim_ctx* ctx, int n, const std::vector<Term>& terms, Plan& out);
 std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
                                        int c128, int& rc);
 // Light cones after dropping trailing diagonal gates (Z-string terms) and

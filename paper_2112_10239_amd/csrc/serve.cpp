@@ -10,7 +10,9 @@ namespace qsim {
 
 namespace {
 
-constexpr size_t kMaxRunning = 512;
+constexpr size_t kMaxRunning = 512;          // requests launching passes at once
+constexpr size_t kMaxSteps = 3;              // steps in flight on the device
+constexpr size_t kRingBytes = 64ull << 20;   // pinned staging for plan/coefficient uploads
 
 enum Phase { PH_FWD = 0, PH_HAPPLY = 1, PH_ADJ = 2, PH_DONE = 3 };
 
@@ -20,6 +22,14 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Device copy of a per-request plan, in pooled blocks.
+struct ReqPlan {
+  PassDesc* P = nullptr;
+  StageDesc* S = nullptr;
+  DevOp* O = nullptr;
+  size_t bp = 0, bs = 0, bo = 0;
+};
+
 struct SReq {
   uint64_t ticket = 0;
   CircuitDesc c;
@@ -27,27 +37,28 @@ struct SReq {
   std::vector<double> params;
   bool want_grad = false;
   size_t footprint = 0;
-  // lifecycle
-  bool cancelled = false, done = false, failed = false, prepared = false;
+  // lifecycle (under the server mutex once queued)
+  bool cancelled = false, done = false, failed = false, admitted = false;
   int status = QSIM_PENDING;
   double E = 0;
   std::vector<double> grad;
-  // execution
-  std::shared_ptr<DevPlan> fp, hp, ap;
-  int phase = PH_FWD;
-  int next = 0;
-  int ended = -1;  // phase that ended in the current step
-  size_t state_bytes = 0, coef_f_bytes = 0, coef_a_bytes = 0, meas_bytes = 0, gpart_bytes = 0, res_bytes = 0;
-  void *A = nullptr, *B = nullptr, *coef_f = nullptr, *coef_a = nullptr;
-  double *meas = nullptr, *gpart = nullptr, *res = nullptr;
-  std::vector<float> h_coef_f, h_coef_a;
-  std::vector<double> h_res;
-  int passes_done = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
+  // host preparation, done by the submitting thread
+  Plan fplan, hplan;            // forward (+ measurement) and H-apply plans
+  std::shared_ptr<DevPlan> ap;  // adjoint plan, shared by requests of one circuit structure
+  std::vector<float> coef_f, coef_a;
+  int np_used = 0;
+  // device state (scheduler thread)
+  ReqPlan df, dh;
+  void *A = nullptr, *B = nullptr, *cf = nullptr, *ca = nullptr;
+  double *meas = nullptr, *gpart = nullptr, *res = nullptr;
+  size_t state_bytes = 0, cf_bytes = 0, ca_bytes = 0, meas_bytes = 0, gpart_bytes = 0, res_bytes = 0;
+  double* h_res = nullptr;  // pinned ring space of the final step: E, then the gradient
+  int phase = PH_FWD, next = 0, passes_done = 0;
 };
 
 // ---------------------------------------------------------------------------
-// block pool
+// block pool and pinned ring
 // ---------------------------------------------------------------------------
 
 static int g_fail_alloc_countdown = [] {
@@ -98,6 +109,32 @@ void BlockPool::trim(size_t keep_bytes) {
   }
 }
 
+PinnedRing::~PinnedRing() {
+  if (!base_) return;
+  if (mock_) std::free(base_);
+  else (void)hipHostFree(base_);
+}
+
+bool PinnedRing::init(size_t bytes, bool mock) {
+  mock_ = mock;
+  if (mock) base_ = static_cast<char*>(std::malloc(bytes));
+  else if (hipHostMalloc(reinterpret_cast<void**>(&base_), bytes, hipHostMallocDefault) != hipSuccess)
+    base_ = nullptr;
+  cap_ = base_ ? bytes : 0;
+  return base_ != nullptr;
+}
+
+void* PinnedRing::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (!base_ || bytes > cap_) return nullptr;
+  uint64_t start = head_;
+  const uint64_t pos = head_ % cap_;
+  if (pos + bytes > cap_) start += cap_ - pos;  // no room before the end: wrap to the front
+  if (start + bytes - tail_ > cap_) return nullptr;
+  head_ = start + bytes;
+  return base_ + (start % cap_);
+}
+
 // ---------------------------------------------------------------------------
 // server
 // ---------------------------------------------------------------------------
@@ -107,6 +144,7 @@ Server::Server(qsim_ctx* ctx, bool mock) : ctx_(ctx), mock_(mock), pool_(mock) {
     (void)hipSetDevice(ctx_->device);
     (void)hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking);
   }
+  ok_ = ring_.init(kRingBytes, mock_);
   thread_ = std::thread([this] { loop(); });
 }
 
@@ -119,8 +157,8 @@ Server::~Server() {
   if (thread_.joinable()) thread_.join();
   if (!mock_) {
     (void)hipStreamSynchronize(stream_);
+    for (hipEvent_t e : free_events_) (void)hipEventDestroy(e);
     pool_.trim(0);
-    ws_.release();
     d_items_.release();
     (void)hipStreamDestroy(stream_);
   }
@@ -163,17 +201,41 @@ int Server::submit(const qsim_request* rq, uint64_t* ticket) {
   r->params.assign(rq->params, rq->params + r->c.n_params);
   r->want_grad = rq->want_grad != 0;
   r->footprint = footprint_of(r->c, r->terms, r->want_grad);
+  auto admissible = [&]() -> int {
+    if (stop_) return QSIM_ESHUTDOWN;
+    if (r->footprint > ctx_->opt.hbm_budget_bytes) {
+      st_.rejected++;
+      set_error(ctx_, "request footprint exceeds the memory budget");
+      return QSIM_ETOOBIG;
+    }
+    if (queue_.size() + running_.size() >= (size_t)ctx_->opt.max_queue) {
+      st_.rejected++;
+      return QSIM_EAGAIN;
+    }
+    return QSIM_OK;
+  };
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    if ((rc = admissible())) return rc;
+  }
+  // Host preparation runs here, in the caller's thread, so the scheduler never
+  // waits for it: plans (gate passes from the structure cache) and coefficients.
+  if (!mock_) (void)hipSetDevice(ctx_->device);
+  if ((rc = host_forward_plan(ctx_, r->c, r->terms, r->want_grad, r->fplan))) return rc;
+  const int64_t crs_f = (int64_t)std::max<size_t>(1, r->fplan.slots.size()) * 8;
+  r->coef_f.resize((size_t)crs_f);
+  build_coefficients<float>(r->c, r->fplan.slots, r->params.data(), 1, crs_f, r->coef_f.data());
+  if (r->want_grad) {
+    if ((rc = host_happly_plan(ctx_, r->c.n, r->terms, r->hplan))) return rc;
+    r->ap = get_adjoint_plan(ctx_, r->c, 0, rc);
+    if (!r->ap) return rc;
+    const int64_t crs_a = (int64_t)std::max<size_t>(1, r->ap->plan.slots.size()) * 8;
+    r->coef_a.resize((size_t)crs_a);
+    build_coefficients<float>(r->c, r->ap->plan.slots, r->params.data(), 1, crs_a, r->coef_a.data());
+    for (int p : r->ap->plan.gslot_param) r->np_used = std::max(r->np_used, p + 1);
+  }
   std::lock_guard<std::mutex> g(mu_);
-  if (stop_) return QSIM_ESHUTDOWN;
-  if (r->footprint > ctx_->opt.hbm_budget_bytes) {
-    st_.rejected++;
-    set_error(ctx_, "request footprint exceeds the memory budget");
-    return QSIM_ETOOBIG;
-  }
-  if (queue_.size() + running_.size() >= (size_t)ctx_->opt.max_queue) {
-    st_.rejected++;
-    return QSIM_EAGAIN;
-  }
+  if ((rc = admissible())) return rc;
   r->ticket = next_ticket_++;
   *ticket = r->ticket;
   r->t_submit = now_s();
@@ -230,100 +292,140 @@ void Server::stats(qsim_server_stats* out) {
   out->running = running_.size();
 }
 
-int Server::prepare(SReq* r) {
-  int rc = QSIM_OK;
-  r->fp = get_dense_plan(ctx_, r->c, r->terms, 0, true, r->want_grad, true, rc);
-  if (!r->fp) return rc;
-  if (r->want_grad) {
-    r->ap = get_grad_plans(ctx_, r->c, r->terms, 0, r->hp, rc);
-    if (!r->ap) return rc;
+// Pinned ring space; when the ring is full, the oldest steps in flight are
+// retired until it fits (nullptr only if it cannot fit at all).
+void* Server::ring_alloc(size_t bytes) {
+  while (true) {
+    void* p = ring_.alloc(bytes);
+    if (p || steps_.empty()) return p;
+    retire(steps_.front());
+    steps_.pop_front();
   }
-  const Plan& F = r->fp->plan;
+}
+
+// Copies host bytes through the pinned ring into device memory, asynchronously
+// on the server stream; the ring space is reclaimed when the current step retires.
+void* Server::stage_upload(const void* src, size_t bytes, void* dst) {
+  if (bytes == 0) return dst;
+  void* h = ring_alloc(bytes);
+  if (!h) return nullptr;
+  std::memcpy(h, src, bytes);
+  if (!mock_ && hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, stream_) != hipSuccess) return nullptr;
+  return dst;
+}
+
+int Server::admit(SReq* r) {
+  r->admitted = true;  // from here on release() gives back whatever was taken
+  auto plan_blocks = [&](const Plan& p, ReqPlan& d) {
+    d.bp = std::max<size_t>(1, p.passes.size()) * sizeof(PassDesc);
+    d.bs = std::max<size_t>(1, p.stages.size()) * sizeof(StageDesc);
+    d.bo = std::max<size_t>(1, p.ops.size()) * sizeof(DevOp);
+    d.P = static_cast<PassDesc*>(pool_.get(d.bp));
+    d.S = static_cast<StageDesc*>(pool_.get(d.bs));
+    d.O = static_cast<DevOp*>(pool_.get(d.bo));
+    return d.P && d.S && d.O;
+  };
+  auto upload_plan = [&](const Plan& p, const ReqPlan& d) {
+    return stage_upload(p.passes.data(), p.passes.size() * sizeof(PassDesc), d.P) &&
+           stage_upload(p.stages.data(), p.stages.size() * sizeof(StageDesc), d.S) &&
+           stage_upload(p.ops.data(), p.ops.size() * sizeof(DevOp), d.O);
+  };
+  const Plan& F = r->fplan;
+  size_t ns = 0;
   r->state_bytes = ((size_t)1 << r->c.n) * 8;
-  const int64_t crs_f = (int64_t)std::max<size_t>(1, F.slots.size()) * 8;
-  r->coef_f_bytes = (size_t)crs_f * sizeof(float);
+  r->cf_bytes = r->coef_f.size() * sizeof(float);
   r->meas_bytes = std::max<size_t>(1, (size_t)F.n_meas << (F.n - F.m)) * sizeof(double);
-  size_t ns = 0, np = r->c.n_params;
+  bool ok = plan_blocks(F, r->df);
+  r->A = pool_.get(r->state_bytes);
+  r->cf = pool_.get(r->cf_bytes);
+  r->meas = static_cast<double*>(pool_.get(r->meas_bytes));
+  ok = ok && r->A && r->cf && r->meas;
   if (r->want_grad) {
     const Plan& P = r->ap->plan;
     ns = P.n_gslots;
-    r->coef_a_bytes = std::max<size_t>(1, P.slots.size()) * 8 * sizeof(float);
+    r->ca_bytes = r->coef_a.size() * sizeof(float);
     r->gpart_bytes = std::max<size_t>(1, ns << (P.n - P.m)) * sizeof(double);
+    ok = plan_blocks(r->hplan, r->dh) && ok;
+    r->B = pool_.get(r->state_bytes);
+    r->ca = pool_.get(r->ca_bytes);
+    r->gpart = static_cast<double*>(pool_.get(r->gpart_bytes));
+    ok = ok && r->B && r->ca && r->gpart;
   }
-  r->res_bytes = (1 + ns + np) * sizeof(double);
-  r->A = pool_.get(r->state_bytes);
-  if (r->want_grad) r->B = pool_.get(r->state_bytes);
-  r->coef_f = pool_.get(r->coef_f_bytes);
-  if (r->want_grad) r->coef_a = pool_.get(r->coef_a_bytes);
-  r->meas = (double*)pool_.get(r->meas_bytes);
-  if (r->want_grad) r->gpart = (double*)pool_.get(r->gpart_bytes);
-  r->res = (double*)pool_.get(r->res_bytes);
-  r->prepared = true;
-  if (!r->A || (r->want_grad && (!r->B || !r->coef_a || !r->gpart)) || !r->coef_f || !r->meas || !r->res) {
+  r->res_bytes = (1 + ns + (size_t)r->c.n_params) * sizeof(double);
+  r->res = static_cast<double*>(pool_.get(r->res_bytes));
+  if (!ok || !r->res) {
     set_error(ctx_, "serving: device allocation failed");
     return QSIM_ENOMEM;
   }
-  r->h_coef_f.resize((size_t)crs_f);
-  build_coefficients<float>(r->c, F.slots, r->params.data(), 1, crs_f, r->h_coef_f.data());
-  if (r->want_grad) {
-    const int64_t crs_a = (int64_t)std::max<size_t>(1, r->ap->plan.slots.size()) * 8;
-    r->h_coef_a.resize((size_t)crs_a);
-    build_coefficients<float>(r->c, r->ap->plan.slots, r->params.data(), 1, crs_a, r->h_coef_a.data());
+  bool up = upload_plan(F, r->df) && stage_upload(r->coef_f.data(), r->cf_bytes, r->cf);
+  if (up && r->want_grad) up = upload_plan(r->hplan, r->dh) && stage_upload(r->coef_a.data(), r->ca_bytes, r->ca);
+  if (!up) {
+    set_error(ctx_, "serving: staging upload failed");
+    return QSIM_ENOMEM;
   }
-  if (!mock_) {
-    if (hipMemcpyAsync(r->coef_f, r->h_coef_f.data(), r->coef_f_bytes, hipMemcpyHostToDevice, stream_) != hipSuccess)
-      return hip_fail(ctx_, hipGetLastError(), "serving coefficient upload");
-    if (r->want_grad &&
-        hipMemcpyAsync(r->coef_a, r->h_coef_a.data(), r->coef_a_bytes, hipMemcpyHostToDevice, stream_) != hipSuccess)
-      return hip_fail(ctx_, hipGetLastError(), "serving coefficient upload");
-  }
-  r->h_res.assign(1 + np, 0.0);
+  r->phase = PH_FWD;
+  r->next = 0;
   return QSIM_OK;
 }
 
 void Server::release(SReq* r) {
-  if (!r->prepared) return;
+  if (!r->admitted) return;
+  for (ReqPlan* d : {&r->df, &r->dh}) {
+    pool_.put(d->P, d->bp);
+    pool_.put(d->S, d->bs);
+    pool_.put(d->O, d->bo);
+    *d = ReqPlan();
+  }
   pool_.put(r->A, r->state_bytes);
   pool_.put(r->B, r->state_bytes);
-  pool_.put(r->coef_f, r->coef_f_bytes);
-  pool_.put(r->coef_a, r->coef_a_bytes);
+  pool_.put(r->cf, r->cf_bytes);
+  pool_.put(r->ca, r->ca_bytes);
   pool_.put(r->meas, r->meas_bytes);
   pool_.put(r->gpart, r->gpart_bytes);
   pool_.put(r->res, r->res_bytes);
-  r->A = r->B = r->coef_f = r->coef_a = nullptr;
+  r->A = r->B = r->cf = r->ca = nullptr;
   r->meas = r->gpart = r->res = nullptr;
-  r->prepared = false;
-  r->fp.reset();
-  r->hp.reset();
-  r->ap.reset();
+  r->h_res = nullptr;
+  r->admitted = false;
   // keep the pool within the memory budget
   const size_t budget = ctx_->opt.hbm_budget_bytes;
   const size_t limit = budget > inflight_ ? budget - inflight_ : 0;
   if (pool_.cached() > limit) pool_.trim(limit);
 }
 
-// Launch one pass for every running request; returns false on a device error.
-bool Server::step(std::vector<SReq*>& run) {
-  std::vector<PassItem> single, dual;
+// Launches the next pass of every request in 'run' (one multi-request launch
+// per kernel kind).  Requests whose last pass this was get their reductions and
+// result copies queued behind it and move to st.finishing; 'run' keeps the rest.
+int Server::launch_step(std::vector<SReq*>& run, Step& st) {
+  std::vector<PassItem> single, dual;  // single-state (forward) and dual-state passes
   int64_t tiles_s = 0, tiles_d = 0;
   int m_s = 4, m_d = 4, r_s = 0, r_d = 0;
+  std::vector<SReq*> still;
   for (SReq* r : run) {
-    r->ended = -1;
-    if (r->failed || r->cancelled || r->phase == PH_DONE) continue;
-    const DevPlan* dp = r->phase == PH_FWD ? r->fp.get() : r->phase == PH_HAPPLY ? r->hp.get() : r->ap.get();
-    const Plan& P = dp->plan;
-    const int p = r->next;
+    if (r->failed || r->cancelled) {
+      st.finishing.push_back(r);
+      continue;
+    }
+    const bool fwd = r->phase == PH_FWD;
+    const Plan& P = fwd ? r->fplan : r->phase == PH_HAPPLY ? r->hplan : r->ap->plan;
     PassItem it;
-    it.pass = dp->d_passes + p;
-    it.stages = dp->d_stages;
-    it.ops = dp->d_ops;
+    if (r->phase == PH_ADJ) {
+      it.pass = r->ap->d_passes + r->next;
+      it.stages = r->ap->d_stages;
+      it.ops = r->ap->d_ops;
+    } else {
+      const ReqPlan& d = fwd ? r->df : r->dh;
+      it.pass = d.P + r->next;
+      it.stages = d.S;
+      it.ops = d.O;
+    }
     it.A = r->A;
     it.B = r->B;
-    it.coef = r->phase == PH_FWD ? r->coef_f : r->coef_a;
+    it.coef = fwd ? r->cf : r->ca;
     it.meas = r->meas;
     it.grad = r->gpart;
     const int64_t tiles = 1ll << (P.n - P.m);
-    if (r->phase == PH_FWD) {
+    if (fwd) {
       it.tile_begin = tiles_s;
       tiles_s += tiles;
       m_s = std::max(m_s, P.m);
@@ -337,65 +439,132 @@ bool Server::step(std::vector<SReq*>& run) {
       dual.push_back(it);
     }
     r->passes_done++;
-    if (++r->next == (int)P.passes.size()) r->ended = r->phase;
-  }
-  if (mock_) return true;
-  items_.clear();
-  items_.insert(items_.end(), single.begin(), single.end());
-  items_.insert(items_.end(), dual.begin(), dual.end());
-  if (items_.empty()) return true;
-  const size_t bytes = items_.size() * sizeof(PassItem);
-  if (ws_.h_out.ensure(bytes) != hipSuccess || d_items_.ensure(bytes) != hipSuccess) return false;
-  // the previous step synchronised the stream, so the pinned staging buffer is free
-  std::memcpy(ws_.h_out.p, items_.data(), bytes);
-  if (hipMemcpyAsync(d_items_.p, ws_.h_out.p, bytes, hipMemcpyHostToDevice, stream_) != hipSuccess) return false;
-  const PassItem* d = reinterpret_cast<const PassItem*>(d_items_.p);
-  if (launch_pass_multi(d, (int)single.size(), tiles_s, m_s, r_s, 0, 0, stream_) != hipSuccess) return false;
-  if (launch_pass_multi(d + single.size(), (int)dual.size(), tiles_d, m_d, r_d, 0, 1, stream_) != hipSuccess)
-    return false;
-  st_.launches += (single.empty() ? 0 : 1) + (dual.empty() ? 0 : 1);
-  // reductions of requests whose phase ended in this step
-  for (SReq* r : run) {
-    if (r->ended == PH_FWD) {
-      const Plan& F = r->fp->plan;
-      if (launch_reduce_rows(r->meas, 1, (int64_t)F.n_meas << (F.n - F.m), F.const_term, r->res, stream_) !=
-          hipSuccess)
-        return false;
-      if (!r->want_grad &&
-          hipMemcpyAsync(r->h_res.data(), r->res, sizeof(double), hipMemcpyDeviceToHost, stream_) != hipSuccess)
-        return false;
-    } else if (r->ended == PH_ADJ) {
-      const Plan& P = r->ap->plan;
-      const int ns = P.n_gslots, np = r->c.n_params;
-      double* slot_total = r->res + 1;
-      double* g = r->res + 1 + ns;
-      if (ns > 0) {
-        if (launch_reduce_rows(r->gpart, ns, 1ll << (P.n - P.m), 0.0, slot_total, stream_) != hipSuccess) return false;
-        int np_used = 0;
-        for (int p : P.gslot_param) np_used = std::max(np_used, p + 1);
-        if (launch_grad_scatter(slot_total, 1, ns, r->ap->d_poff, r->ap->d_pslots, np_used, g, stream_) !=
-            hipSuccess)
-          return false;
-        if (hipMemcpyAsync(r->h_res.data() + 1, g, sizeof(double) * np_used, hipMemcpyDeviceToHost, stream_) !=
-            hipSuccess)
-          return false;
-      }
-      (void)np;
-      if (hipMemcpyAsync(r->h_res.data(), r->res, sizeof(double), hipMemcpyDeviceToHost, stream_) != hipSuccess)
-        return false;
+    if (++r->next < (int)P.passes.size()) {
+      still.push_back(r);
+    } else if (r->phase == PH_FWD && r->want_grad) {
+      r->phase = PH_HAPPLY;
+      r->next = 0;
+      still.push_back(r);
+    } else if (r->phase == PH_HAPPLY) {
+      r->phase = PH_ADJ;
+      r->next = 0;
+      still.push_back(r);
+    } else {
+      r->phase = PH_DONE;
+      st.finishing.push_back(r);
     }
   }
-  return hipStreamSynchronize(stream_) == hipSuccess;
+  const size_t n_single = single.size();
+  std::vector<PassItem>& items = single;
+  items.insert(items.end(), dual.begin(), dual.end());
+  run.swap(still);
+  if (!mock_ && !items.empty()) {
+    const size_t bytes = items.size() * sizeof(PassItem);
+    if (d_items_.bytes < bytes) {
+      // earlier steps may still read the buffer
+      if (hipStreamSynchronize(stream_) != hipSuccess || d_items_.ensure(2 * bytes) != hipSuccess)
+        return QSIM_EDEVICE;
+    }
+    // steps run in stream order, so this copy lands after the previous step's kernels
+    if (!stage_upload(items.data(), bytes, d_items_.p)) return QSIM_ENOMEM;
+    const PassItem* d = static_cast<const PassItem*>(d_items_.p);
+    const int n_dual = (int)(items.size() - n_single);
+    if (n_single && launch_pass_multi(d, (int)n_single, tiles_s, m_s, r_s, 0, 0, stream_) != hipSuccess)
+      return QSIM_EDEVICE;
+    if (n_dual && launch_pass_multi(d + n_single, n_dual, tiles_d, m_d, r_d, 0, 1, stream_) != hipSuccess)
+      return QSIM_EDEVICE;
+    st_.launches += (n_single ? 1 : 0) + (n_dual ? 1 : 0);
+  }
+  if (!mock_) {
+    for (SReq* r : st.finishing) {
+      if (r->failed || r->cancelled || r->phase != PH_DONE) continue;
+      r->h_res = static_cast<double*>(ring_alloc((1 + (size_t)r->np_used) * sizeof(double)));
+      if (!r->h_res) return QSIM_ENOMEM;
+      const Plan& F = r->fplan;
+      if (launch_reduce_rows(r->meas, 1, (int64_t)F.n_meas << (F.n - F.m), F.const_term, r->res, stream_) !=
+          hipSuccess)
+        return QSIM_EDEVICE;
+      if (r->want_grad && r->np_used > 0) {
+        const Plan& P = r->ap->plan;
+        const int ns = P.n_gslots;
+        double* slot_total = r->res + 1;
+        double* g = r->res + 1 + ns;
+        if (launch_reduce_rows(r->gpart, ns, 1ll << (P.n - P.m), 0.0, slot_total, stream_) != hipSuccess ||
+            launch_grad_scatter(slot_total, 1, ns, r->ap->d_poff, r->ap->d_pslots, r->np_used, g, stream_) !=
+                hipSuccess ||
+            hipMemcpyAsync(r->h_res + 1, g, sizeof(double) * r->np_used, hipMemcpyDeviceToHost, stream_) !=
+                hipSuccess)
+          return QSIM_EDEVICE;
+      }
+      if (hipMemcpyAsync(r->h_res, r->res, sizeof(double), hipMemcpyDeviceToHost, stream_) != hipSuccess)
+        return QSIM_EDEVICE;
+    }
+    if (free_events_.empty()) {
+      hipEvent_t e;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return QSIM_EDEVICE;
+      free_events_.push_back(e);
+    }
+    st.ev = free_events_.back();
+    free_events_.pop_back();
+    if (hipEventRecord(st.ev, stream_) != hipSuccess) return QSIM_EDEVICE;
+  }
+  return QSIM_OK;
+}
+
+// Waits for a step's work and publishes the requests that finished in it.
+void Server::retire(Step& st) {
+  bool ok = ok_;
+  if (!mock_ && st.ev) {
+    ok = ok && hipEventSynchronize(st.ev) == hipSuccess;
+    free_events_.push_back(st.ev);
+    st.ev = nullptr;
+  }
+  if (!ok) ok_ = false;
+  std::lock_guard<std::mutex> g(mu_);
+  st_.steps++;
+  for (SReq* r : st.finishing) {
+    if (!ok && !r->failed) {
+      r->failed = true;
+      r->status = QSIM_EDEVICE;
+    }
+    if (r->failed) {
+      st_.failed++;
+    } else if (r->cancelled) {
+      r->status = QSIM_ECANCELED;
+      st_.cancelled++;
+    } else {
+      r->status = QSIM_OK;
+      r->E = mock_ ? (double)r->passes_done : r->h_res[0];
+      if (r->want_grad) {
+        r->grad.assign(r->c.n_params, 0.0);
+        if (!mock_)
+          for (int k = 0; k < r->np_used; ++k) r->grad[k] = r->h_res[1 + k];
+      }
+      st_.completed++;
+    }
+    inflight_ -= r->footprint;
+    release(r);
+    r->t_done = now_s();
+    r->done = true;
+  }
+  // everything staged up to this step's launch has been consumed
+  ring_.release_to(st.ring_mark);
 }
 
 void Server::loop() {
   if (!mock_) (void)hipSetDevice(ctx_->device);
   const size_t budget = ctx_->opt.hbm_budget_bytes;
+  auto retire_front = [&] {
+    retire(steps_.front());
+    steps_.pop_front();
+  };
+  std::vector<SReq*> run;  // admitted requests still launching passes (scheduler-owned copy of running_)
   while (true) {
-    std::vector<SReq*> fresh, run;
+    while (!steps_.empty() && (mock_ || hipEventQuery(steps_.front().ev) != hipErrorNotReady)) retire_front();
+    std::vector<SReq*> fresh;
     {
       std::unique_lock<std::mutex> lk(mu_);
-      cv_.wait(lk, [&] { return stop_ || !queue_.empty() || !running_.empty(); });
+      if (run.empty() && steps_.empty()) cv_.wait(lk, [&] { return stop_ || !queue_.empty(); });
       if (stop_) break;
       while (!queue_.empty() && running_.size() < kMaxRunning) {
         SReq* r = queue_.front();
@@ -407,69 +576,33 @@ void Server::loop() {
         r->t_admit = now_s();
         fresh.push_back(r);
       }
-      run = running_;
     }
     for (SReq* r : fresh) {
-      const int rc = prepare(r);
+      const int rc = admit(r);
       if (rc) {
         r->failed = true;
         r->status = rc;
       }
+      run.push_back(r);
     }
-    const bool ok = step(run);
-    std::lock_guard<std::mutex> g(mu_);
-    st_.steps++;
-    for (SReq* r : run) {
-      if (!ok && !r->failed) {
-        r->failed = true;
-        r->status = QSIM_EDEVICE;
+    if (!run.empty()) {
+      Step st;
+      if (launch_step(run, st) != QSIM_OK) ok_ = false;
+      st.ring_mark = ring_.mark();
+      {
+        std::lock_guard<std::mutex> g(mu_);
+        for (SReq* r : st.finishing) running_.erase(std::find(running_.begin(), running_.end(), r));
       }
-      if (!r->failed && !r->cancelled) {
-        if (r->ended == PH_FWD) {
-          if (r->want_grad) {
-            r->phase = PH_HAPPLY;
-            r->next = 0;
-          } else {
-            r->phase = PH_DONE;
-          }
-        } else if (r->ended == PH_HAPPLY) {
-          r->phase = PH_ADJ;
-          r->next = 0;
-        } else if (r->ended == PH_ADJ) {
-          r->phase = PH_DONE;
-        }
-      }
-      const bool finished = r->failed || r->cancelled || r->phase == PH_DONE;
-      if (!finished) continue;
-      if (r->failed) {
-        st_.failed++;
-      } else if (r->cancelled) {
-        r->status = QSIM_ECANCELED;
-        st_.cancelled++;
-      } else {
-        r->status = QSIM_OK;
-        r->E = mock_ ? (double)r->passes_done : r->h_res[0];
-        if (r->want_grad) {
-          r->grad.assign(r->c.n_params, 0.0);
-          if (!mock_) {
-            int np_used = 0;
-            for (int p : r->ap->plan.gslot_param) np_used = std::max(np_used, p + 1);
-            for (int k = 0; k < np_used; ++k) r->grad[k] = r->h_res[1 + k];
-          }
-        }
-        st_.completed++;
-      }
-      inflight_ -= r->footprint;
-      release(r);
-      r->t_done = now_s();
-      r->done = true;
-      running_.erase(std::find(running_.begin(), running_.end(), r));
+      steps_.push_back(std::move(st));
     }
+    // bound the steps in flight; with nothing left to launch, wait for the oldest
+    if (!steps_.empty() && (mock_ || steps_.size() >= kMaxSteps || run.empty())) retire_front();
   }
-  // shutdown: everything still pending ends with ESHUTDOWN
+  // shutdown: launched work finishes normally, everything else ends with ESHUTDOWN
+  while (!steps_.empty()) retire_front();
   std::lock_guard<std::mutex> g(mu_);
-  if (!mock_) (void)hipStreamSynchronize(stream_);
   for (SReq* r : running_) {
+    inflight_ -= r->footprint;
     release(r);
     r->done = true;
     r->status = QSIM_ESHUTDOWN;
