@@ -17,6 +17,9 @@ product simulator, Clifford Pauli propagation, the parameter-shift identity):
 ``expect_lightcone``        equal to the dense value (n<=14), Clifford n=500
 ``grad_psr`` / ``grad_fd``  single-parameter trigonometric identity (exact
                             shift rule; FD = derivative * sin h / h)
+``grad_psr_lightcone``      equal to ``grad_psr`` (n<=12), closed-form
+                            product-state gradient and Clifford shift rule
+                            at n=500
 ==========================  ================================================
 
 The C source ``qsim_oracle.c`` is compiled here with gcc (``build()``).
@@ -200,6 +203,22 @@ def expect_lightcone(c, h, theta, max_cone: int = 24):
     _check(lib.oracle_expect_lightcone(*ca, *ha, _p(th, ctypes.c_double), ctypes.c_int(max_cone),
                                        _p(tv, ctypes.c_double), ctypes.byref(tot)), "expect_lightcone")
     return float(tot.value), tv[: h.n_terms]
+
+
+def grad_psr_lightcone(c, h, theta, idx, max_cone: int = 24) -> np.ndarray:
+    """Parameter-shift derivative for the listed parameters, every term on its canonical light cone."""
+    lib = _load()
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1)
+    if th.size == 0:
+        th = np.zeros(1)
+    ix = np.ascontiguousarray(idx, dtype=np.int32)
+    ca, k1 = _circ_args(c)
+    ha, k2 = _ham_args(h)
+    g = np.zeros(max(ix.size, 1))
+    _check(lib.oracle_grad_psr_lightcone(*ca, *ha, _p(th, ctypes.c_double), ctypes.c_int(max_cone),
+                                         ctypes.c_int(ix.size), _p(ix, ctypes.c_int32), _p(g, ctypes.c_double)),
+           "grad_psr_lightcone")
+    return g[: ix.size]
 
 
 if __name__ == "__main__":  # pragma: no cover

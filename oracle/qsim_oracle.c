@@ -517,3 +517,85 @@ int oracle_expect_lightcone(CIRCUIT_ARGS, HAM_ARGS, const double* theta, int max
     free(sm);
     return rc;
 }
+
+/* Parameter-shift gradient with every term evaluated on its canonical light
+ * cone (Sec. 3's full gradient of <H>; Sec. 4's causality-based contraction).
+ * A gate outside a term's cone cannot change that term, so for each listed
+ * parameter idx[k] and every gate g that uses it, only the terms whose cone
+ * contains g are re-evaluated, on their cones, with g's angle shifted by
+ * +-pi/2: grad[k] = sum of c_t (<P_t>(+) - <P_t>(-)) / 2.  max_cone bounds the
+ * cone size. */
+int oracle_grad_psr_lightcone(CIRCUIT_ARGS, HAM_ARGS, const double* theta, int max_cone, int n_idx,
+                              const int32_t* idx, double* grad) {
+    const circuit_t c = CIRCUIT_INIT;
+    const hamiltonian_t h = HAM_INIT;
+    if (check_circuit(&c, n_params, 1 << 24) != OK || check_hamiltonian(&h, n) != OK) return EINVAL_;
+    for (int k = 0; k < n_idx; ++k) {
+        if (idx[k] < 0 || idx[k] >= n_params) return EINVAL_;
+        grad[k] = 0.0;
+    }
+    const size_t ng = (size_t)(n_gates > 0 ? n_gates : 1);
+    uint8_t* in_set = (uint8_t*)malloc((size_t)n);
+    uint8_t* in_cone = (uint8_t*)malloc(ng);
+    int32_t* label = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    uint8_t* sk = (uint8_t*)malloc(ng);
+    int32_t* sq0 = (int32_t*)malloc(sizeof(int32_t) * ng);
+    int32_t* sq1 = (int32_t*)malloc(sizeof(int32_t) * ng);
+    int32_t* sp = (int32_t*)malloc(sizeof(int32_t) * ng);
+    double* sa = (double*)malloc(sizeof(double) * ng);
+    double* sm = (double*)malloc(sizeof(double) * 8 * ng);
+    int32_t tq[64];
+    int rc = OK;
+    for (int t = 0; t < n_terms && rc == OK; ++t) {
+        const int a = term_off[t], b = term_off[t + 1];
+        if (b == a) continue; /* identity: no dependence on the parameters */
+        light_cone(&c, b - a, qubits + a, in_set, in_cone);
+        int s = 0;
+        for (int q = 0; q < n; ++q) label[q] = in_set[q] ? s++ : -1;
+        if (s > max_cone || b - a > 64) {
+            rc = -3;
+            break;
+        }
+        int sg = 0;
+        for (int g = 0; g < n_gates; ++g) {
+            if (!in_cone[g]) continue;
+            sk[sg] = kind[g];
+            sq0[sg] = label[q0[g]];
+            sq1[sg] = (kind[g] == K_CZ || kind[g] == K_CNOT) ? label[q1[g]] : -1;
+            sp[sg] = param[g];
+            sa[sg] = angle[g];
+            if (mat) memcpy(sm + 8 * (size_t)sg, mat + 8 * (size_t)g, sizeof(double) * 8);
+            else memset(sm + 8 * (size_t)sg, 0, sizeof(double) * 8);
+            ++sg;
+        }
+        for (int k = a; k < b; ++k) tq[k - a] = label[qubits[k]];
+        const circuit_t sub = {s, sg, sk, sq0, sq1, sp, sa, sm};
+        cplx* psi = (cplx*)malloc(sizeof(cplx) * ((size_t)1 << s));
+        if (!psi) {
+            rc = ENOMEM_;
+            break;
+        }
+        for (int g = 0; g < sg; ++g) {
+            if (sp[g] < 0 || !(sk[g] == K_RX || sk[g] == K_RY || sk[g] == K_RZ)) continue;
+            for (int k = 0; k < n_idx; ++k) {
+                if (idx[k] != sp[g]) continue;
+                run_gates(&sub, theta, g, +M_PI / 2, psi);
+                const double ep = creal(pauli_expect(s, psi, b - a, tq, paulis + a));
+                run_gates(&sub, theta, g, -M_PI / 2, psi);
+                const double em = creal(pauli_expect(s, psi, b - a, tq, paulis + a));
+                grad[k] += coeff[t] * 0.5 * (ep - em);
+            }
+        }
+        free(psi);
+    }
+    free(in_set);
+    free(in_cone);
+    free(label);
+    free(sk);
+    free(sq0);
+    free(sq1);
+    free(sp);
+    free(sa);
+    free(sm);
+    return rc;
+}

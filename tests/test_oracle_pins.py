@@ -310,6 +310,53 @@ def test_p11_shift_rule_and_fd(oracle_mod):
         assert psr[k] == pytest.approx(deriv, abs=1e-11)
 
 
+@pytest.mark.parametrize("fam", ["ry_cz_maxcut", "ry_rz_cnot_tfim"])
+def test_p11_lightcone_gradient_equals_dense(oracle_mod, fam):
+    """Light-cone parameter shift = full-state parameter shift (itself pinned by the trigonometric form)."""
+    if fam == "ry_cz_maxcut":
+        c = W.brickwork_ry_cz(12, 4)
+        H = W.maxcut(W.random_regular3(12, np.random.default_rng([3, 12])))
+    else:
+        c = W.brickwork_ry_rz_cnot(10, 3)
+        H = W.tfim(10, 0.7)
+    th = W.angles(c.n_params, [3, 12, 2])
+    idx = np.arange(c.n_params, dtype=np.int32)
+    np.testing.assert_allclose(oracle_mod.grad_psr_lightcone(c, H, th, idx), oracle_mod.grad_psr(c, H, th),
+                               atol=1e-11)
+
+
+def test_p11_lightcone_gradient_product_state_n500(oracle_mod):
+    """One RY layer on 500 qubits: <Z_i Z_j> = cos t_i cos t_j, so d<H>/dt_i = -sin t_i sum_j~i cos t_j."""
+    n = 500
+    b = W.GateListBuilder(n)
+    for q in range(n):
+        b.rot(W.RY, q)
+    c = b.build()
+    edges = W.random_regular3(n, np.random.default_rng([3, 0]))
+    H = W.maxcut(edges)
+    th = W.angles(n, [3, 500, 7])
+    idx = np.array([0, 17, 250, 499], dtype=np.int32)
+    got = oracle_mod.grad_psr_lightcone(c, H, th, idx)
+    for k, i in enumerate(idx):
+        nb = [int(b_) for a_, b_ in edges if a_ == i] + [int(a_) for a_, b_ in edges if b_ == i]
+        want = -math.sin(th[i]) * sum(math.cos(th[j]) for j in nb)
+        assert got[k] == pytest.approx(want, abs=1e-12)
+
+
+def test_p11_lightcone_gradient_clifford_n500(oracle_mod):
+    """At Clifford angles both shifted points are Clifford: the shift rule from Heisenberg propagation."""
+    w = W.lightcone_maxcut()
+    th = pinlib.clifford_angles(w.circuit.n_params, np.random.default_rng([11, 501]))
+    idx = np.array([640, 1998], dtype=np.int32)
+    got = oracle_mod.grad_psr_lightcone(w.circuit, w.H, th, idx)
+    for k, j in enumerate(idx):
+        tp, tm = th.copy(), th.copy()
+        tp[j] += math.pi / 2
+        tm[j] -= math.pi / 2
+        want = 0.5 * (pinlib.clifford_expect(w.circuit, w.H, tp) - pinlib.clifford_expect(w.circuit, w.H, tm))
+        assert got[k] == pytest.approx(want, abs=1e-10)
+
+
 def test_p11_full_gradient_vs_kronecker_product_rule(oracle_mod):
     """dE/dtheta_j by differentiating the Kronecker matrix product directly (d/dt exp(-itP/2) = -i P/2 exp(...))."""
     rng = np.random.default_rng(12)
