@@ -160,6 +160,19 @@ int qsim_expect_grad(qsim_ctx* ctx, const qsim_circuit* c, const double* params,
                      const qsim_hamiltonian* H, int dtype, void* stream, qsim_state* saved, double* E,
                      double* grad);
 
+/* E[b] = <H> and grad[b*n_params + j] = d<H>/dtheta_j (float64, host) for b < batch,
+ * with every term evaluated on light cones instead of the full state (Sec. 3's
+ * forward value and full gradient; Sec. 4's causality-based contraction), so n may
+ * be in the hundreds.  mode: QSIM_MODE_LIGHTCONE (each term on its canonical cone)
+ * or QSIM_MODE_LIGHTCONE_FACTORED / QSIM_MODE_AUTO (Z-string terms split into
+ * disjoint pruned factors, shared across terms).  Inside each cone the gradient is
+ * taken by the adjoint method; per-cone parameter gradients are weighted by
+ * d<H>/d<cone> and summed per parameter on the device in a fixed order.  params,
+ * E and grad are host buffers owned by the caller; E may be NULL.  Errors as for
+ * qsim_expect_circuit; QSIM_ETOOBIG when a cone exceeds the context's cone_cap. */
+int qsim_expect_grad_cones(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
+                           const qsim_hamiltonian* H, int mode, int dtype, void* stream, double* E, double* grad);
+
 /* ---- light cones (Sec. 4: causality-simplified contraction) ------------------------- */
 
 /* Canonical light-cone qubit sets, ascending, term by term: set t is

@@ -48,3 +48,35 @@ class Expectation(torch.autograd.Function):
 def expectation(theta: torch.Tensor, engine: "qsim.Context", circuit, hamiltonian) -> torch.Tensor:
     """Differentiable <H>; theta [B, P] -> [B]."""
     return Expectation.apply(theta, engine, circuit, hamiltonian)
+
+
+class ExpectationCones(torch.autograd.Function):
+    """E[b] for theta of shape [B, P] with every term on light cones (n in the hundreds).
+
+    When theta needs a gradient, the forward call already runs the adjoint sweep
+    inside every cone (it costs little more than the cones' forward pass) and the
+    backward only applies the chain rule."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, engine: "qsim.Context", circuit, hamiltonian, mode: int):
+        th = theta.detach().to("cpu", torch.float64).contiguous().numpy().reshape(theta.shape[0], -1)
+        stream = _stream_handle(theta)
+        if theta.requires_grad:
+            E, g = engine.expect_grad(circuit, hamiltonian, th, dtype=qsim.C64, stream=stream, mode=mode)
+            ctx.grad = np.asarray(g).reshape(th.shape)
+        else:
+            E = engine.expect_circuit(circuit, hamiltonian, th, mode=mode, dtype=qsim.C64, stream=stream)
+            ctx.grad = None
+        return torch.as_tensor(np.asarray(E, dtype=np.float64).reshape(-1), device=theta.device).to(theta.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_E: torch.Tensor):
+        g = torch.as_tensor(ctx.grad, device=grad_E.device, dtype=grad_E.dtype)
+        ctx.grad = None
+        return grad_E.reshape(-1, 1) * g, None, None, None, None
+
+
+def expectation_cones(theta: torch.Tensor, engine: "qsim.Context", circuit, hamiltonian,
+                      mode: int = qsim.MODE_LIGHTCONE_FACTORED) -> torch.Tensor:
+    """Differentiable <H> evaluated on light cones; theta [B, P] -> [B]."""
+    return ExpectationCones.apply(theta, engine, circuit, hamiltonian, mode)

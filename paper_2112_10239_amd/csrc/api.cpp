@@ -307,6 +307,40 @@ int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* para
   return QSIM_OK;
 }
 
+int qsim_expect_grad_cones(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
+                           const qsim_hamiltonian* H, int mode, int dtype, void* stream, double* E, double* grad) {
+  if (!ctx || !grad || batch < 1 || !valid_dtype(dtype)) return QSIM_EINVAL;
+  if (mode == QSIM_MODE_AUTO) mode = QSIM_MODE_LIGHTCONE_FACTORED;
+  if (mode != QSIM_MODE_LIGHTCONE && mode != QSIM_MODE_LIGHTCONE_FACTORED) {
+    set_error(ctx, "expect_grad_cones: mode must be LIGHTCONE, LIGHTCONE_FACTORED or AUTO");
+    return QSIM_EINVAL;
+  }
+  if (ctx->mock) return no_device(ctx);
+  CircuitDesc cd;
+  int rc = to_circuit(ctx, c, cd);
+  if (rc) return rc;
+  std::vector<Term> terms;
+  if ((rc = to_terms(ctx, H, cd.n, terms))) return rc;
+  if (cd.n_params > 0 && !params) {
+    set_error(ctx, "expect_grad_cones: params missing");
+    return QSIM_EINVAL;
+  }
+  const int c128 = dtype == QSIM_C128;
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  hipStream_t st = pick_stream(ctx, stream);
+  auto dp = get_factor_plan(ctx, cd, terms, c128, rc, true, mode == QSIM_MODE_LIGHTCONE_FACTORED);
+  if (!dp) return rc;
+  for (int b = 0; b < batch; ++b) {
+    double e = 0;
+    rc = run_cone_grad(ctx, ctx->ws, *dp, cd, params ? params + (size_t)b * cd.n_params : nullptr, c128, st, &e,
+                       grad + (size_t)b * cd.n_params);
+    if (rc) return rc;
+    if (E) E[b] = e;
+  }
+  return QSIM_OK;
+}
+
 int qsim_expect_grad(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch, const qsim_hamiltonian* H,
                      int dtype, void* stream, qsim_state* saved, double* E, double* grad) {
   if (!ctx || batch < 1 || !valid_dtype(dtype) || !grad) return QSIM_EINVAL;

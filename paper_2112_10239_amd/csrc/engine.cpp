@@ -141,6 +141,9 @@ DevPlan::~DevPlan() {
   (void)hipFree(d_toff);
   (void)hipFree(d_tfac);
   (void)hipFree(d_tcoef);
+  (void)hipFree(d_gcone);
+  (void)hipFree(d_foff);
+  (void)hipFree(d_fterms);
 }
 
 template <class V>
@@ -166,6 +169,11 @@ hipError_t DevPlan::upload(bool mock) {
     if ((e = upload_vec(t_off, &d_toff)) != hipSuccess) return e;
     if ((e = upload_vec(t_fac, &d_tfac)) != hipSuccess) return e;
     if ((e = upload_vec(t_coef, &d_tcoef)) != hipSuccess) return e;
+  }
+  if (cone_grad) {
+    if ((e = upload_vec(g_cone, &d_gcone)) != hipSuccess) return e;
+    if ((e = upload_vec(f_off, &d_foff)) != hipSuccess) return e;
+    if ((e = upload_vec(f_terms, &d_fterms)) != hipSuccess) return e;
   }
   if (plan.n_gslots > 0) {
     int np = 0;
@@ -453,19 +461,71 @@ std::shared_ptr<DevPlan> get_adjoint_plan(qsim_ctx* ctx, const CircuitDesc& c, i
   return dp;
 }
 
-// Shared state while packing cones into one plan.
+PlanOptions cone_grad_options(int c128) {
+  PlanOptions o = dual_options(c128);
+  o.r = 4;  // the cone kernel keeps 16 amplitudes per thread and state
+  return o;
+}
+
+// Shared state while packing cones into one plan.  In gradient mode every cone
+// runs forward (measuring its observable with coefficient 1), lambda = P psi,
+// then the adjoint sweep; cone values are weighted on the device afterwards.
 struct ConePacker {
   DevPlan& dp;
   const CircuitDesc& c;
   PlanOptions base;
   int cap;
+  bool grad;
   std::vector<int> relabel;
-  std::map<std::pair<int, std::vector<int>>, int> slot_id;  // shared coefficient table
-  ConePacker(DevPlan& d, const CircuitDesc& cc, int c128, int cap_) : dp(d), c(cc), base(cone_options(c128)), cap(cap_),
-                                                                      relabel(cc.n, -1) {}
+  // shared coefficient table: (kind, inverse, source gates) -> slot
+  std::map<std::tuple<int, bool, std::vector<int>>, int> slot_id;
+  ConePacker(DevPlan& d, const CircuitDesc& cc, int c128, int cap_, bool grad_ = false)
+      : dp(d), c(cc), base(grad_ ? cone_grad_options(c128) : cone_options(c128)), cap(cap_), grad(grad_),
+        relabel(cc.n, -1) {}
 
-  // Adds one cone evaluating coefficient * <obs> on the gates not in 'skip';
-  // returns QSIM_OK or an error code (message in err).
+  // Appends a sub-plan's passes, stages and ops to the packed plan; its
+  // coefficient slots go through the shared table, its gradient slots are
+  // renumbered after the ones already packed and tagged with 'cone'.
+  void append(const Plan& cp, const std::vector<PGate>& slots, int cone) {
+    Plan& all = dp.plan;
+    const int sb = (int)all.stages.size(), ob = (int)all.ops.size(), gb = all.n_gslots;
+    for (PassDesc pd : cp.passes) {
+      pd.stage_begin += sb;
+      pd.stage_end += sb;
+      if (pd.store_stage >= 0) pd.store_stage += sb;
+      pd.grad_begin += gb;
+      all.passes.push_back(pd);
+    }
+    for (StageDesc st : cp.stages) {
+      st.op_begin += ob;
+      st.op_end += ob;
+      all.stages.push_back(st);
+    }
+    std::vector<int> remap(slots.size());
+    for (size_t k = 0; k < slots.size(); ++k) {
+      auto key = std::make_tuple(slots[k].kind, slots[k].inverse, slots[k].srcs);
+      auto it = slot_id.find(key);
+      if (it == slot_id.end()) {
+        it = slot_id.emplace(key, (int)all.slots.size()).first;
+        all.slots.push_back(slots[k]);
+      }
+      remap[k] = it->second;
+    }
+    for (DevOp op : cp.ops) {
+      if (op.type == OP_U || op.type == OP_RY || op.type == OP_PHASE) op.slot = remap[op.slot];
+      if (op.type == OP_GRAD_X || op.type == OP_GRAD_Y || op.type == OP_GRAD_Z) op.slot += gb;
+      all.ops.push_back(op);
+    }
+    for (int g = 0; g < cp.n_gslots; ++g) {
+      all.gslot_param.push_back(cp.gslot_param[g]);
+      dp.g_cone.push_back(cone);
+    }
+    all.n_gslots += cp.n_gslots;
+    dp.cone_m_max = std::max(dp.cone_m_max, cp.m);
+  }
+
+  // Adds one cone evaluating coefficient * <obs> on the gates not in 'skip'
+  // (gradient mode: <obs> alone); returns QSIM_OK or an error code (message in err).
   int add(const Term& obs, const std::vector<char>* skip, std::string& err) {
     Plan& all = dp.plan;
     std::vector<int> support, set, gates;
@@ -487,57 +547,50 @@ struct ConePacker {
       if (x.kind == G_CZ || x.kind == G_CNOT) x.q1 = relabel[x.q1];
       sub.gates.push_back(x);
     }
-    std::vector<PGate> pg, slots, meas;
-    forward_pgates(sub, true, pg, slots);
-    for (auto* v : {&pg, &slots})
-      for (PGate& p : *v)
+    auto to_circuit_gates = [&](std::vector<PGate>& v) {
+      for (PGate& p : v)
         for (int& src : p.srcs) src = gates[src];
+    };
+    std::vector<PGate> pg, slots, meas, hterms;
+    forward_pgates(sub, true, pg, slots);
+    to_circuit_gates(pg);
+    to_circuit_gates(slots);
+    Term unit = obs;
+    if (grad) unit.c = 1.0;
     double cst = 0;
-    term_pgates({obs}, false, meas, cst, &relabel);
+    term_pgates({unit}, false, meas, cst, &relabel);
+    if (grad) term_pgates({unit}, true, hterms, cst, &relabel);
     for (int k = 0; k < s; ++k) relabel[set[k]] = -1;
     PlanOptions o = base;
     o.init = true;
-    o.store_final = false;
+    o.store_final = grad;
     Plan cp;
     if (plan_forward(s_eff, pg, meas, o, cp, err)) return QSIM_EINVAL;
+    const int cone = (int)dp.cones.size();
     ConeDesc cd;
     std::memset(&cd, 0, sizeof(cd));
     cd.pass_begin = (int)all.passes.size();
-    cd.pass_end = cd.pass_begin + (int)cp.passes.size();
     cd.coef_begin = 0;
-    cd.out_index = (int)dp.cones.size();
+    cd.out_index = cone;
     cd.n = s_eff;
-    if (s_eff > cp.m) {
+    if (grad || s_eff > cp.m) {  // gradient cones keep psi and lambda between passes
       cd.scratch_off = dp.scratch_amps;
-      dp.scratch_amps += 1ll << s_eff;
+      dp.scratch_amps += (int64_t)(grad ? 2 : 1) << s_eff;
     }
-    const int sb = (int)all.stages.size(), ob = (int)all.ops.size();
-    for (PassDesc pd : cp.passes) {
-      pd.stage_begin += sb;
-      pd.stage_end += sb;
-      if (pd.store_stage >= 0) pd.store_stage += sb;
-      all.passes.push_back(pd);
+    append(cp, slots, cone);
+    if (grad) {
+      Plan hp, ap;
+      if (plan_happly(s_eff, hterms, base, hp, err)) return QSIM_EINVAL;
+      append(hp, {}, cone);
+      std::vector<PGate> apg, aslots;
+      std::vector<int> gsp;
+      adjoint_pgates(sub, apg, aslots, gsp);
+      to_circuit_gates(apg);
+      to_circuit_gates(aslots);
+      if (plan_adjoint(s_eff, apg, base, ap, err)) return QSIM_EINVAL;
+      append(ap, aslots, cone);
     }
-    for (StageDesc st : cp.stages) {
-      st.op_begin += ob;
-      st.op_end += ob;
-      all.stages.push_back(st);
-    }
-    std::vector<int> remap(slots.size());
-    for (size_t k = 0; k < slots.size(); ++k) {
-      auto key = std::make_pair(slots[k].kind, slots[k].srcs);
-      auto it = slot_id.find(key);
-      if (it == slot_id.end()) {
-        it = slot_id.emplace(key, (int)all.slots.size()).first;
-        all.slots.push_back(slots[k]);
-      }
-      remap[k] = it->second;
-    }
-    for (DevOp op : cp.ops) {
-      if (op.type == OP_U || op.type == OP_RY || op.type == OP_PHASE) op.slot = remap[op.slot];
-      all.ops.push_back(op);
-    }
-    dp.cone_m_max = std::max(dp.cone_m_max, cp.m);
+    cd.pass_end = (int)all.passes.size();
     dp.cones.push_back(cd);
     return QSIM_OK;
   }
@@ -590,13 +643,14 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
 }
 
 std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
-                                         int c128, int& rc) {
+                                         int c128, int& rc, bool grad, bool split) {
   rc = QSIM_OK;
-  const uint64_t key = structure_hash(c, terms, 0x600 | c128);
+  const uint64_t key = structure_hash(c, terms, 0x600 | c128 | (grad ? 2 : 0) | (split ? 0 : 4));
   if (auto p = cache_get(ctx, key)) return p;
   auto dp = std::make_shared<DevPlan>();
   dp->factored = true;
-  ConePacker pk(*dp, c, c128, ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20);
+  dp->cone_grad = grad;
+  ConePacker pk(*dp, c, c128, ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20, grad);
   const std::vector<char> drop = trailing_diagonal(c);
   std::map<std::vector<int>, int> factor_id;  // (pruned flag, qubit*4 + letter ...) -> cone
   auto factor = [&](const Term& obs, bool pruned, std::string& err, int& id) {
@@ -618,7 +672,7 @@ std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, co
       dp->plan.const_term += t.c;
       continue;
     }
-    bool zstring = true;
+    bool zstring = split;
     for (auto [q, L] : t.ops) zstring &= L == 'Z';
     std::string err;
     std::vector<std::vector<std::pair<int, char>>> parts;
@@ -662,6 +716,16 @@ std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, co
     }
     dp->t_off.push_back((int32_t)dp->t_fac.size());
     dp->t_coef.push_back(t.c);
+  }
+  if (grad) {  // factor -> terms that use it, in term order
+    const int F = (int)dp->cones.size(), T = (int)dp->t_coef.size();
+    dp->f_off.assign(F + 1, 0);
+    for (int32_t f : dp->t_fac) dp->f_off[f + 1]++;
+    for (int f = 0; f < F; ++f) dp->f_off[f + 1] += dp->f_off[f];
+    std::vector<int32_t> fill(dp->f_off.begin(), dp->f_off.end() - 1);
+    dp->f_terms.resize(dp->t_fac.size());
+    for (int t = 0; t < T; ++t)
+      for (int k = dp->t_off[t]; k < dp->t_off[t + 1]; ++k) dp->f_terms[fill[dp->t_fac[k]]++] = t;
   }
   pk.finish();
   hipError_t e = dp->upload(ctx->mock);
@@ -851,9 +915,11 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
   L.scratch = ws.scratch.p;
   L.coef = ws.coef.p;
   L.out = (double*)ws.meas.p;
+  L.grad = nullptr;
   L.m_max = dp.cone_m_max;
   L.r = 4;
   L.c128 = c128;
+  L.dual = 0;
   double cone_bytes = 0;  // only cones above the tile size touch HBM scratch
   for (const PassDesc& pd : P.passes)
     if (pd.n > pd.m) cone_bytes += pass_bytes(pd, 1, c128);
@@ -874,6 +940,70 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
             "cone reduce");
   }
   return fetch_out(ctx, ws, 1, st, out_host);
+}
+
+int run_cone_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params,
+                  int c128, hipStream_t st, double* E_host, double* grad_host) {
+  const Plan& P = dp.plan;
+  const int np = c.n_params, ns = P.n_gslots;
+  const size_t nc = dp.cones.size();
+  if (nc == 0) {
+    *E_host = P.const_term;
+    std::memset(grad_host, 0, sizeof(double) * (size_t)np);
+    return QSIM_OK;
+  }
+  int64_t crs = 8;
+  int rc = stage_coefficients(ctx, ws, c, P.slots, params, 1, c128, st, crs);
+  if (rc) return rc;
+  const size_t amp = c128 ? 16 : 8;
+  HIP_TRY(ws.scratch.ensure((size_t)dp.scratch_amps * amp), "cone scratch");
+  HIP_TRY(ws.meas.ensure(nc * sizeof(double)), "cone values");
+  HIP_TRY(ws.grad.ensure((size_t)std::max(1, ns) * sizeof(double)), "cone gradient slots");
+  ConeLaunch L;
+  L.d_cones = dp.d_cones;
+  L.d_order = dp.d_order;
+  L.n_cones = (int)nc;
+  L.d_passes = dp.d_passes;
+  L.d_stages = dp.d_stages;
+  L.d_ops = dp.d_ops;
+  L.scratch = ws.scratch.p;
+  L.coef = ws.coef.p;
+  L.out = (double*)ws.meas.p;
+  L.grad = (double*)ws.grad.p;
+  L.m_max = dp.cone_m_max;
+  L.r = 4;
+  L.c128 = c128;
+  L.dual = 1;
+  double bytes = 0;  // psi and lambda through scratch between a cone's passes
+  for (const PassDesc& pd : P.passes) bytes += pass_bytes(pd, 1, c128);
+  const int ti = timing_begin(ctx, st, bytes, PF_GRAD, 1);
+  HIP_TRY(launch_cones(L, st), "gradient cone launch");
+  timing_end(ctx, ti, st);
+  // E = const + sum_t coef_t prod_f v_f; weights w_f = d<H>/d v_f; grad = sum_slots w g
+  int np_used = 0;
+  for (int p : P.gslot_param) np_used = std::max(np_used, p + 1);
+  const int T = (int)dp.t_coef.size();
+  HIP_TRY(ws.slot_total.ensure((size_t)std::max(1, T) * sizeof(double)), "term values");
+  HIP_TRY(ws.weights.ensure(nc * sizeof(double)), "factor weights");
+  HIP_TRY(ws.out.ensure((size_t)(1 + np_used) * sizeof(double)), "result buffer");
+  double* out = (double*)ws.out.p;
+  const double* fval = (const double*)ws.meas.p;
+  HIP_TRY(launch_term_products(fval, dp.d_toff, dp.d_tfac, dp.d_tcoef, T, (double*)ws.slot_total.p, st),
+          "term products");
+  HIP_TRY(launch_reduce_rows((const double*)ws.slot_total.p, 1, T, P.const_term, out, st), "term reduce");
+  HIP_TRY(launch_factor_weights(fval, dp.d_foff, dp.d_fterms, dp.d_toff, dp.d_tfac, dp.d_tcoef, (int)nc,
+                                (double*)ws.weights.p, st),
+          "factor weights");
+  if (np_used > 0)
+    HIP_TRY(launch_weighted_scatter((const double*)ws.grad.p, dp.d_gcone, (const double*)ws.weights.p, dp.d_poff,
+                                    dp.d_pslots, np_used, out + 1, st),
+            "gradient scatter");
+  std::vector<double> tmp((size_t)(1 + np_used));
+  if ((rc = fetch_out(ctx, ws, tmp.size(), st, tmp.data()))) return rc;
+  *E_host = tmp[0];
+  std::memcpy(grad_host, tmp.data() + 1, sizeof(double) * (size_t)np_used);
+  std::memset(grad_host + np_used, 0, sizeof(double) * (size_t)(np - np_used));
+  return QSIM_OK;
 }
 
 }  // namespace qsim

@@ -84,12 +84,18 @@ struct DevPlan {
   int32_t* d_toff = nullptr;
   int32_t* d_tfac = nullptr;
   double* d_tcoef = nullptr;
+  // light-cone gradients: gradient slot -> factor, factor -> terms (CSR)
+  bool cone_grad = false;
+  std::vector<int32_t> g_cone, f_off, f_terms;
+  int32_t* d_gcone = nullptr;
+  int32_t* d_foff = nullptr;
+  int32_t* d_fterms = nullptr;
   ~DevPlan();
   hipError_t upload(bool mock);
 };
 
 struct Workspace {
-  DevBuf coef, meas, grad, slot_total, out, scratch, lambda;
+  DevBuf coef, meas, grad, slot_total, out, scratch, lambda, weights;
   HostBuf h_coef, h_out;
   void release() {
     coef.release();
@@ -99,6 +105,7 @@ struct Workspace {
     out.release();
     scratch.release();
     lambda.release();
+    weights.release();
     h_coef.release();
     h_out.release();
   }
@@ -168,8 +175,10 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
                                        int c128, int& rc);
 // Light cones after dropping trailing diagonal gates (Z-string terms) and
 // splitting terms into factors with disjoint cones, shared across terms.
+// Factored light cones (split = true: Z-string terms split into disjoint pruned
+// factors; false: one canonical cone per term).  grad = true packs gradient cones.
 std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
-                                         int c128, int& rc);
+                                         int c128, int& rc, bool grad = false, bool split = true);
 
 // Run a dense plan on states A (and B) with 'rows' rows; coefficients from params.
 int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params, int rows,
@@ -178,6 +187,9 @@ int run_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& hp, const DevPlan& ap,
              const double* params, int rows, int c128, void* A, void* B, hipStream_t st, double* grad_host);
 int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params, int c128,
               hipStream_t st, double* out_host);
+// <H> and its gradient from a gradient cone plan (one parameter row).
+int run_cone_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params,
+                  int c128, hipStream_t st, double* E_host, double* grad_host);
 
 // Launch bracketing for qsim_timing_*: returns the record index or -1.
 int timing_begin(qsim_ctx* ctx, hipStream_t st, double bytes, int flags, int kind, double flops = 0);

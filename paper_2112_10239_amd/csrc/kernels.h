@@ -41,9 +41,11 @@ struct ConeLaunch {
   void* scratch;            // cone states with more than m qubits
   const void* coef;         // slots of all cones
   double* out;              // [n_out] measurement per cone
+  double* grad;             // dual cones: [gradient slots], written by the slot's cone
   int m_max;                // largest tile of any cone pass
   int r;
   int c128;
+  int dual;                 // 1: forward, lambda = P psi and adjoint sweep per cone
 };
 
 hipError_t launch_cones(const ConeLaunch& L, hipStream_t stream);
@@ -62,6 +64,15 @@ hipError_t launch_grad_scatter(const double* slot_total, int rows, int n_slots, 
 // tval[t] = coef[t] * prod_{k in [off[t], off[t+1])} fval[fac[k]] (in k order).
 hipError_t launch_term_products(const double* fval, const int32_t* off, const int32_t* fac, const double* coef, int T,
                                 double* tval, hipStream_t stream);
+
+// w[f] = sum over terms t containing factor f (CSR f_off/f_terms) of
+// t_coef[t] * prod of fval over t's other factors: d<H>/d<P_f>.
+hipError_t launch_factor_weights(const double* fval, const int32_t* f_off, const int32_t* f_terms,
+                                 const int32_t* t_off, const int32_t* t_fac, const double* t_coef, int F, double* w,
+                                 hipStream_t stream);
+// grad[p] = sum over slots s of p (CSR) of w[g_cone[s]] * g[s], in CSR order.
+hipError_t launch_weighted_scatter(const double* g, const int32_t* g_cone, const double* w, const int32_t* p_off,
+                                   const int32_t* p_slots, int n_params, double* grad, hipStream_t stream);
 
 // Plain copy of n16 16-byte words (reference HBM stream).
 hipError_t launch_copy(const void* src, void* dst, uint64_t n16, hipStream_t stream);

@@ -29,6 +29,59 @@ struct __attribute__((aligned(2 * sizeof(T)))) cpx {
   T x, y;
 };
 
+// One amplitude per lane in a single 8- or 16-byte access.
+template <class T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+
+template <class T>
+__device__ __forceinline__ cpx<T> ld_amp(const cpx<T>* p) {
+  const typename Vec2<T>::type v = *reinterpret_cast<const typename Vec2<T>::type*>(p);
+  cpx<T> r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ void st_amp(cpx<T>* p, const cpx<T>& a) {
+  typename Vec2<T>::type v;
+  v.x = a.x;
+  v.y = a.y;
+  *reinterpret_cast<typename Vec2<T>::type*>(p) = v;
+}
+
+// Pass, stage and op descriptors and gate coefficients are read-only while a
+// kernel runs and the same for every wave of a workgroup.  Reading them through
+// the constant address space gives scalar loads, which stay out of the vector
+// memory pipeline and do not wait behind the HBM loads of a prefetched tile.
+template <class T>
+using kptr = const __attribute__((address_space(4))) T*;
+
+template <class T>
+__device__ __forceinline__ kptr<T> kc(const T* p) {
+  return (kptr<T>)(uintptr_t)p;
+}
+
+// Scalar loads are dword-granular: 8- and 16-bit descriptor fields are read
+// through their aligned dword.
+__device__ __forceinline__ uint32_t kb(kptr<uint8_t> p) {
+  const uintptr_t a = (uintptr_t)p;
+  return (*(kptr<uint32_t>)(a & ~(uintptr_t)3) >> (8 * (a & 3))) & 0xffu;
+}
+
+__device__ __forceinline__ uint32_t kh(kptr<uint16_t> p) {
+  const uintptr_t a = (uintptr_t)p;
+  return (*(kptr<uint32_t>)(a & ~(uintptr_t)3) >> (8 * (a & 2))) & 0xffffu;
+}
+
 template <int N>
 using IC = std::integral_constant<int, N>;
 
@@ -84,7 +137,7 @@ __device__ __forceinline__ T sgn(int odd) {
 // ---------------------------------------------------------------------------
 
 template <class T, int R, int J>
-__device__ __forceinline__ void ap_u(cpx<T>* a, const T* __restrict__ u, const BitSel& c) {
+__device__ __forceinline__ void ap_u(cpx<T>* a, kptr<T> u, const BitSel& c) {
   const T u00r = u[0], u00i = u[1], u01r = u[2], u01i = u[3];
   const T u10r = u[4], u10i = u[5], u11r = u[6], u11i = u[7];
   const bool ctl = c.kind != BK_NONE;
@@ -110,7 +163,7 @@ __device__ __forceinline__ void ap_u(cpx<T>* a, const T* __restrict__ u, const B
 }
 
 template <class T, int R, int J>
-__device__ __forceinline__ void ap_ry(cpx<T>* a, const T* __restrict__ u, const BitSel& c) {
+__device__ __forceinline__ void ap_ry(cpx<T>* a, kptr<T> u, const BitSel& c) {
   const T cs = u[0], sn = u[1];
   const bool ctl = c.kind != BK_NONE;
 #pragma unroll
@@ -149,7 +202,7 @@ __device__ __forceinline__ void ap_x(cpx<T>* a, const BitSel& c) {
 }
 
 template <class T, int R>
-__device__ __forceinline__ void ap_phase(cpx<T>* a, const T* __restrict__ d, const BitSel& b) {
+__device__ __forceinline__ void ap_phase(cpx<T>* a, kptr<T> d, const BitSel& b) {
   const T d0r = d[0], d0i = d[1], d1r = d[2], d1i = d[3];
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
@@ -287,44 +340,44 @@ struct TileRegs {
   cpx<T> b[DUAL ? (1 << R) : 1];
 };
 
-__device__ __forceinline__ uint64_t tile_base(const PassDesc* __restrict__ P, uint64_t tile) {
+__device__ __forceinline__ uint64_t tile_base(kptr<PassDesc> P, uint64_t tile) {
   uint64_t base = 0;
   const int nn = P->n - P->m;
   for (int k = 0; k < nn; ++k)
-    if ((tile >> k) & 1) base |= 1ull << P->npos[k];
+    if ((tile >> k) & 1) base |= 1ull << kb(&P->npos[k]);
   return base;
 }
 
 // Thread-local part of stage S's local index (thread bits deposited into tb).
 template <int R>
-__device__ __forceinline__ uint32_t thread_local_index(const StageDesc* __restrict__ S, int m, int tid) {
+__device__ __forceinline__ uint32_t thread_local_index(kptr<StageDesc> S, int m, int tid) {
   uint32_t tl = 0;
-  for (int k = 0; k < m - R; ++k) tl |= ((uint32_t)(tid >> k) & 1u) << S->tb[k];
+  for (int k = 0; k < m - R; ++k) tl |= ((uint32_t)(tid >> k) & 1u) << kb(&S->tb[k]);
   return tl;
 }
 
 // Global offsets (physical index bits) of stage S: per-thread part and per-register-bit parts.
 template <int R>
-__device__ __forceinline__ uint64_t stage_gaddr(const PassDesc* __restrict__ P, const StageDesc* __restrict__ S,
-                                                int tid, uint64_t base, uint64_t* gr) {
+__device__ __forceinline__ uint64_t stage_gaddr(kptr<PassDesc> P, kptr<StageDesc> S, int tid, uint64_t base,
+                                                uint64_t* gr) {
   const int m = P->m;
   uint64_t gt = base;
   for (int k = 0; k < m - R; ++k)
-    if ((tid >> k) & 1) gt |= 1ull << P->lpos[S->tb[k]];
+    if ((tid >> k) & 1) gt |= 1ull << kb(&P->lpos[kb(&S->tb[k])]);
 #pragma unroll
-  for (int j = 0; j < R; ++j) gr[j] = 1ull << P->lpos[S->rb[j]];
+  for (int j = 0; j < R; ++j) gr[j] = 1ull << kb(&P->lpos[kb(&S->rb[j])]);
   return gt;
 }
 
-// First stage of a tile: load a (and b) from HBM, or generate |0...0>.
+// First stage of a tile: load a (and b) from HBM, or generate |0...0>.  Lanes
+// past the tile (tiles of fewer than 64 threads' worth of amplitudes) read a
+// valid slot of their tile too; tile_run zeroes them.
 template <class T, int R, bool DUAL>
-__device__ __forceinline__ void tile_load(const PassDesc* __restrict__ P, const StageDesc* __restrict__ S0,
-                                          const cpx<T>* __restrict__ A, const cpx<T>* __restrict__ B, uint64_t base,
-                                          TileRegs<T, R, DUAL>& t) {
+__device__ __forceinline__ void tile_load(kptr<PassDesc> P, kptr<StageDesc> S0, const cpx<T>* __restrict__ A,
+                                          const cpx<T>* __restrict__ B, uint64_t base, TileRegs<T, R, DUAL>& t) {
   constexpr int NR = 1 << R;
   const int m = P->m, flags = P->flags;
   const int tid = threadIdx.x;
-  const bool active = tid < (1 << (m - R));
   const bool ld_a = (flags & PF_LOAD_A) != 0, ld_b = DUAL && (flags & PF_LOAD_B) != 0;
   cpx<T> z;
   z.x = 0;
@@ -332,20 +385,35 @@ __device__ __forceinline__ void tile_load(const PassDesc* __restrict__ P, const 
   if (ld_a || ld_b) {
     uint64_t gr[R];
     const uint64_t gt = stage_gaddr<R>(P, S0, tid, base, gr);
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
+    auto addr = [&](int i) __attribute__((always_inline)) {
       uint64_t g = gt;
 #pragma unroll
       for (int j = 0; j < R; ++j)
         if ((i >> j) & 1) g |= gr[j];
-      t.a[i] = (ld_a && active) ? A[g] : z;
-      if constexpr (DUAL) t.b[i] = (ld_b && active) ? B[g] : z;
+      return g;
+    };
+    if (ld_a) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) t.a[i] = ld_amp(A + addr(i));
+    } else {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) t.a[i] = z;
+    }
+    if constexpr (DUAL) {
+      if (ld_b) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) t.b[i] = ld_amp(B + addr(i));
+      } else {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) t.b[i] = z;
+      }
     }
   } else {
+    const bool active = tid < (1 << (m - R));
     const uint32_t tl = thread_local_index<R>(S0, m, tid);
     uint32_t rl[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) rl[j] = 1u << S0->rb[j];
+    for (int j = 0; j < R; ++j) rl[j] = 1u << kb(&S0->rb[j]);
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       uint32_t o = tl;
@@ -362,11 +430,10 @@ __device__ __forceinline__ void tile_load(const PassDesc* __restrict__ P, const 
 // All stages of a tile whose first-stage registers are loaded: ops, LDS
 // exchanges (with exit permutations), the store, and the block's partial sums.
 template <class T, int R, bool DUAL>
-__device__ __forceinline__ double tile_run(const PassDesc* __restrict__ P, const StageDesc* __restrict__ SD,
-                                           const DevOp* __restrict__ OPS, cpx<T>* __restrict__ A,
-                                           cpx<T>* __restrict__ B, const T* __restrict__ coef, uint64_t base,
+__device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD, kptr<DevOp> OPS,
+                                           cpx<T>* __restrict__ A, cpx<T>* __restrict__ B, kptr<T> coef, uint64_t base,
                                            TileRegs<T, R, DUAL>& t, cpx<T>* lds, double* red, double* gacc,
-                                           double* __restrict__ grad_out, int64_t grad_stride) {
+                                           double* __restrict__ grad_out, int64_t grad_stride, bool grad_add = false) {
   constexpr int NR = 1 << R;
   const int m = P->m, flags = P->flags;
   const int tid = threadIdx.x;
@@ -382,14 +449,24 @@ __device__ __forceinline__ double tile_run(const PassDesc* __restrict__ P, const
     for (int k = tid; k < nwaves * gcount; k += nthr) gacc[k] = 0.0;
     lds_sync();
   }
+  cpx<T> z;
+  z.x = 0;
+  z.y = 0;
+  if (!active) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      a[i] = z;
+      if constexpr (DUAL) b[i] = z;
+    }
+  }
   double acc = 0.0;
   const int s0 = P->stage_begin, s1 = P->stage_end, sst = P->store_stage;
   for (int s = s0; s < s1; ++s) {
-    const StageDesc* S = SD + s;
+    kptr<StageDesc> S = SD + s;
     const uint32_t tl = thread_local_index<R>(S, m, tid);
     uint32_t rl[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) rl[j] = 1u << S->rb[j];
+    for (int j = 0; j < R; ++j) rl[j] = 1u << kb(&S->rb[j]);
     auto roff = [&](int i) __attribute__((always_inline)) {
       uint32_t o = 0;
 #pragma unroll
@@ -398,24 +475,32 @@ __device__ __forceinline__ double tile_run(const PassDesc* __restrict__ P, const
       return o;
     };
     if (s != s0) {
+      // lanes past the tile read valid slots (their local index keeps only tile bits) and are zeroed
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
-        cpx<T> z;
-        z.x = 0;
-        z.y = 0;
         const uint32_t l = swz(tl | roff(i));
-        a[i] = active ? lds[l] : z;
-        if constexpr (DUAL) b[i] = active ? lds[tsize + l] : z;
+        a[i] = ld_amp(lds + l);
+        if constexpr (DUAL) b[i] = ld_amp(lds + tsize + l);
+      }
+      if (!active) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          a[i] = z;
+          if constexpr (DUAL) b[i] = z;
+        }
       }
     }
 
     for (int o = S->op_begin; o < S->op_end; ++o) {
-      const DevOp op = OPS[o];
-      const uint32_t type = op.type;
+      kptr<DevOp> op = OPS + o;
+      // type, j, ck, cb | ck2, cb2, ph, pad
+      const uint32_t w0 = *(kptr<uint32_t>)op, w1 = *((kptr<uint32_t>)op + 1);
+      const uint32_t type = w0 & 0xffu, opj = (w0 >> 8) & 0xffu, ck = (w0 >> 16) & 0xffu, cb = w0 >> 24;
+      const uint32_t ck2 = w1 & 0xffu, cb2 = (w1 >> 8) & 0xffu, ph = (w1 >> 16) & 0xffu;
       if (type == OP_U || type == OP_RY || type == OP_X) {
-        const T* u = coef + (int64_t)op.slot * 8;
-        const BitSel c = mkbit(op.ck, op.cb, tl, base);
-        for_bit<R>(op.j, [&](auto JC) __attribute__((always_inline)) {
+        kptr<T> u = coef + (int64_t)op->slot * 8;
+        const BitSel c = mkbit(ck, cb, tl, base);
+        for_bit<R>(opj, [&](auto JC) __attribute__((always_inline)) {
           constexpr int J = decltype(JC)::value;
           if (type == OP_U) {
             ap_u<T, R, J>(a, u, c);
@@ -429,22 +514,22 @@ __device__ __forceinline__ double tile_run(const PassDesc* __restrict__ P, const
           }
         });
       } else if (type == OP_PHASE) {
-        const T* d = coef + (int64_t)op.slot * 8;
-        const BitSel c = mkbit(op.ck, op.cb, tl, base);
+        kptr<T> d = coef + (int64_t)op->slot * 8;
+        const BitSel c = mkbit(ck, cb, tl, base);
         ap_phase<T, R>(a, d, c);
         if constexpr (DUAL) ap_phase<T, R>(b, d, c);
       } else if (type == OP_CZ) {
-        const BitSel c1 = mkbit(op.ck, op.cb, tl, base);
-        const BitSel c2 = mkbit(op.ck2, op.cb2, tl, base);
+        const BitSel c1 = mkbit(ck, cb, tl, base);
+        const BitSel c2 = mkbit(ck2, cb2, tl, base);
         ap_cz<T, R>(a, c1, c2);
         if constexpr (DUAL) ap_cz<T, R>(b, c1, c2);
       } else if (type == OP_MEAS_Z) {
         T p[NR];  // |a_i|^2
 #pragma unroll
         for (int i = 0; i < NR; ++i) p[i] = a[i].x * a[i].x + a[i].y * a[i].y;
-        const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
-        const double v = (double)meas_zp<T, R>(p, op.rz);
-        acc += op.c * (par ? -v : v);
+        const uint32_t par = (__popc(tl & op->tz) + __popcll(base & op->pz)) & 1;
+        const double v = (double)meas_zp<T, R>(p, op->rz);
+        acc += op->c * (par ? -v : v);
       } else if (type == OP_MEAS_ZS) {
         // W[k] = sum_i (-1)^{parity(i & k)} |a_i|^2 by an in-register Walsh-Hadamard transform;
         // each term then reads W at its register mask.
@@ -461,50 +546,50 @@ __device__ __forceinline__ double tile_run(const PassDesc* __restrict__ P, const
             wt[i | (1 << bb)] = x - y;
           }
         }
-        const int nt = op.slot;
+        const int nt = op->slot;
         T part = 0;
         for (int k = 1; k <= nt; ++k) {
-          const DevOp tr = OPS[o + k];
-          const uint32_t par = (__popc(tl & tr.tz) + __popcll(base & tr.pz)) & 1;
+          kptr<DevOp> tr = OPS + o + k;
+          const uint32_t par = (__popc(tl & tr->tz) + __popcll(base & tr->pz)) & 1;
           T wv = 0;
-          if (tr.rz == 0u) {
+          if (tr->rz == 0u) {
             wv = wt[0];
           } else {
-            for_mask<NR>(tr.rz, [&](auto KC) __attribute__((always_inline)) { wv = wt[decltype(KC)::value]; });
+            for_mask<NR>(tr->rz, [&](auto KC) __attribute__((always_inline)) { wv = wt[decltype(KC)::value]; });
           }
-          const T cc = (T)tr.c;
+          const T cc = (T)tr->c;
           part += par ? -cc * wv : cc * wv;
         }
         acc += (double)part;
         o += nt;
       } else if (type == OP_MEAS_F) {
-        const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
-        for_mask<NR>(op.fr, [&](auto FC) __attribute__((always_inline)) {
+        const uint32_t par = (__popc(tl & op->tz) + __popcll(base & op->pz)) & 1;
+        for_mask<NR>(op->fr, [&](auto FC) __attribute__((always_inline)) {
           constexpr int F = decltype(FC)::value;
-          acc += op.c * meas_f<T, R, F>(a, op.rz, par, op.ph);
+          acc += op->c * meas_f<T, R, F>(a, op->rz, par, ph);
         });
       } else if constexpr (DUAL) {
         if (type == OP_H_Z) {
-          const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
-          h_z<T, R>(a, b, (T)op.c, op.rz, par);
+          const uint32_t par = (__popc(tl & op->tz) + __popcll(base & op->pz)) & 1;
+          h_z<T, R>(a, b, (T)op->c, op->rz, par);
         } else if (type == OP_H_F) {
-          const uint32_t par = (__popc(tl & op.tz) + __popcll(base & op.pz)) & 1;
-          for_mask<NR>(op.fr, [&](auto FC) __attribute__((always_inline)) {
+          const uint32_t par = (__popc(tl & op->tz) + __popcll(base & op->pz)) & 1;
+          for_mask<NR>(op->fr, [&](auto FC) __attribute__((always_inline)) {
             constexpr int F = decltype(FC)::value;
-            h_f<T, R, F>(a, b, (T)op.c, op.rz, par, op.ph);
+            h_f<T, R, F>(a, b, (T)op->c, op->rz, par, ph);
           });
         } else if (type == OP_GRAD_X || type == OP_GRAD_Y || type == OP_GRAD_Z) {
           T v = 0;
           if (type == OP_GRAD_Z) {
-            v = grad_z<T, R>(a, b, mkbit(op.ck, op.cb, tl, base));
+            v = grad_z<T, R>(a, b, mkbit(ck, cb, tl, base));
           } else {
-            for_bit<R>(op.j, [&](auto JC) __attribute__((always_inline)) {
+            for_bit<R>(opj, [&](auto JC) __attribute__((always_inline)) {
               constexpr int J = decltype(JC)::value;
               v = type == OP_GRAD_X ? grad_x<T, R, J>(a, b) : grad_y<T, R, J>(a, b);
             });
           }
           const T w = wave_sum(v);
-          if (lane == 0) gacc[wave * gcount + (op.slot - gbegin)] += (double)w;
+          if (lane == 0) gacc[wave * gcount + (op->slot - gbegin)] += (double)w;
         }
       }
     }
@@ -520,9 +605,9 @@ __device__ __forceinline__ double tile_run(const PassDesc* __restrict__ P, const
 #pragma unroll
           for (int j = 0; j < R; ++j)
             if ((i >> j) & 1) g |= gr[j];
-          if (st_a) A[g] = a[i];
+          if (st_a) st_amp(A + g, a[i]);
           if constexpr (DUAL) {
-            if (st_b) B[g] = b[i];
+            if (st_b) st_amp(B + g, b[i]);
           }
         }
       }
@@ -530,25 +615,26 @@ __device__ __forceinline__ double tile_run(const PassDesc* __restrict__ P, const
     if (s + 1 < s1) {
       lds_sync();
       if (active) {
-        if (S->has_perm) {
+        if (kh(&S->has_perm)) {
           // write every amplitude to its image under the stage's exit permutation
           uint32_t w = 0;
           for (int k = 0; k < m - R; ++k)
-            if ((tid >> k) & 1) w ^= S->tcol[k];
-          for (int j = 0; j < (int)S->n_aff; ++j)
-            if ((base >> S->aff_pos[j]) & 1) w ^= S->aff_mask[j];
+            if ((tid >> k) & 1) w ^= kh(&S->tcol[k]);
+          const int n_aff = (int)kh(&S->n_aff);
+          for (int j = 0; j < n_aff; ++j)
+            if ((base >> kb(&S->aff_pos[j])) & 1) w ^= kh(&S->aff_mask[j]);
 #pragma unroll
           for (int i = 0; i < NR; ++i) {
-            const uint32_t l = swz(w ^ (uint32_t)S->preg[i]);
-            lds[l] = a[i];
-            if constexpr (DUAL) lds[tsize + l] = b[i];
+            const uint32_t l = swz(w ^ kh(&S->preg[i]));
+            st_amp(lds + l, a[i]);
+            if constexpr (DUAL) st_amp(lds + tsize + l, b[i]);
           }
         } else {
 #pragma unroll
           for (int i = 0; i < NR; ++i) {
             const uint32_t l = swz(tl | roff(i));
-            lds[l] = a[i];
-            if constexpr (DUAL) lds[tsize + l] = b[i];
+            st_amp(lds + l, a[i]);
+            if constexpr (DUAL) st_amp(lds + tsize + l, b[i]);
           }
         }
       }
@@ -569,7 +655,8 @@ __device__ __forceinline__ double tile_run(const PassDesc* __restrict__ P, const
     for (int k = tid; k < gcount; k += nthr) {
       double sum = 0.0;
       for (int w = 0; w < nwaves; ++w) sum += gacc[w * gcount + k];
-      grad_out[(int64_t)(gbegin + k) * grad_stride] = sum;
+      double* dst = grad_out + (int64_t)(gbegin + k) * grad_stride;
+      *dst = grad_add ? *dst + sum : sum;  // the same thread wrote the previous tile's value
     }
     lds_sync();
   }
@@ -594,17 +681,21 @@ constexpr int pass_max_threads() {
 // second workgroup to overlap with); this needs twice the data registers.
 template <class T, int R, bool DUAL, bool PF>
 __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass(
-    const PassDesc* __restrict__ P, const StageDesc* __restrict__ SD, const DevOp* __restrict__ OPS, cpx<T>* A,
-    cpx<T>* B, int64_t row_stride, const T* __restrict__ coef, int64_t coef_row_stride, double* meas, int n_meas,
+    const PassDesc* __restrict__ Pg, const StageDesc* __restrict__ SDg, const DevOp* __restrict__ OPSg, cpx<T>* A,
+    cpx<T>* B, int64_t row_stride, const T* __restrict__ coefg, int64_t coef_row_stride, double* meas, int n_meas,
     double* grad, int n_gslots, int64_t rows) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const kptr<PassDesc> P = kc(Pg);
+  const kptr<StageDesc> SD = kc(SDg);
+  const kptr<DevOp> OPS = kc(OPSg);
+  const kptr<T> coef = kc(coefg);
   const int m = P->m, sh = P->n - m;
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
   double* red = reinterpret_cast<double*>(smem + ((size_t)(DUAL ? 2 : 1) * sizeof(cpx<T>) << m));
   double* gacc = red + kRedSlots;
   const int64_t tiles = 1ll << sh;
   const int64_t total = tiles * rows;
-  const StageDesc* S0 = SD + P->stage_begin;
+  const kptr<StageDesc> S0 = SD + P->stage_begin;
   int64_t w = blockIdx.x;
   if (w >= total) return;
   TileRegs<T, R, DUAL> cur;
@@ -653,54 +744,67 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass_multi
   double* red = reinterpret_cast<double*>(smem + ((size_t)(DUAL ? 2 : 1) * sizeof(cpx<T>) << m_max));
   double* gacc = red + kRedSlots;
   const int64_t b = blockIdx.x;
+  const kptr<PassItem> KI = kc(items);
   int lo = 0, hi = n_items - 1;
   while (lo < hi) {  // last item with tile_begin <= b
     const int mid = (lo + hi + 1) >> 1;
-    if (items[mid].tile_begin <= b) lo = mid;
+    if ((KI + mid)->tile_begin <= b) lo = mid;
     else hi = mid - 1;
   }
-  const PassItem it = items[lo];
-  const PassDesc* P = it.pass;
+  const kptr<PassItem> it = KI + lo;
+  const kptr<PassDesc> P = kc(it->pass);
+  const kptr<StageDesc> SD = kc(it->stages);
   const int64_t tiles = 1ll << (P->n - P->m);
-  const uint64_t tile = (uint64_t)(b - it.tile_begin);
+  const uint64_t tile = (uint64_t)(b - it->tile_begin);
   const uint64_t base = tile_base(P, tile);
-  double* gout = (DUAL && it.grad) ? it.grad + (int64_t)tile : nullptr;
-  cpx<T>* A = reinterpret_cast<cpx<T>*>(it.A);
-  cpx<T>* B = reinterpret_cast<cpx<T>*>(it.B);
+  double* gout = (DUAL && it->grad) ? it->grad + (int64_t)tile : nullptr;
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(it->A);
+  cpx<T>* B = reinterpret_cast<cpx<T>*>(it->B);
   TileRegs<T, R, DUAL> t;
-  tile_load<T, R, DUAL>(P, it.stages + P->stage_begin, A, B, base, t);
-  const double v = tile_run<T, R, DUAL>(P, it.stages, it.ops, A, B, reinterpret_cast<const T*>(it.coef), base, t,
+  tile_load<T, R, DUAL>(P, SD + P->stage_begin, A, B, base, t);
+  const double v = tile_run<T, R, DUAL>(P, SD, kc(it->ops), A, B, kc(reinterpret_cast<const T*>(it->coef)), base, t,
                                         lds, red, gacc, gout, tiles);
-  if ((P->flags & PF_MEASURE) && threadIdx.x == 0) it.meas[(int64_t)P->meas_index * tiles + (int64_t)tile] = v;
+  if ((P->flags & PF_MEASURE) && threadIdx.x == 0) it->meas[(int64_t)P->meas_index * tiles + (int64_t)tile] = v;
 }
 
-template <class T, int R>
-__global__ __launch_bounds__((pass_max_threads<T, R, false>())) void k_cones(
-    const ConeDesc* __restrict__ cones, const int32_t* __restrict__ order, const PassDesc* __restrict__ P,
-    const StageDesc* __restrict__ SD, const DevOp* __restrict__ OPS, cpx<T>* scratch, const T* __restrict__ coef,
-    double* out, int m_max) {
+// One workgroup per cone: the cone's passes run in order, each over its tiles.
+// A cone of at most m qubits is a single tile (LDS-resident within a pass);
+// larger cones and states kept between passes live in scratch.  DUAL cones run
+// forward, lambda = P psi and the adjoint sweep; their gradient probes
+// accumulate over tiles into the cone's own gradient slots.
+template <class T, int R, bool DUAL>
+__global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_cones(
+    const ConeDesc* __restrict__ cones, const int32_t* __restrict__ order, const PassDesc* __restrict__ Pg,
+    const StageDesc* __restrict__ SDg, const DevOp* __restrict__ OPSg, cpx<T>* scratch, const T* __restrict__ coef,
+    double* out, double* grad, int m_max) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
-  double* red = reinterpret_cast<double*>(smem + (sizeof(cpx<T>) << m_max));
-  const ConeDesc cd = cones[order[blockIdx.x]];
+  double* red = reinterpret_cast<double*>(smem + ((size_t)(DUAL ? 2 : 1) * sizeof(cpx<T>) << m_max));
+  double* gacc = red + kRedSlots;
+  const kptr<PassDesc> P = kc(Pg);
+  const kptr<StageDesc> SD = kc(SDg);
+  const kptr<DevOp> OPS = kc(OPSg);
+  const kptr<ConeDesc> cd = kc(cones) + *(kc(order) + blockIdx.x);
   double total = 0.0;
-  cpx<T>* st = scratch + cd.scratch_off;
-  const T* cf = coef + (int64_t)cd.coef_begin * 8;
-  for (int p = cd.pass_begin; p < cd.pass_end; ++p) {
-    const PassDesc* pp = P + p;
+  cpx<T>* st = scratch + cd->scratch_off;
+  cpx<T>* st_b = DUAL ? st + (1ll << cd->n) : nullptr;
+  const kptr<T> cf = kc(coef) + (int64_t)cd->coef_begin * 8;
+  const int pass_end = cd->pass_end, out_index = cd->out_index;
+  for (int p = cd->pass_begin; p < pass_end; ++p) {
+    const kptr<PassDesc> pp = P + p;
     const int64_t tiles = 1ll << (pp->n - pp->m);
     for (int64_t t = 0; t < tiles; ++t) {
       const uint64_t base = tile_base(pp, (uint64_t)t);
-      TileRegs<T, R, false> regs;
-      tile_load<T, R, false>(pp, SD + pp->stage_begin, st, nullptr, base, regs);
-      total += tile_run<T, R, false>(pp, SD, OPS, st, nullptr, cf, base, regs, lds, red, nullptr, nullptr, 0);
+      TileRegs<T, R, DUAL> regs;
+      tile_load<T, R, DUAL>(pp, SD + pp->stage_begin, st, st_b, base, regs);
+      total += tile_run<T, R, DUAL>(pp, SD, OPS, st, st_b, cf, base, regs, lds, red, gacc, grad, 1, t > 0);
       lds_sync();
     }
     // the next pass reads what other waves of this workgroup stored
     __threadfence();
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[cd.out_index] = total;
+  if (threadIdx.x == 0) out[out_index] = total;
 }
 
 __global__ __launch_bounds__(256) void k_reduce_rows(const double* __restrict__ part, int64_t per_row, double add,
@@ -739,6 +843,41 @@ __global__ __launch_bounds__(256) void k_term_products(const double* __restrict_
   double v = coef[t];
   for (int k = off[t]; k < off[t + 1]; ++k) v *= fval[fac[k]];
   tval[t] = v;
+}
+
+__global__ __launch_bounds__(256) void k_factor_weights(const double* __restrict__ fval,
+                                                        const int32_t* __restrict__ f_off,
+                                                        const int32_t* __restrict__ f_terms,
+                                                        const int32_t* __restrict__ t_off,
+                                                        const int32_t* __restrict__ t_fac,
+                                                        const double* __restrict__ t_coef, int F, double* w) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f >= F) return;
+  double s = 0.0;
+  for (int i = f_off[f]; i < f_off[f + 1]; ++i) {
+    const int t = f_terms[i];
+    double v = t_coef[t];
+    for (int k = t_off[t]; k < t_off[t + 1]; ++k)
+      if (t_fac[k] != f) v *= fval[t_fac[k]];
+    s += v;
+  }
+  w[f] = s;
+}
+
+__global__ __launch_bounds__(256) void k_weighted_scatter(const double* __restrict__ g,
+                                                          const int32_t* __restrict__ g_cone,
+                                                          const double* __restrict__ w,
+                                                          const int32_t* __restrict__ p_off,
+                                                          const int32_t* __restrict__ p_slots, int n_params,
+                                                          double* grad) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= n_params) return;
+  double s = 0.0;
+  for (int k = p_off[p]; k < p_off[p + 1]; ++k) {
+    const int slot = p_slots[k];
+    s += w[g_cone[slot]] * g[slot];
+  }
+  grad[p] = s;
 }
 
 __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, uint64_t n) {
@@ -801,16 +940,16 @@ hipError_t launch_pass_r(const PassLaunch& L, hipStream_t stream) {
   }
 }
 
-template <class T, int R>
+template <class T, int R, bool DUAL>
 hipError_t launch_cones_t(const ConeLaunch& L, hipStream_t stream) {
-  const size_t lds = (sizeof(cpx<T>) << L.m_max) + kRedSlots * sizeof(double);
-  auto kern = k_cones<T, R>;
+  const size_t lds = pass_lds_bytes(L.m_max, sizeof(T) == 8, DUAL);
+  auto kern = k_cones<T, R, DUAL>;
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = std::max(64, 1 << (L.m_max - R));
   hipLaunchKernelGGL(kern, dim3((unsigned)L.n_cones), dim3(threads), lds, stream, L.d_cones, L.d_order,
                      L.d_passes, L.d_stages, L.d_ops, reinterpret_cast<cpx<T>*>(L.scratch),
-                     reinterpret_cast<const T*>(L.coef), L.out, L.m_max);
+                     reinterpret_cast<const T*>(L.coef), L.out, L.grad, L.m_max);
   return hipGetLastError();
 }
 
@@ -845,6 +984,23 @@ hipError_t launch_term_products(const double* fval, const int32_t* off, const in
   return hipGetLastError();
 }
 
+hipError_t launch_factor_weights(const double* fval, const int32_t* f_off, const int32_t* f_terms,
+                                 const int32_t* t_off, const int32_t* t_fac, const double* t_coef, int F, double* w,
+                                 hipStream_t stream) {
+  if (F <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_factor_weights, dim3((unsigned)((F + 255) / 256)), dim3(256), 0, stream, fval, f_off, f_terms,
+                     t_off, t_fac, t_coef, F, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_weighted_scatter(const double* g, const int32_t* g_cone, const double* w, const int32_t* p_off,
+                                   const int32_t* p_slots, int n_params, double* grad, hipStream_t stream) {
+  if (n_params <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_weighted_scatter, dim3((unsigned)((n_params + 255) / 256)), dim3(256), 0, stream, g, g_cone, w,
+                     p_off, p_slots, n_params, grad);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(const void* src, void* dst, uint64_t n16, hipStream_t stream) {
   const uint64_t blocks = std::min<uint64_t>((n16 + 255) / 256, (uint64_t)device_cus() * 32);
   hipLaunchKernelGGL(k_copy, dim3((unsigned)std::max<uint64_t>(1, blocks)), dim3(256), 0, stream,
@@ -868,7 +1024,10 @@ hipError_t launch_pass(const PassLaunch& L, hipStream_t stream) {
 hipError_t launch_cones(const ConeLaunch& L, hipStream_t stream) {
   if (L.n_cones == 0) return hipSuccess;
   if (L.r != 4) return hipErrorInvalidValue;
-  return L.c128 ? launch_cones_t<double, 4>(L, stream) : launch_cones_t<float, 4>(L, stream);
+  const int mmax = (L.c128 ? 13 : 14) - (L.dual ? 1 : 0);
+  if (L.m_max > mmax || L.m_max < 4 || (L.dual && !L.grad)) return hipErrorInvalidValue;
+  if (L.dual) return L.c128 ? launch_cones_t<double, 4, true>(L, stream) : launch_cones_t<float, 4, true>(L, stream);
+  return L.c128 ? launch_cones_t<double, 4, false>(L, stream) : launch_cones_t<float, 4, false>(L, stream);
 }
 
 hipError_t launch_reduce_rows(const double* part, int rows, int64_t per_row, double add, double* out,

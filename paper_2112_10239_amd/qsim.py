@@ -68,7 +68,7 @@ EXPORTS = [
     "qsim_apply_layer", "qsim_expect", "qsim_state_to_host", "qsim_state_device_ptr", "qsim_expect_circuit",
     "qsim_expect_grad", "qsim_lightcone_sets", "qsim_plan_dense", "qsim_submit", "qsim_poll", "qsim_cancel",
     "qsim_server_stats_get", "qsim_timing_enable", "qsim_timing_get", "qsim_poll_timed", "qsim_clock",
-    "qsim_copy_probe",
+    "qsim_copy_probe", "qsim_expect_grad_cones",
 ]
 
 
@@ -98,6 +98,7 @@ def _load():
         "qsim_state_device_ptr": (I, [V, P(V)]),
         "qsim_expect_circuit": (I, [V, P(Circuit), P(D), I, P(Hamiltonian), I, I, V, P(D), P(V)]),
         "qsim_expect_grad": (I, [V, P(Circuit), P(D), I, P(Hamiltonian), I, V, V, P(D), P(D)]),
+        "qsim_expect_grad_cones": (I, [V, P(Circuit), P(D), I, P(Hamiltonian), I, I, V, P(D), P(D)]),
         "qsim_lightcone_sets": (I, [P(Circuit), P(Hamiltonian), P(ctypes.c_int32), P(ctypes.c_int32), I]),
         "qsim_plan_dense": (I, [P(Circuit), P(Hamiltonian), I, P(ctypes.c_int64), P(ctypes.c_int32), I]),
         "qsim_submit": (I, [V, P(Request), P(ctypes.c_uint64)]),
@@ -287,8 +288,10 @@ class Context:
             return val, State._wrap(self, kp, circ.n, rows, dtype)
         return val
 
-    def expect_grad(self, circ, H, theta, dtype: int = C64, stream=None, saved=None, want_E=True):
-        """(E [B], grad [B, P]) by the adjoint method; theta [P] or [B, P]."""
+    def expect_grad(self, circ, H, theta, dtype: int = C64, stream=None, saved=None, want_E=True,
+                    mode: int = MODE_DENSE):
+        """(E [B], grad [B, P]) by the adjoint method; theta [P] or [B, P].  mode: MODE_DENSE
+        (full state), MODE_LIGHTCONE or MODE_LIGHTCONE_FACTORED (adjoint inside light cones)."""
         th = np.asarray(theta, dtype=np.float64)
         single = th.ndim <= 1
         rows = 1 if single else th.shape[0]
@@ -296,9 +299,17 @@ class Context:
         cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
         E = np.zeros(rows)
         g = np.zeros((rows, max(1, circ.n_params)))
-        rc = lib.qsim_expect_grad(self.ptr, ctypes.byref(cc.c), _dptr(th), rows, ctypes.byref(ch.h), dtype, stream,
-                                  saved.ptr if saved is not None else None, _dptr(E) if want_E else None, _dptr(g))
-        self._check(rc, "qsim_expect_grad")
+        if mode == MODE_DENSE:
+            rc = lib.qsim_expect_grad(self.ptr, ctypes.byref(cc.c), _dptr(th), rows, ctypes.byref(ch.h), dtype,
+                                      stream, saved.ptr if saved is not None else None,
+                                      _dptr(E) if want_E else None, _dptr(g))
+            self._check(rc, "qsim_expect_grad")
+        else:
+            if saved is not None:
+                raise ValueError("saved states are only used by the dense mode")
+            rc = lib.qsim_expect_grad_cones(self.ptr, ctypes.byref(cc.c), _dptr(th), rows, ctypes.byref(ch.h), mode,
+                                            dtype, stream, _dptr(E) if want_E else None, _dptr(g))
+            self._check(rc, "qsim_expect_grad_cones")
         g = g[:, : circ.n_params]
         if single:
             return float(E[0]), g[0]

@@ -392,3 +392,117 @@ def test_factored_brickwork_clifford_n200(Q, eng):
     say("factored clifford n200")
     want = pinlib.clifford_expect(c, H, th)
     assert abs(eng.expect_circuit(c, H, th, mode=Q.MODE_LIGHTCONE_FACTORED) - want) <= 1e-3
+
+
+# --- light-cone gradients (adjoint inside every cone, weighted per-parameter sums) --------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_cone_grad_random_vs_psr(Q, eng, oracle_mod, seed):
+    rng = np.random.default_rng([31, seed])
+    n = int(rng.integers(4, 15))
+    kinds = (W.RX, W.RY, W.RZ, W.CZ, W.CNOT) if seed % 3 else (W.RX, W.RY, W.RZ, W.CZ, W.CNOT, W.U1)
+    c = W.random_circuit(n, 60, rng, kinds=kinds, p_fixed=0.1)
+    th = W.angles(max(c.n_params, 1), [31, seed])[: c.n_params]
+    letters = "Z" if seed % 2 == 0 else "XYZ"
+    H = W.random_hamiltonian(n, 10, rng, max_weight=min(n, 3), letters=letters)
+    mode = Q.MODE_LIGHTCONE if seed % 4 == 1 else Q.MODE_LIGHTCONE_FACTORED
+    say("cone grad random", seed, n, c.n_params, "mode", mode)
+    psr = oracle_mod.grad_psr(c, H, th)
+    E, g = eng.expect_grad(c, H, th, mode=mode)
+    assert abs(E - oracle_mod.expect(c, H, th)) <= tol(H, 0)
+    np.testing.assert_allclose(g, psr, atol=tol(H, 0))
+
+
+def test_cone_grad_c128(Q, eng, oracle_mod):
+    rng = np.random.default_rng([32, 0])
+    c = W.brickwork_ry_rz_cnot(11, 3)
+    H = W.tfim(11, 0.6)
+    th = W.angles(c.n_params, [32, 1])
+    say("cone grad c128")
+    for mode in (Q.MODE_LIGHTCONE, Q.MODE_LIGHTCONE_FACTORED):
+        E, g = eng.expect_grad(c, H, th, mode=mode, dtype=Q.C128)
+        assert abs(E - oracle_mod.expect(c, H, th)) <= tol(H, 1)
+        np.testing.assert_allclose(g, oracle_mod.grad_psr(c, H, th), atol=tol(H, 1))
+    del rng
+
+
+def test_cone_grad_n500_vs_oracle(Q, eng, oracle_mod):
+    """n=500, 4 layers of RY + CZ brickwork, 3-regular MaxCut: E and sampled gradient entries."""
+    w = W.lightcone_maxcut()
+    idx = np.array([0, 1, 250, 499, 500, 1001, 1500, 1999], dtype=np.int32)
+    want_E, _ = oracle_mod.expect_lightcone(w.circuit, w.H, w.theta)
+    want_g = oracle_mod.grad_psr_lightcone(w.circuit, w.H, w.theta, idx)
+    for mode in (Q.MODE_LIGHTCONE_FACTORED, Q.MODE_LIGHTCONE):
+        say("cone grad n500 mode", mode)
+        E, g = eng.expect_grad(w.circuit, w.H, w.theta, mode=mode)
+        assert abs(E - want_E) <= tol(w.H, 0), (E, want_E)
+        np.testing.assert_allclose(g[idx], want_g, atol=tol(w.H, 0))
+        assert np.all(np.isfinite(g))
+
+
+def test_cone_grad_product_state_n500(Q, eng):
+    """One RY layer: d<H>/dt_i = -sin t_i sum over neighbours j of cos t_j."""
+    n = 500
+    b = W.GateListBuilder(n)
+    for q in range(n):
+        b.rot(W.RY, q)
+    c = b.build()
+    edges = W.random_regular3(n, np.random.default_rng([3, 0]))
+    H = W.maxcut(edges)
+    th = W.angles(n, [3, 500, 7])
+    say("cone grad product n500")
+    E, g = eng.expect_grad(c, H, th, mode=Q.MODE_LIGHTCONE_FACTORED)
+    cs = np.cos(th)
+    want = np.zeros(n)
+    for a, bb in edges:
+        want[a] += -math.sin(th[a]) * cs[bb]
+        want[bb] += -math.sin(th[bb]) * cs[a]
+    np.testing.assert_allclose(g, want, atol=tol(H, 0))
+    assert abs(E - sum(cs[a] * cs[bb] for a, bb in edges)) <= tol(H, 0)
+
+
+def test_cone_grad_equals_dense_grad(Q, eng):
+    """The same gradient two ways on the device: full-state adjoint and per-cone adjoint."""
+    w = W.batched_grad_tfim(batch=2, n=14, depth=3)
+    say("cone grad vs dense n14")
+    E0, g0 = eng.expect_grad(w.circuit, w.H, w.theta)
+    for mode in (Q.MODE_LIGHTCONE, Q.MODE_LIGHTCONE_FACTORED):
+        E1, g1 = eng.expect_grad(w.circuit, w.H, w.theta, mode=mode)
+        np.testing.assert_allclose(E1, E0, atol=2 * tol(w.H, 0))
+        np.testing.assert_allclose(g1, g0, atol=2 * tol(w.H, 0))
+    # the same plan on the same input gives the same bits
+    E2, g2 = eng.expect_grad(w.circuit, w.H, w.theta, mode=Q.MODE_LIGHTCONE_FACTORED)
+    np.testing.assert_array_equal(E2, E1)
+    np.testing.assert_array_equal(g2, g1)
+
+
+def test_cone_grad_autograd(Q, eng, oracle_mod):
+    import torch
+
+    from paper_2112_10239_amd.autograd import expectation_cones
+
+    c = W.brickwork_ry_cz(40, 3)
+    H = W.maxcut(W.random_regular3(40, np.random.default_rng([33, 40])))
+    th = W.angles(c.n_params, [33, 1])
+    theta = torch.tensor(th[None, :], dtype=torch.float64, device="cuda:0", requires_grad=True)
+    say("cone autograd n40")
+    E = expectation_cones(theta, eng, c, H)
+    (2.0 * E.sum()).backward()
+    idx = np.array([0, 39, 40, 80, 119], dtype=np.int32)
+    want = oracle_mod.grad_psr_lightcone(c, H, th, idx)
+    np.testing.assert_allclose(theta.grad[0].cpu().numpy()[idx], 2.0 * want, atol=2 * tol(H, 0))
+    want_E, _ = oracle_mod.expect_lightcone(c, H, th)
+    assert abs(float(E[0]) - want_E) <= tol(H, 0)
+
+
+def test_cone_grad_errors(Q, eng):
+    w = W.lightcone_maxcut(n=60, depth=2)
+    with pytest.raises(Q.QsimError):
+        eng.expect_grad(w.circuit, w.H, w.theta, mode=99)
+    small = Q.Context(0, cone_cap=4)
+    try:
+        with pytest.raises(Q.QsimError) as ei:
+            small.expect_grad(w.circuit, w.H, w.theta, mode=Q.MODE_LIGHTCONE)
+        assert ei.value.code == Q.qsim.ETOOBIG
+    finally:
+        small.close()
