@@ -20,6 +20,10 @@ product simulator, Clifford Pauli propagation, the parameter-shift identity):
 ``grad_psr_lightcone``      equal to ``grad_psr`` (n<=12), closed-form
                             product-state gradient and Clifford shift rule
                             at n=500
+``partial_trace``           Bell/GHZ closed forms, product states, kept-qubit
+                            Pauli expectations equal to the full state's,
+                            invariance under gates on the traced qubits,
+                            brute-force sum over basis states (n<=6)
 ==========================  ================================================
 
 The C source ``qsim_oracle.c`` is compiled here with gcc (``build()``).
@@ -219,6 +223,22 @@ def grad_psr_lightcone(c, h, theta, idx, max_cone: int = 24) -> np.ndarray:
                                          ctypes.c_int(ix.size), _p(ix, ctypes.c_int32), _p(g, ctypes.c_double)),
            "grad_psr_lightcone")
     return g[: ix.size]
+
+
+def partial_trace(psi, n: int, keep) -> np.ndarray:
+    """Reduced density matrix of a pure state (paper, Sec. 2: partial trace as a
+    contraction): rho[i, j] = sum_k psi(i, k) conj(psi(j, k)), where bit a of i
+    (and j) is qubit keep[a] and k runs over the other qubits.  psi: 2^n complex
+    amplitudes, qubit q = bit q of the index.  Plain numpy, complex128."""
+    keep = [int(q) for q in keep]
+    m = len(keep)
+    rest = [q for q in range(n) if q not in keep]
+    # tensor axes: axis a of reshape(2,...,2) in C order is qubit n-1-a
+    t = np.asarray(psi, dtype=np.complex128).reshape((2,) * n)
+    ax_keep = [n - 1 - q for q in reversed(keep)]  # most significant kept bit first
+    ax_rest = [n - 1 - q for q in reversed(rest)]
+    M = np.transpose(t, ax_keep + ax_rest).reshape(2 ** m, 2 ** (n - m))
+    return M @ M.conj().T
 
 
 if __name__ == "__main__":  # pragma: no cover

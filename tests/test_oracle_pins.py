@@ -408,3 +408,100 @@ def test_golden_ring_maxcut_regenerates(oracle_mod):
     assert w.edges.tolist() == gold["edges"]
     assert oracle_mod.expect(w.circuit, w.H, w.theta) == pytest.approx(gold["E"], abs=1e-13)
     np.testing.assert_allclose(oracle_mod.grad_psr(w.circuit, w.H, w.theta), gold["grad_psr"], atol=1e-12)
+
+
+# --- reduced density matrices (partial trace) ----------------------------------------------
+
+def _ptrace_brute(psi, n, keep):
+    """Definition by enumeration: rho[i, j] = sum_k psi[x(i, k)] conj(psi[x(j, k)])."""
+    m = len(keep)
+    rest = [q for q in range(n) if q not in keep]
+    rho = np.zeros((2 ** m, 2 ** m), dtype=complex)
+
+    def idx(i, k):
+        x = 0
+        for a, q in enumerate(keep):
+            x |= ((i >> a) & 1) << q
+        for b, q in enumerate(rest):
+            x |= ((k >> b) & 1) << q
+        return x
+
+    for i in range(2 ** m):
+        for j in range(2 ** m):
+            rho[i, j] = sum(psi[idx(i, k)] * np.conj(psi[idx(j, k)]) for k in range(2 ** (n - m)))
+    return rho
+
+
+@pytest.mark.parametrize("keep", [[0], [2, 0], [1, 3, 4], [5, 0, 2, 1], [0, 1, 2, 3, 4, 5]])
+def test_partial_trace_brute_force(oracle_mod, keep):
+    rng = np.random.default_rng([40, len(keep)])
+    n = 6
+    psi = rng.normal(size=2 ** n) + 1j * rng.normal(size=2 ** n)
+    psi /= np.linalg.norm(psi)
+    np.testing.assert_allclose(oracle_mod.partial_trace(psi, n, keep), _ptrace_brute(psi, n, keep), atol=1e-14)
+
+
+def test_partial_trace_bell_ghz_product(oracle_mod):
+    # Bell pair on qubits 0, 1: either half is I/2
+    c = W.GateListBuilder(2)
+    c.rot(W.RY, 0, math.pi / 2)
+    c.two(W.CNOT, 0, 1)
+    psi = oracle_mod.statevector(c.build(), np.zeros(0))
+    for q in (0, 1):
+        np.testing.assert_allclose(oracle_mod.partial_trace(psi, 2, [q]), np.eye(2) / 2, atol=1e-15)
+    # GHZ_5: two kept qubits give diag(1/2, 0, 0, 1/2)
+    b = W.GateListBuilder(5)
+    b.rot(W.RY, 0, math.pi / 2)
+    for q in range(4):
+        b.two(W.CNOT, q, q + 1)
+    psi = oracle_mod.statevector(b.build(), np.zeros(0))
+    np.testing.assert_allclose(oracle_mod.partial_trace(psi, 5, [1, 3]), np.diag([0.5, 0, 0, 0.5]), atol=1e-15)
+    # product of RY(t_q)|0>: rho = kron of [[c^2, cs], [cs, s^2]] (c = cos t/2, s = sin t/2)
+    t = np.array([0.3, -1.1, 2.0, 0.7])
+    b = W.GateListBuilder(4)
+    for q in range(4):
+        b.rot(W.RY, q)
+    psi = oracle_mod.statevector(b.build(), t)
+    one = [np.array([[math.cos(x / 2) ** 2, math.cos(x / 2) * math.sin(x / 2)],
+                     [math.cos(x / 2) * math.sin(x / 2), math.sin(x / 2) ** 2]]) for x in t]
+    # keep = [3, 1]: bit 0 of i is qubit 3, bit 1 is qubit 1 -> kron(one[1], one[3])
+    np.testing.assert_allclose(oracle_mod.partial_trace(psi, 4, [3, 1]), np.kron(one[1], one[3]), atol=1e-15)
+
+
+def test_partial_trace_properties(oracle_mod):
+    w = W.dense_tfim(n=10, depth=3)
+    psi = oracle_mod.statevector(w.circuit, w.theta)
+    keep = [7, 2, 4]
+    rho = oracle_mod.partial_trace(psi, 10, keep)
+    assert np.trace(rho).real == pytest.approx(1.0, abs=1e-13)
+    np.testing.assert_allclose(rho, rho.conj().T, atol=1e-15)
+    assert np.linalg.eigvalsh(rho).min() > -1e-13
+    # Pauli strings on kept qubits: Tr(rho P) = <psi|P|psi>
+    rng = np.random.default_rng([41, 0])
+    for _ in range(6):
+        letters = rng.choice(list("IXYZ"), size=3)
+        if all(x == "I" for x in letters):
+            continue
+        H = W.Hamiltonian.from_terms([(1.0, [(q, str(L)) for q, L in zip(keep, letters) if L != "I"])])
+        mats = {"I": np.eye(2), "X": np.array([[0, 1], [1, 0]]), "Y": np.array([[0, -1j], [1j, 0]]),
+                "Z": np.diag([1.0, -1.0])}
+        P = np.array([[1.0]])
+        for L in reversed(letters):  # bit 2 of i (keep[2]) is the most significant factor
+            P = np.kron(P, mats[str(L)])
+        want = oracle_mod.expect_state(10, psi, H)[0]
+        assert np.trace(rho @ P).real == pytest.approx(want, abs=1e-12)
+    # gates on the traced qubits leave rho unchanged
+    b = W.GateListBuilder(10)
+    for q in (0, 1, 3, 5, 6, 8, 9):
+        b.rot(W.RX, q, 0.37 * q + 0.1)
+    b.two(W.CNOT, 0, 9)
+    b.two(W.CZ, 3, 5)
+    psi2 = psi.copy()
+    c2 = b.build()
+    from tests import pinlib
+    for u in pinlib.circuit_unitary_steps(c2, np.zeros(0)):
+        psi2 = u @ psi2
+    np.testing.assert_allclose(oracle_mod.partial_trace(psi2, 10, keep), rho, atol=1e-13)
+    # keeping every qubit gives the pure state's projector
+    full = oracle_mod.partial_trace(psi, 10, list(range(10)))
+    np.testing.assert_allclose(full, np.outer(psi, psi.conj()), atol=1e-15)
