@@ -140,6 +140,18 @@ int qsim_state_to_host(qsim_state* st, void* host);
 /* Device pointer of the amplitudes (layout as in qsim_create_state); flushes first. */
 int qsim_state_device_ptr(qsim_state* st, void** ptr);
 
+/* Reduced density matrices of the batch's states (Sec. 2: partial trace as a
+ * contraction of the state with its conjugate over the traced modes; the paper's
+ * n=20 example keeps 14 or 10 qubits): rho_b[i][j] = sum_k psi_b(i, k) conj(psi_b(j, k)),
+ * where bit a of i and j is qubit qubits[a] (any order, distinct) and k runs over the
+ * other qubits.  m = number of kept qubits, 1 <= m <= min(n, 15).  rho: [batch][2^m][2^m]
+ * complex of the state's dtype, row-major; a device buffer if rho_on_device, else host
+ * memory (the library stages through device memory).  Computed on the matrix cores in
+ * the state's precision (fp32 / fp64 accumulation); rho is exactly Hermitian (each
+ * off-diagonal pair is written from one value).  Flushes queued gates; returns when
+ * rho is complete.  QSIM_EINVAL on bad qubits or m. */
+int qsim_reduced_density(qsim_state* st, const int32_t* qubits, int m, void* rho, int rho_on_device);
+
 /* ---- one-call evaluation (Sec. 3: forward value) ----------------------------------- */
 
 /* out[b] = <psi(theta_b)|H|psi(theta_b)> for b < batch, theta_b = params + b*n_params
@@ -203,7 +215,10 @@ int qsim_timing_enable(qsim_ctx* ctx, int on);
  * rotation, 6 per phase, 0 per CNOT/CZ, plus measurement terms), flags[i] = the
  * pass flags (bit 1 generate |0...0>, 2 load psi, 4 store psi, 8 load lambda,
  * 16 store lambda, 64 measure, 128 gradient), kind[i] = 0 dense pass, 1
- * light-cone batch.  Any output pointer may be NULL.  *count = records copied. */
+ * light-cone batch, 2 reduced density matrix (bytes = state read once plus rho
+ * written once; flops = 4 N (N + 1) K per state for N = 2^m, K = 2^(n-m): the
+ * Hermitian product's lower triangle at 8 real flops per complex multiply-add).
+ * Any output pointer may be NULL.  *count = records copied. */
 int qsim_timing_get(qsim_ctx* ctx, double* ms, double* bytes, double* flops, int32_t* flags, int32_t* kind, int cap,
                     int* count);
 

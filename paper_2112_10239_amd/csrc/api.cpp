@@ -223,6 +223,90 @@ int qsim_state_to_host(qsim_state* st, void* host) {
   return QSIM_OK;
 }
 
+int qsim_reduced_density(qsim_state* st, const int32_t* qubits, int m, void* rho, int rho_on_device) {
+  if (check_state(st) || !qubits || !rho) return QSIM_EINVAL;
+  qsim_ctx* ctx = st->ctx;
+  const int n = st->n;
+  if (m < 1 || m > n || m > 15) {
+    set_error(ctx, "reduced_density: need 1 <= m <= min(n, 15) kept qubits");
+    return QSIM_EINVAL;
+  }
+  uint64_t keep_mask = 0;
+  for (int a = 0; a < m; ++a) {
+    if (qubits[a] < 0 || qubits[a] >= n || ((keep_mask >> qubits[a]) & 1)) {
+      set_error(ctx, "reduced_density: kept qubits must be distinct and in [0, n)");
+      return QSIM_EINVAL;
+    }
+    keep_mask |= 1ull << qubits[a];
+  }
+  if (ctx->mock) return no_device(ctx);
+  // offsets (in amplitudes) of the kept index i and of the traced index k = (hi, lo)
+  const int64_t N = 1ll << m, K = 1ll << (n - m);
+  const int lo_bits = std::min(n - m, 10);
+  std::vector<int> traced;
+  for (int q = 0; q < n; ++q)
+    if (!((keep_mask >> q) & 1)) traced.push_back(q);
+  std::vector<int64_t> tab((size_t)(N + (1ll << lo_bits) + (K >> lo_bits)));
+  int64_t* off_i = tab.data();
+  int64_t* klo = off_i + N;
+  int64_t* khi = klo + (1ll << lo_bits);
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t o = 0;
+    for (int a = 0; a < m; ++a) o |= ((i >> a) & 1) << qubits[a];
+    off_i[i] = o;
+  }
+  for (int64_t k = 0; k < (1ll << lo_bits); ++k) {
+    int64_t o = 0;
+    for (int b = 0; b < lo_bits; ++b) o |= ((k >> b) & 1) << traced[b];
+    klo[k] = o;
+  }
+  for (int64_t k = 0; k < (K >> lo_bits); ++k) {
+    int64_t o = 0;
+    for (int b = lo_bits; b < n - m; ++b) o |= ((k >> (b - lo_bits)) & 1) << traced[b];
+    khi[k] = o;
+  }
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  int rc = flush(st, nullptr, nullptr);
+  if (rc) return rc;
+  Workspace& ws = ctx->ws;
+  hipStream_t s = st->stream;
+  HIP_TRY(hipStreamSynchronize(s), "stream sync");  // the pinned staging buffer may still feed an upload
+  HIP_TRY(ws.table.ensure(tab.size() * sizeof(int64_t)), "density tables");
+  HIP_TRY(ws.h_coef.ensure(tab.size() * sizeof(int64_t)), "pinned table staging");
+  std::memcpy(ws.h_coef.p, tab.data(), tab.size() * sizeof(int64_t));
+  HIP_TRY(hipMemcpyAsync(ws.table.p, ws.h_coef.p, tab.size() * sizeof(int64_t), hipMemcpyHostToDevice, s),
+          "density table upload");
+  const size_t amp = amp_bytes(st->dtype);
+  const size_t out_bytes = (size_t)st->batch * (size_t)N * (size_t)N * amp;
+  void* dst = rho;
+  if (!rho_on_device) {
+    HIP_TRY(ws.dens.ensure(out_bytes), "density output buffer");
+    dst = ws.dens.p;
+  }
+  DensityLaunch L;
+  L.psi = st->buf;
+  L.row_stride = 1ll << n;
+  L.batch = st->batch;
+  L.off_i = static_cast<const int64_t*>(ws.table.p);
+  L.klo = L.off_i + N;
+  L.khi = L.klo + (1ll << lo_bits);
+  L.lo_bits = lo_bits;
+  L.N = (int)N;
+  L.K = K;
+  L.rho = dst;
+  L.c128 = st->dtype == QSIM_C128;
+  const double bytes = (double)st->batch * ((double)(1ll << n) * amp + (double)N * (double)N * amp);
+  const double flops = 4.0 * (double)N * (double)(N + 1) * (double)K * st->batch;
+  const int ti = timing_begin(ctx, s, bytes, 0, 2, flops);
+  HIP_TRY(launch_density(L, s), "density launch");
+  timing_end(ctx, ti, s);
+  if (!rho_on_device) HIP_TRY(hipMemcpyAsync(rho, dst, out_bytes, hipMemcpyDeviceToHost, s), "density copy");
+  HIP_TRY(hipStreamSynchronize(s), "stream sync");
+  timing_collect(ctx);
+  return QSIM_OK;
+}
+
 int qsim_state_device_ptr(qsim_state* st, void** ptr) {
   if (check_state(st) || !ptr) return QSIM_EINVAL;
   qsim_ctx* ctx = st->ctx;

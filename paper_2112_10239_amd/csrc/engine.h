@@ -95,7 +95,7 @@ struct DevPlan {
 };
 
 struct Workspace {
-  DevBuf coef, meas, grad, slot_total, out, scratch, lambda, weights;
+  DevBuf coef, meas, grad, slot_total, out, scratch, lambda, weights, table, dens;
   HostBuf h_coef, h_out;
   void release() {
     coef.release();
@@ -106,6 +106,8 @@ struct Workspace {
     scratch.release();
     lambda.release();
     weights.release();
+    table.release();
+    dens.release();
     h_coef.release();
     h_out.release();
   }

@@ -74,6 +74,23 @@ hipError_t launch_factor_weights(const double* fval, const int32_t* f_off, const
 hipError_t launch_weighted_scatter(const double* g, const int32_t* g_cone, const double* w, const int32_t* p_off,
                                    const int32_t* p_slots, int n_params, double* grad, hipStream_t stream);
 
+// Reduced density matrices rho_b = M_b M_b^dagger, M_b[i][k] = psi_b[off_i[i] + off_k(k)]
+// with off_k(k) = klo[k & (2^lo_bits - 1)] + khi[k >> lo_bits]; rho row-major [batch][N][N].
+struct DensityLaunch {
+  const void* psi;          // [batch][row_stride] complex amplitudes
+  int64_t row_stride;
+  int batch;
+  const int64_t* off_i;     // [N] amplitude offsets of the kept-qubit index
+  const int64_t* klo;       // [2^lo_bits] offsets of the low traced bits
+  const int64_t* khi;       // [K >> lo_bits] offsets of the high traced bits
+  int lo_bits;
+  int N;                    // 2^m
+  int64_t K;                // 2^(n-m)
+  void* rho;
+  int c128;
+};
+hipError_t launch_density(const DensityLaunch& L, hipStream_t stream);
+
 // Plain copy of n16 16-byte words (reference HBM stream).
 hipError_t launch_copy(const void* src, void* dst, uint64_t n16, hipStream_t stream);
 

@@ -68,7 +68,7 @@ EXPORTS = [
     "qsim_apply_layer", "qsim_expect", "qsim_state_to_host", "qsim_state_device_ptr", "qsim_expect_circuit",
     "qsim_expect_grad", "qsim_lightcone_sets", "qsim_plan_dense", "qsim_submit", "qsim_poll", "qsim_cancel",
     "qsim_server_stats_get", "qsim_timing_enable", "qsim_timing_get", "qsim_poll_timed", "qsim_clock",
-    "qsim_copy_probe", "qsim_expect_grad_cones",
+    "qsim_copy_probe", "qsim_expect_grad_cones", "qsim_reduced_density",
 ]
 
 
@@ -99,6 +99,7 @@ def _load():
         "qsim_expect_circuit": (I, [V, P(Circuit), P(D), I, P(Hamiltonian), I, I, V, P(D), P(V)]),
         "qsim_expect_grad": (I, [V, P(Circuit), P(D), I, P(Hamiltonian), I, V, V, P(D), P(D)]),
         "qsim_expect_grad_cones": (I, [V, P(Circuit), P(D), I, P(Hamiltonian), I, I, V, P(D), P(D)]),
+        "qsim_reduced_density": (I, [V, P(ctypes.c_int32), I, V, I]),
         "qsim_lightcone_sets": (I, [P(Circuit), P(Hamiltonian), P(ctypes.c_int32), P(ctypes.c_int32), I]),
         "qsim_plan_dense": (I, [P(Circuit), P(Hamiltonian), I, P(ctypes.c_int64), P(ctypes.c_int32), I]),
         "qsim_submit": (I, [V, P(Request), P(ctypes.c_uint64)]),
@@ -434,6 +435,25 @@ class State:
         dt = np.complex64 if self.dtype == C64 else np.complex128
         out = np.empty((self.batch, 1 << self.n), dtype=dt)
         self.ctx._check(lib.qsim_state_to_host(self.ptr, out.ctypes.data_as(ctypes.c_void_p)), "qsim_state_to_host")
+        return out
+
+    def reduced_density(self, qubits, out=None):
+        """rho[b] = Tr_rest |psi_b><psi_b| over the qubits not listed; bit a of rho's
+        index is qubits[a].  Returns a host array [batch, 2^m, 2^m], or fills 'out'
+        (a device tensor of that many complex elements of the state's dtype)."""
+        keep = np.ascontiguousarray(qubits, dtype=np.int32).reshape(-1)
+        N = 1 << keep.size
+        kp = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        if out is None:
+            dt = np.complex64 if self.dtype == C64 else np.complex128
+            host = np.empty((self.batch, N, N), dtype=dt)
+            self.ctx._check(lib.qsim_reduced_density(self.ptr, kp, keep.size, host.ctypes.data_as(ctypes.c_void_p), 0),
+                            "qsim_reduced_density")
+            return host
+        if out.numel() < self.batch * N * N or not out.is_contiguous():
+            raise ValueError("out must be a contiguous device tensor of batch * 4^m complex elements")
+        self.ctx._check(lib.qsim_reduced_density(self.ptr, kp, keep.size, ctypes.c_void_p(out.data_ptr()), 1),
+                        "qsim_reduced_density")
         return out
 
     def device_ptr(self) -> int:

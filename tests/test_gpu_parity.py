@@ -506,3 +506,83 @@ def test_cone_grad_errors(Q, eng):
         assert ei.value.code == Q.qsim.ETOOBIG
     finally:
         small.close()
+
+
+# --- reduced density matrices (partial trace on the matrix cores) --------------------------
+
+def _state(Q, eng, c, th, dtype=0, batch=1):
+    st = eng.create_state(c.n, batch=batch, dtype=dtype)
+    st.apply_layer(c.gates, np.tile(th, (batch, 1)) if c.n_params else None, c.n_params, c.mats)
+    return st
+
+
+@pytest.mark.parametrize("keep", [[0], [1, 0], [0, 1, 2, 3, 4, 5, 6], [9, 2, 5], [3, 11, 0, 7, 6],
+                                  list(range(12))])
+def test_density_small_vs_oracle(Q, eng, oracle_mod, keep):
+    w = W.dense_tfim(n=12, depth=3)
+    say("density n12 keep", keep)
+    st = _state(Q, eng, w.circuit, w.theta)
+    rho = st.reduced_density(keep)[0]
+    psi_gpu = st.to_host()[0]
+    st.destroy()
+    # the kernel's arithmetic against the oracle on the same (device) state
+    np.testing.assert_allclose(rho, oracle_mod.partial_trace(psi_gpu, 12, keep), atol=2e-6)
+    # end to end against the oracle's own state
+    psi = oracle_mod.statevector(w.circuit, w.theta)
+    np.testing.assert_allclose(rho, oracle_mod.partial_trace(psi, 12, keep), atol=1e-5)
+    np.testing.assert_array_equal(rho, rho.conj().T)
+
+
+def test_density_c128_batch(Q, eng, oracle_mod):
+    w = W.batched_grad_tfim(batch=2, n=10, depth=3)
+    say("density c128 batch 2")
+    st = eng.create_state(10, batch=2, dtype=Q.C128)
+    st.apply_layer(w.circuit.gates, w.theta, w.circuit.n_params, w.circuit.mats)
+    keep = [4, 0, 8, 2]
+    rho = st.reduced_density(keep)
+    st.destroy()
+    for b in range(2):
+        psi = oracle_mod.statevector(w.circuit, w.theta[b])
+        np.testing.assert_allclose(rho[b], oracle_mod.partial_trace(psi, 10, keep), atol=1e-12)
+
+
+@pytest.mark.parametrize("m", [10, 14])
+def test_density_n20_paper_sizes(Q, eng, m):
+    """n=20 keeping 10 or 14 qubits: sampled entries against direct sums on the same state,
+    trace 1, exact Hermitian symmetry, and <Z_q> of kept qubits equal to the state's."""
+    import torch
+
+    w = W.dense_tfim(n=20, depth=4)
+    say("density n20 m", m)
+    st = _state(Q, eng, w.circuit, w.theta)
+    keep = list(range(m))
+    N = 1 << m
+    rho_t = torch.empty((N, N), dtype=torch.complex64, device="cuda:0")
+    st.reduced_density(keep, out=rho_t)
+    psi = st.to_host()[0].astype(np.complex128)
+    zq = st.expect(W.Hamiltonian.from_terms([(1.0, [(3, "Z")])]))[0]
+    st.destroy()
+    rho = rho_t.cpu().numpy()
+    M = psi.reshape(1 << (20 - m), N)  # row k, column i (kept qubits are the low bits)
+    rng = np.random.default_rng([42, m])
+    for _ in range(64):
+        i, j = (int(x) for x in rng.integers(0, N, size=2))
+        want = np.dot(M[:, i], np.conj(M[:, j]))
+        assert abs(rho[i, j] - want) <= 2e-6, (i, j, rho[i, j], want)
+    diag = np.real(np.diag(rho)).astype(np.float64)
+    assert abs(diag.sum() - 1.0) <= 1e-4
+    sign = 1.0 - 2.0 * ((np.arange(N) >> 3) & 1)
+    assert abs(float(np.dot(diag, sign)) - zq) <= 1e-5
+    i = rng.integers(0, N, size=256)
+    j = rng.integers(0, N, size=256)
+    np.testing.assert_array_equal(rho[i, j], np.conj(rho[j, i]))
+
+
+def test_density_errors(Q, eng):
+    st = eng.create_state(6)
+    try:
+        for bad in ([0, 0], [6], [-1], []):
+            with pytest.raises(Q.QsimError):
+                st.reduced_density(bad)
+    finally:
+        st.destroy()
