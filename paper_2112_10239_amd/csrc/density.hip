@@ -12,7 +12,7 @@
 // Tiling: a workgroup of four waves owns a (32*WB) x (32*WB) output tile of
 // the lower triangle (tile row >= tile column); each wave owns a
 // (16*WB) x (16*WB) corner of it as WB x WB blocks of 16 x 16, and writes
-// each block both at (i, j) and, conjugated, at (j, i).  Operands come
+// each element below the diagonal both at (i, j) and, conjugated, at (j, i).  Operands come
 // straight from HBM/L2 (each amplitude of a k-slice is read by the tiles of
 // its row and column); the next k-slice is loaded before the current one is
 // multiplied.
@@ -124,8 +124,10 @@ __global__ __launch_bounds__(256) void k_density(const T* __restrict__ psi, int6
         ci[a][b] = Mfma<T>::step(-xc[a].x, yc[b].y, ci[a][b]);
       }
   }
+  // Each pair (i > j) is written from one value, at (i, j) and conjugated at
+  // (j, i); the diagonal keeps its real part (its imaginary part is zero up to
+  // rounding).  The upper half of a diagonal tile is left to the mirror writes.
   A2* out = reinterpret_cast<A2*>(rho) + (int64_t)blockIdx.y * N * N;
-  const bool mirror = ti != tj;
 #pragma unroll
   for (int a = 0; a < WB; ++a)
 #pragma unroll
@@ -133,9 +135,13 @@ __global__ __launch_bounds__(256) void k_density(const T* __restrict__ psi, int6
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t i = i0 + 16 * a + 4 * kq + v, j = j0 + 16 * b + r16;
-        if (i < N && j < N) {
-          out[i * N + j] = A2{cr[a][b][v], ci[a][b][v]};
-          if (mirror) out[j * N + i] = A2{cr[a][b][v], -ci[a][b][v]};
+        if (i < N && j < N && i >= j) {
+          if (i == j) {
+            out[i * N + i] = A2{cr[a][b][v], T(0)};
+          } else {
+            out[i * N + j] = A2{cr[a][b][v], ci[a][b][v]};
+            out[j * N + i] = A2{cr[a][b][v], -ci[a][b][v]};
+          }
         }
       }
 }

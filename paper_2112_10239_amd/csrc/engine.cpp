@@ -70,6 +70,7 @@ static double pass_bytes(const PassDesc& p, int rows, int c128) {
 
 // Tuning knobs read once from the environment (for A/B measurements):
 // QSIM_FWD_R = register bits of complex64 forward passes (4 or 5, default 5),
+// QSIM_FWD_M = tile qubits of complex64 forward passes (12..14, default 14),
 // QSIM_ABSORB = 0 disables CNOT exit permutations.
 static int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
@@ -104,9 +105,10 @@ static double pass_flops_per_amp(const Plan& P, const PassDesc& pd) {
 
 PlanOptions fwd_options(int c128) {
   static const int r64 = env_int("QSIM_FWD_R", 5) == 4 ? 4 : 5;
+  static const int m64 = std::min(14, std::max(12, env_int("QSIM_FWD_M", 14)));
   static const bool absorb = env_int("QSIM_ABSORB", 1) != 0;
   PlanOptions o;
-  o.m_max = c128 ? 13 : 14;
+  o.m_max = c128 ? 13 : m64;
   o.r = c128 ? 4 : r64;
   o.c_low = 6;
   o.absorb = absorb;

@@ -17,6 +17,7 @@
 // passes: per-thread sums in the state's precision over the thread's
 // registers, fp64 across threads, one fp64 partial per tile, then a
 // fixed-order cross-tile reduction, so results do not depend on scheduling.
+#include <cstdlib>
 #include <type_traits>
 
 #include "kernels.h"
@@ -903,6 +904,16 @@ int device_cus() {
   return cus;
 }
 
+// QSIM_FWD_PF=0 turns off the next-tile prefetch of the 32-register forward
+// kernel (a tuning knob for A/B measurements; default on).
+bool fwd_prefetch() {
+  static const bool on = [] {
+    const char* v = std::getenv("QSIM_FWD_PF");
+    return !v || std::atoi(v) != 0;
+  }();
+  return on;
+}
+
 template <class T, int R, bool DUAL, bool PF>
 hipError_t launch_pass_t(const PassLaunch& L, hipStream_t stream) {
   const int m = L.h_pass->m, n = L.h_pass->n;
@@ -935,7 +946,8 @@ hipError_t launch_pass_r(const PassLaunch& L, hipStream_t stream) {
       else return launch_pass_t<T, 4, DUAL, DUAL && sizeof(T) == 4>(L, stream);
     case 5:
       if constexpr (DUAL || sizeof(T) == 8) return hipErrorInvalidValue;
-      else return launch_pass_t<T, 5, false, true>(L, stream);
+      else return fwd_prefetch() ? launch_pass_t<T, 5, false, true>(L, stream)
+                                 : launch_pass_t<T, 5, false, false>(L, stream);
     default: return hipErrorInvalidValue;
   }
 }
