@@ -12,10 +12,10 @@
 // Tiling: a workgroup of four waves owns a (32*WB) x (32*WB) output tile of
 // the lower triangle (tile row >= tile column); each wave owns a
 // (16*WB) x (16*WB) corner of it as WB x WB blocks of 16 x 16, and writes
-// each element below the diagonal both at (i, j) and, conjugated, at (j, i).  Operands come
-// straight from HBM/L2 (each amplitude of a k-slice is read by the tiles of
-// its row and column); the next k-slice is loaded before the current one is
-// multiplied.
+// each element below the diagonal both at (i, j) and, conjugated, at (j, i).
+// Operands come straight from HBM/L2 (each amplitude of a k-slice is read by
+// the tiles of its row and column); the next k-slice is loaded before the
+// current one is multiplied.
 #include <cmath>
 
 #include "kernels.h"
@@ -32,6 +32,8 @@ struct Mfma<float> {
   static __device__ __forceinline__ v4 step(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  // result item v of lane group q = l / 16 is row 4 q + v
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
 };
 
 template <>
@@ -40,6 +42,8 @@ struct Mfma<double> {
   static __device__ __forceinline__ v4 step(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  // the fp64 variant interleaves the rows: item v of lane group q is row 4 v + q
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * v + q; }
 };
 
 template <class T>
@@ -55,7 +59,7 @@ struct Amp2<double> {
 
 // MFMA 16x16x4 operand/result layout (per lane l of the wave):
 //   A operand: element (row l % 16, k l / 16); B operand: (k l / 16, col l % 16);
-//   result v = 0..3: element (row 4 * (l / 16) + v, col l % 16).
+//   result v = 0..3: element (row Mfma<T>::row(l / 16, v), col l % 16).
 template <class T, int WB>
 __global__ __launch_bounds__(256) void k_density(const T* __restrict__ psi, int64_t row_stride,
                                                  const int64_t* __restrict__ off_i,
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(256) void k_density(const T* __restrict__ psi, int6
     for (int b = 0; b < WB; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t i = i0 + 16 * a + 4 * kq + v, j = j0 + 16 * b + r16;
+        const int64_t i = i0 + 16 * a + Mfma<T>::row(kq, v), j = j0 + 16 * b + r16;
         if (i < N && j < N && i >= j) {
           if (i == j) {
             out[i * N + i] = A2{cr[a][b][v], T(0)};
