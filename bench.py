@@ -164,6 +164,61 @@ def bench_grad(Q, W, reps=2):
                 pass_GBs=gbs)
 
 
+def bench_lightcone_grad(Q, W, reps=5):
+    """<H> and its full gradient at n=500 with the adjoint inside every light cone."""
+    import torch
+
+    w = W.lightcone_maxcut()
+    out = dict(workload="lightcone_maxcut_n500_d4: <H> + d<H>/dtheta (2000 parameters), one cone launch")
+    for name, mode in (("canonical", Q.MODE_LIGHTCONE), ("factored", Q.MODE_LIGHTCONE_FACTORED)):
+        ctx = Q.Context(0)
+        ctx.expect_grad(w.circuit, w.H, w.theta, mode=mode)
+        ctx.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            E, g = ctx.expect_grad(w.circuit, w.H, w.theta, mode=mode)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rec = ctx.timing_get()
+        ctx.close()
+        out[name] = dict(evals_grads_per_s=reps / (t1 - t0), cone_kernel_ms=float(rec["ms"][rec["kind"] == 1].mean()),
+                         E=E, grad_norm=float(np.linalg.norm(g)))
+    return out
+
+
+def bench_density(Q, W, reps=5):
+    """Reduced density matrices of an n=20 state keeping 10 or 14 qubits (fp32 matrix cores)."""
+    import torch
+
+    w = W.dense_tfim(n=20, depth=4)
+    out = dict(workload="dense_tfim n=20 state; rho of the low m qubits, complex64")
+    ctx = Q.Context(0)
+    st = ctx.create_state(20)
+    st.apply_layer(w.circuit.gates, w.theta, w.circuit.n_params, w.circuit.mats)
+    for m in (10, 14):
+        N = 1 << m
+        rho = torch.empty((N, N), dtype=torch.complex64, device="cuda:0")
+        st.reduced_density(list(range(m)), out=rho)
+        ctx.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st.reduced_density(list(range(m)), out=rho)
+        t1 = time.perf_counter()
+        ctx.timing_enable(False)
+        rec = ctx.timing_get()
+        k = rec["kind"] == 2
+        ms = float(rec["ms"][k].mean())
+        fl = float(rec["flops"][k].mean())
+        by = float(rec["bytes"][k].mean())
+        out[f"m{m}"] = dict(kernel_ms=ms, call_ms=(t1 - t0) / reps * 1e3, TFLOPs=fl / (ms * 1e-3) / 1e12,
+                            mfma_frac=fl / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, GBs=by / (ms * 1e-3) / 1e9,
+                            trace=float(torch.diagonal(rho).real.sum()))
+        del rho
+    st.destroy()
+    ctx.close()
+    return out
+
+
 def bench_small(Q, W, reps=200):
     w = W.small_ring_maxcut()
     ctx = Q.Context(0)
@@ -329,6 +384,7 @@ def main():
         line["cpu_baseline"] = cpu_baseline(W)
     if not args.no_extras:
         line["extras"] = {"lightcone": bench_lightcone(Q, W), "gradient": bench_grad(Q, W),
+                          "lightcone_gradient": bench_lightcone_grad(Q, W), "density": bench_density(Q, W),
                           "small_c128": bench_small(Q, W)}
     if args.serving > 0:
         line.setdefault("extras", {})["serving"] = bench_serving(Q, W, args.serving)
