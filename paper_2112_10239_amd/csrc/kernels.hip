@@ -83,6 +83,19 @@ __device__ __forceinline__ uint32_t kh(kptr<uint16_t> p) {
   return (*(kptr<uint32_t>)(a & ~(uintptr_t)3) >> (8 * (a & 2))) & 0xffffu;
 }
 
+// A dword-aligned descriptor array read once as NW scalar dwords; elements are
+// then extracted with constant shifts (indices are compile-time in unrolled loops).
+template <int NW>
+struct KWords {
+  uint32_t w[NW];
+  __device__ __forceinline__ explicit KWords(const void __attribute__((address_space(4))) * p) {
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = *((kptr<uint32_t>)p + i);
+  }
+  __device__ __forceinline__ uint32_t u8(int k) const { return (w[k >> 2] >> (8 * (k & 3))) & 0xffu; }
+  __device__ __forceinline__ uint32_t u16(int k) const { return (w[k >> 1] >> (16 * (k & 1))) & 0xffffu; }
+};
+
 template <int N>
 using IC = std::integral_constant<int, N>;
 
@@ -341,19 +354,26 @@ struct TileRegs {
   cpx<T> b[DUAL ? (1 << R) : 1];
 };
 
+// Physical index of a tile's first amplitude: the tile number's bits deposited
+// at the non-local positions (uniform across the workgroup: scalar work).
 __device__ __forceinline__ uint64_t tile_base(kptr<PassDesc> P, uint64_t tile) {
-  uint64_t base = 0;
+  const KWords<kMaxQubits / 4> np(P->npos);
   const int nn = P->n - P->m;
-  for (int k = 0; k < nn; ++k)
-    if ((tile >> k) & 1) base |= 1ull << kb(&P->npos[k]);
+  uint64_t base = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxQubits; ++k)
+    if (k < nn && ((tile >> k) & 1)) base |= 1ull << np.u8(k);
   return base;
 }
 
 // Thread-local part of stage S's local index (thread bits deposited into tb).
 template <int R>
 __device__ __forceinline__ uint32_t thread_local_index(kptr<StageDesc> S, int m, int tid) {
+  const KWords<kMaxLocal / 4> tb(S->tb);
   uint32_t tl = 0;
-  for (int k = 0; k < m - R; ++k) tl |= ((uint32_t)(tid >> k) & 1u) << kb(&S->tb[k]);
+#pragma unroll
+  for (int k = 0; k < kMaxLocal - R; ++k)
+    if (k < m - R) tl |= ((uint32_t)(tid >> k) & 1u) << tb.u8(k);
   return tl;
 }
 
@@ -362,11 +382,14 @@ template <int R>
 __device__ __forceinline__ uint64_t stage_gaddr(kptr<PassDesc> P, kptr<StageDesc> S, int tid, uint64_t base,
                                                 uint64_t* gr) {
   const int m = P->m;
+  const KWords<kMaxLocal / 4> tp(S->tpos);
+  const KWords<2> rp(S->rpos);
   uint64_t gt = base;
-  for (int k = 0; k < m - R; ++k)
-    if ((tid >> k) & 1) gt |= 1ull << kb(&P->lpos[kb(&S->tb[k])]);
 #pragma unroll
-  for (int j = 0; j < R; ++j) gr[j] = 1ull << kb(&P->lpos[kb(&S->rb[j])]);
+  for (int k = 0; k < kMaxLocal - R; ++k)
+    if (k < m - R) gt |= (uint64_t)((uint32_t)(tid >> k) & 1u) << tp.u8(k);
+#pragma unroll
+  for (int j = 0; j < R; ++j) gr[j] = 1ull << rp.u8(j);
   return gt;
 }
 
@@ -412,9 +435,10 @@ __device__ __forceinline__ void tile_load(kptr<PassDesc> P, kptr<StageDesc> S0, 
   } else {
     const bool active = tid < (1 << (m - R));
     const uint32_t tl = thread_local_index<R>(S0, m, tid);
+    const KWords<2> rbw(S0->rb);
     uint32_t rl[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) rl[j] = 1u << kb(&S0->rb[j]);
+    for (int j = 0; j < R; ++j) rl[j] = 1u << rbw.u8(j);
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       uint32_t o = tl;
@@ -465,9 +489,13 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
   for (int s = s0; s < s1; ++s) {
     kptr<StageDesc> S = SD + s;
     const uint32_t tl = thread_local_index<R>(S, m, tid);
+    const KWords<2> rbw(S->rb);
     uint32_t rl[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) rl[j] = 1u << kb(&S->rb[j]);
+    for (int j = 0; j < R; ++j) rl[j] = 1u << rbw.u8(j);
+    // The swizzle is linear over XOR and the thread and register bits are
+    // disjoint, so an LDS slot is swz(tl) ^ swz(register offset): one lane
+    // value and one uniform value per register (byte offsets here).
     auto roff = [&](int i) __attribute__((always_inline)) {
       uint32_t o = 0;
 #pragma unroll
@@ -475,13 +503,17 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         if ((i >> j) & 1) o |= rl[j];
       return o;
     };
+    const uint32_t tl_b = swz(tl) * (uint32_t)sizeof(cpx<T>);
+    auto slot = [&](uint32_t lane_b, uint32_t uni) __attribute__((always_inline)) {
+      return reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(lds) + (lane_b ^ (swz(uni) * (uint32_t)sizeof(cpx<T>))));
+    };
     if (s != s0) {
       // lanes past the tile read valid slots (their local index keeps only tile bits) and are zeroed
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
-        const uint32_t l = swz(tl | roff(i));
-        a[i] = ld_amp(lds + l);
-        if constexpr (DUAL) b[i] = ld_amp(lds + tsize + l);
+        cpx<T>* l = slot(tl_b, roff(i));
+        a[i] = ld_amp(l);
+        if constexpr (DUAL) b[i] = ld_amp(l + tsize);
       }
       if (!active) {
 #pragma unroll
@@ -618,24 +650,29 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
       if (active) {
         if (kh(&S->has_perm)) {
           // write every amplitude to its image under the stage's exit permutation
+          const KWords<kMaxLocal / 2> tcol(S->tcol);
           uint32_t w = 0;
-          for (int k = 0; k < m - R; ++k)
-            if ((tid >> k) & 1) w ^= kh(&S->tcol[k]);
+#pragma unroll
+          for (int k = 0; k < kMaxLocal - R; ++k)
+            if (k < m - R) w ^= ((uint32_t)(tid >> k) & 1u) ? tcol.u16(k) : 0u;
           const int n_aff = (int)kh(&S->n_aff);
+          uint32_t wa = 0;  // affine part: tile bits (uniform)
           for (int j = 0; j < n_aff; ++j)
-            if ((base >> kb(&S->aff_pos[j])) & 1) w ^= kh(&S->aff_mask[j]);
+            if ((base >> kb(&S->aff_pos[j])) & 1) wa ^= kh(&S->aff_mask[j]);
+          const uint32_t w_b = swz(w ^ wa) * (uint32_t)sizeof(cpx<T>);
+          const KWords<(1 << R) / 2> preg(S->preg);
 #pragma unroll
           for (int i = 0; i < NR; ++i) {
-            const uint32_t l = swz(w ^ kh(&S->preg[i]));
-            st_amp(lds + l, a[i]);
-            if constexpr (DUAL) st_amp(lds + tsize + l, b[i]);
+            cpx<T>* l = slot(w_b, preg.u16(i));
+            st_amp(l, a[i]);
+            if constexpr (DUAL) st_amp(l + tsize, b[i]);
           }
         } else {
 #pragma unroll
           for (int i = 0; i < NR; ++i) {
-            const uint32_t l = swz(tl | roff(i));
-            st_amp(lds + l, a[i]);
-            if constexpr (DUAL) st_amp(lds + tsize + l, b[i]);
+            cpx<T>* l = slot(tl_b, roff(i));
+            st_amp(l, a[i]);
+            if constexpr (DUAL) st_amp(l + tsize, b[i]);
           }
         }
       }

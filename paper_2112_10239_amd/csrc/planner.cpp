@@ -628,11 +628,17 @@ struct PassEmitter {
       StageDesc st;
       std::memset(&st, 0, sizeof(st));
       const auto& rb = sb[si].rb;
-      for (int j = 0; j < r; ++j) st.rb[j] = (uint8_t)rb[j];
+      for (int j = 0; j < r; ++j) {
+        st.rb[j] = (uint8_t)rb[j];
+        st.rpos[j] = (uint8_t)L[rb[j]];
+      }
       {
         int t = 0;
         for (int k = 0; k < m; ++k)
-          if (!rb_has(rb, k)) st.tb[t++] = (uint8_t)k;
+          if (!rb_has(rb, k)) {
+            st.tpos[t] = (uint8_t)L[k];
+            st.tb[t++] = (uint8_t)k;
+          }
       }
       st.op_begin = (int)plan.ops.size();
       const auto& its = sb[si].items;

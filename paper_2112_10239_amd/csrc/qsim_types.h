@@ -75,8 +75,10 @@ struct StageDesc {
   uint16_t preg[1 << kMaxRegBits];  // M applied to register offset i
   uint8_t aff_pos[kMaxAffine];      // physical non-local bit of affine term j
   uint16_t aff_mask[kMaxAffine];    // xor into the image when that bit is 1
+  uint8_t tpos[kMaxLocal];  // physical bit of thread bit k (the pass's lpos[tb[k]])
+  uint8_t rpos[8];          // physical bit of register bit j (lpos[rb[j]])
 };
-static_assert(sizeof(StageDesc) == 156, "StageDesc layout");
+static_assert(sizeof(StageDesc) == 180, "StageDesc layout");
 
 enum PassFlags : int32_t {
   PF_INIT = 1,      // first stage generates |0...0> instead of loading a
