@@ -354,16 +354,31 @@ struct TileRegs {
   cpx<T> b[DUAL ? (1 << R) : 1];
 };
 
-// Physical index of a tile's first amplitude: the tile number's bits deposited
-// at the non-local positions (uniform across the workgroup: scalar work).
-__device__ __forceinline__ uint64_t tile_base(kptr<PassDesc> P, uint64_t tile) {
-  const KWords<kMaxQubits / 4> np(P->npos);
+// Physical index bits of the non-local qubits of a pass (uniform, scalar work).
+__device__ __forceinline__ uint64_t nonlocal_mask(kptr<PassDesc> P) {
   const int nn = P->n - P->m;
-  uint64_t base = 0;
-#pragma unroll
-  for (int k = 0; k < kMaxQubits; ++k)
-    if (k < nn && ((tile >> k) & 1)) base |= 1ull << np.u8(k);
-  return base;
+  uint64_t M = 0;
+  for (int k = 0; k < nn; ++k) M |= 1ull << kb(&P->npos[k]);
+  return M;
+}
+
+// The bits of x deposited, lowest first, at the set bits of M.
+__device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t M) {
+  uint64_t r = 0;
+  for (uint64_t m = M; m && x; m &= m - 1, x >>= 1)
+    if (x & 1) r |= m & (~m + 1);
+  return r;
+}
+
+// Physical index of a tile's first amplitude: the tile number deposited at the
+// non-local positions.  Walking tiles by a fixed stride d, the next base is
+// ((base | ~M) + deposit(d, M)) & M: the carries skip the local positions.
+__device__ __forceinline__ uint64_t tile_base(kptr<PassDesc> P, uint64_t tile) {
+  return deposit(tile, nonlocal_mask(P));
+}
+
+__device__ __forceinline__ uint64_t next_base(uint64_t base, uint64_t M, uint64_t dstep) {
+  return ((base | ~M) + dstep) & M;
 }
 
 // Thread-local part of stage S's local index (thread bits deposited into tb).
@@ -739,14 +754,16 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass(
   TileRegs<T, R, DUAL> cur;
   int64_t row = w >> sh;
   uint64_t tile = (uint64_t)(w & (tiles - 1));
-  uint64_t base = tile_base(P, tile);
+  const uint64_t M = nonlocal_mask(P);
+  const uint64_t dstep = deposit((uint64_t)gridDim.x & (uint64_t)(tiles - 1), M);
+  uint64_t base = deposit(tile, M);
   tile_load<T, R, DUAL>(P, S0, A + row * row_stride, DUAL ? B + row * row_stride : nullptr, base, cur);
   while (true) {
     const int64_t wn = w + gridDim.x;
     const bool more = wn < total;
     const int64_t rown = wn >> sh;
     const uint64_t tilen = (uint64_t)(wn & (tiles - 1));
-    const uint64_t basen = more ? tile_base(P, tilen) : 0;
+    const uint64_t basen = next_base(base, M, dstep);
     if constexpr (PF) {
       TileRegs<T, R, DUAL> nxt;
       if (more)
@@ -831,8 +848,9 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_cones(
   for (int p = cd->pass_begin; p < pass_end; ++p) {
     const kptr<PassDesc> pp = P + p;
     const int64_t tiles = 1ll << (pp->n - pp->m);
-    for (int64_t t = 0; t < tiles; ++t) {
-      const uint64_t base = tile_base(pp, (uint64_t)t);
+    const uint64_t M = nonlocal_mask(pp), d1 = M & (~M + 1);
+    uint64_t base = 0;
+    for (int64_t t = 0; t < tiles; ++t, base = next_base(base, M, d1)) {
       TileRegs<T, R, DUAL> regs;
       tile_load<T, R, DUAL>(pp, SD + pp->stage_begin, st, st_b, base, regs);
       total += tile_run<T, R, DUAL>(pp, SD, OPS, st, st_b, cf, base, regs, lds, red, gacc, grad, 1, t > 0);
