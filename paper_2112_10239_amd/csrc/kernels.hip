@@ -469,7 +469,7 @@ __device__ __forceinline__ void tile_load(kptr<PassDesc> P, kptr<StageDesc> S0, 
 
 // All stages of a tile whose first-stage registers are loaded: ops, LDS
 // exchanges (with exit permutations), the store, and the block's partial sums.
-template <class T, int R, bool DUAL>
+template <class T, int R, bool DUAL, bool TAIL = false>
 __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD, kptr<DevOp> OPS,
                                            cpx<T>* __restrict__ A, cpx<T>* __restrict__ B, kptr<T> coef, uint64_t base,
                                            TileRegs<T, R, DUAL>& t, cpx<T>* lds, double* red, double* gacc,
@@ -642,7 +642,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
       }
     }
 
-    if (s == sst) {
+    if (!TAIL && s == sst) {
       const bool st_a = (flags & PF_STORE_A) != 0, st_b = DUAL && (flags & PF_STORE_B) != 0;
       uint64_t gr[R];
       const uint64_t gt = stage_gaddr<R>(P, S, tid, base, gr);
@@ -694,6 +694,22 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
       lds_sync();
     }
   }
+  if constexpr (TAIL) {
+    // The caller guarantees: psi is stored after the last stage and every lane
+    // holds amplitudes of the tile.  Stores issued unconditionally let the
+    // compiler count them, so waiting for a prefetched tile does not also wait
+    // for these stores to complete.
+    uint64_t gr[R];
+    const uint64_t gt = stage_gaddr<R>(P, SD + (s1 - 1), tid, base, gr);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      uint64_t g = gt;
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if ((i >> j) & 1) g |= gr[j];
+      st_amp(A + g, a[i]);
+    }
+  }
   double total = 0.0;
   if (flags & PF_MEASURE) {
     const double v = wave_sum(acc);
@@ -732,7 +748,7 @@ constexpr int pass_max_threads() {
 // next tile before working on the current one, so the loads overlap the
 // register and LDS work (a 2^14-amplitude tile fills a CU's LDS, leaving no
 // second workgroup to overlap with); this needs twice the data registers.
-template <class T, int R, bool DUAL, bool PF>
+template <class T, int R, bool DUAL, bool PF, bool TAIL = false>
 __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass(
     const PassDesc* __restrict__ Pg, const StageDesc* __restrict__ SDg, const DevOp* __restrict__ OPSg, cpx<T>* A,
     cpx<T>* B, int64_t row_stride, const T* __restrict__ coefg, int64_t coef_row_stride, double* meas, int n_meas,
@@ -769,8 +785,9 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass(
       if (more)
         tile_load<T, R, DUAL>(P, S0, A + rown * row_stride, DUAL ? B + rown * row_stride : nullptr, basen, nxt);
       double* gout = (DUAL && grad) ? grad + row * n_gslots * tiles + (int64_t)tile : nullptr;
-      const double v = tile_run<T, R, DUAL>(P, SD, OPS, A + row * row_stride, DUAL ? B + row * row_stride : nullptr,
-                                            coef + row * coef_row_stride, base, cur, lds, red, gacc, gout, tiles);
+      const double v = tile_run<T, R, DUAL, TAIL>(P, SD, OPS, A + row * row_stride,
+                                                  DUAL ? B + row * row_stride : nullptr, coef + row * coef_row_stride,
+                                                  base, cur, lds, red, gacc, gout, tiles);
       if ((P->flags & PF_MEASURE) && threadIdx.x == 0)
         meas[(row * n_meas + P->meas_index) * tiles + (int64_t)tile] = v;
       if (!more) break;
@@ -969,11 +986,11 @@ bool fwd_prefetch() {
   return on;
 }
 
-template <class T, int R, bool DUAL, bool PF>
+template <class T, int R, bool DUAL, bool PF, bool TAIL = false>
 hipError_t launch_pass_t(const PassLaunch& L, hipStream_t stream) {
   const int m = L.h_pass->m, n = L.h_pass->n;
   const size_t lds = pass_lds_bytes(m, sizeof(T) == 8, DUAL);
-  auto kern = k_pass<T, R, DUAL, PF>;
+  auto kern = k_pass<T, R, DUAL, PF, TAIL>;
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = std::max(64, 1 << (m - R));
@@ -1001,8 +1018,13 @@ hipError_t launch_pass_r(const PassLaunch& L, hipStream_t stream) {
       else return launch_pass_t<T, 4, DUAL, DUAL && sizeof(T) == 4>(L, stream);
     case 5:
       if constexpr (DUAL || sizeof(T) == 8) return hipErrorInvalidValue;
-      else return fwd_prefetch() ? launch_pass_t<T, 5, false, true>(L, stream)
-                                 : launch_pass_t<T, 5, false, false>(L, stream);
+      else {
+        if (!fwd_prefetch()) return launch_pass_t<T, 5, false, false>(L, stream);
+        // psi stored after the last stage by every lane: the store-at-the-end variant
+        const PassDesc& p = *L.h_pass;
+        const bool tail = (p.flags & PF_STORE_A) && p.store_stage == p.stage_end - 1 && p.m - 5 >= 6;
+        return tail ? launch_pass_t<T, 5, false, true, true>(L, stream) : launch_pass_t<T, 5, false, true>(L, stream);
+      }
     default: return hipErrorInvalidValue;
   }
 }
