@@ -69,8 +69,8 @@ static double pass_bytes(const PassDesc& p, int rows, int c128) {
 }
 
 // Tuning knobs read once from the environment (for A/B measurements):
-// QSIM_FWD_R = register bits of complex64 forward passes (4 or 5, default 5),
-// QSIM_FWD_M = tile qubits of complex64 forward passes (12..14, default 14),
+// QSIM_FWD_R = register bits of complex64 forward passes (4 or 5, default 4),
+// QSIM_FWD_M = tile qubits of complex64 forward passes (12..14, default 13),
 // QSIM_ABSORB = 0 disables CNOT exit permutations.
 static int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
@@ -104,8 +104,11 @@ static double pass_flops_per_amp(const Plan& P, const PassDesc& pd) {
 }
 
 PlanOptions fwd_options(int c128) {
-  static const int r64 = env_int("QSIM_FWD_R", 5) == 4 ? 4 : 5;
-  static const int m64 = std::min(14, std::max(12, env_int("QSIM_FWD_M", 14)));
+  // 2^13-amplitude tiles with 16 per thread: two 512-thread workgroups per CU
+  // (64 KiB of LDS each), so one workgroup's exchanges and barriers overlap the
+  // other's arithmetic (measured faster than one 2^14 tile with 32 per thread).
+  static const int r64 = env_int("QSIM_FWD_R", 4) == 5 ? 5 : 4;
+  static const int m64 = std::min(14, std::max(12, env_int("QSIM_FWD_M", 13)));
   static const bool absorb = env_int("QSIM_ABSORB", 1) != 0;
   PlanOptions o;
   o.m_max = c128 ? 13 : m64;
