@@ -810,33 +810,44 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass(
 
 template <class T, int R, bool DUAL>
 __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass_multi(const PassItem* __restrict__ items,
-                                                                             int n_items, int m_max) {
+                                                                             int n_items, int m_max, int64_t total) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
   double* red = reinterpret_cast<double*>(smem + ((size_t)(DUAL ? 2 : 1) * sizeof(cpx<T>) << m_max));
   double* gacc = red + kRedSlots;
-  const int64_t b = blockIdx.x;
   const kptr<PassItem> KI = kc(items);
-  int lo = 0, hi = n_items - 1;
-  while (lo < hi) {  // last item with tile_begin <= b
-    const int mid = (lo + hi + 1) >> 1;
-    if ((KI + mid)->tile_begin <= b) lo = mid;
-    else hi = mid - 1;
+  // Persistent workgroups walk the launch's tiles b, b + gridDim.x, ...; the
+  // items' tile ranges ascend, so each search starts at the current item.
+  int cur = 0;
+  kptr<PassItem> it = KI;
+  kptr<PassDesc> P = kc(it->pass);
+  uint64_t M = nonlocal_mask(P);
+  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    int lo = cur, hi = n_items - 1;
+    while (lo < hi) {  // last item with tile_begin <= b
+      const int mid = (lo + hi + 1) >> 1;
+      if ((KI + mid)->tile_begin <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    if (lo != cur) {
+      cur = lo;
+      it = KI + lo;
+      P = kc(it->pass);
+      M = nonlocal_mask(P);
+    }
+    const kptr<StageDesc> SD = kc(it->stages);
+    const int64_t tiles = 1ll << (P->n - P->m);
+    const uint64_t tile = (uint64_t)(b - it->tile_begin);
+    const uint64_t base = deposit(tile, M);
+    double* gout = (DUAL && it->grad) ? it->grad + (int64_t)tile : nullptr;
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(it->A);
+    cpx<T>* B = reinterpret_cast<cpx<T>*>(it->B);
+    TileRegs<T, R, DUAL> t;
+    tile_load<T, R, DUAL>(P, SD + P->stage_begin, A, B, base, t);
+    const double v = tile_run<T, R, DUAL>(P, SD, kc(it->ops), A, B, kc(reinterpret_cast<const T*>(it->coef)), base,
+                                          t, lds, red, gacc, gout, tiles);
+    if ((P->flags & PF_MEASURE) && threadIdx.x == 0) it->meas[(int64_t)P->meas_index * tiles + (int64_t)tile] = v;
   }
-  const kptr<PassItem> it = KI + lo;
-  const kptr<PassDesc> P = kc(it->pass);
-  const kptr<StageDesc> SD = kc(it->stages);
-  const int64_t tiles = 1ll << (P->n - P->m);
-  const uint64_t tile = (uint64_t)(b - it->tile_begin);
-  const uint64_t base = tile_base(P, tile);
-  double* gout = (DUAL && it->grad) ? it->grad + (int64_t)tile : nullptr;
-  cpx<T>* A = reinterpret_cast<cpx<T>*>(it->A);
-  cpx<T>* B = reinterpret_cast<cpx<T>*>(it->B);
-  TileRegs<T, R, DUAL> t;
-  tile_load<T, R, DUAL>(P, SD + P->stage_begin, A, B, base, t);
-  const double v = tile_run<T, R, DUAL>(P, SD, kc(it->ops), A, B, kc(reinterpret_cast<const T*>(it->coef)), base, t,
-                                        lds, red, gacc, gout, tiles);
-  if ((P->flags & PF_MEASURE) && threadIdx.x == 0) it->meas[(int64_t)P->meas_index * tiles + (int64_t)tile] = v;
 }
 
 // One workgroup per cone: the cone's passes run in order, each over its tiles.
@@ -1049,7 +1060,9 @@ hipError_t launch_multi_t(const PassItem* items, int n_items, int64_t total, int
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = std::max(64, 1 << (m_max - R));
-  hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(threads), lds, stream, items, n_items, m_max);
+  const int per_cu = std::max(1, std::min((int)((size_t)max_lds_bytes() / lds), 2048 / threads));
+  const int64_t grid = std::min<int64_t>(total, (int64_t)device_cus() * per_cu);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, stream, items, n_items, m_max, total);
   return hipGetLastError();
 }
 
