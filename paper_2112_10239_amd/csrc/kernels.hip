@@ -561,6 +561,64 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
             if constexpr (DUAL) ap_x<T, R, J>(b, c);
           }
         });
+      } else if (!DUAL && R <= 4 && (type == OP_UALL || type == OP_RYALL)) {
+        // one rotation per register bit, bits 0..R-1 in order: straight-line code
+        const BitSel nc{BK_NONE, 0u, 0u};
+        auto slot_u = [&](int J) __attribute__((always_inline)) { return coef + (int64_t)(op + 1 + J)->slot * 8; };
+        if (type == OP_UALL) {
+          auto apply = [&](auto JC) __attribute__((always_inline)) {
+            constexpr int J = decltype(JC)::value;
+            const kptr<T> u = slot_u(J);
+            ap_u<T, R, J>(a, u, nc);
+            if constexpr (DUAL) ap_u<T, R, J>(b, u, nc);
+          };
+          apply(IC<0>{});
+          // no interleaving across bits: the compiler would keep several bits' partial
+          // results live at once and spill
+          if constexpr (R > 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            apply(IC<1>{});
+          }
+          if constexpr (R > 2) {
+            __builtin_amdgcn_sched_barrier(0);
+            apply(IC<2>{});
+          }
+          if constexpr (R > 3) {
+            __builtin_amdgcn_sched_barrier(0);
+            apply(IC<3>{});
+          }
+          if constexpr (R > 4) {
+            __builtin_amdgcn_sched_barrier(0);
+            apply(IC<4>{});
+          }
+        } else {
+          auto apply = [&](auto JC) __attribute__((always_inline)) {
+            constexpr int J = decltype(JC)::value;
+            const kptr<T> u = slot_u(J);
+            ap_ry<T, R, J>(a, u, nc);
+            if constexpr (DUAL) ap_ry<T, R, J>(b, u, nc);
+          };
+          apply(IC<0>{});
+          // no interleaving across bits: the compiler would keep several bits' partial
+          // results live at once and spill
+          if constexpr (R > 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            apply(IC<1>{});
+          }
+          if constexpr (R > 2) {
+            __builtin_amdgcn_sched_barrier(0);
+            apply(IC<2>{});
+          }
+          if constexpr (R > 3) {
+            __builtin_amdgcn_sched_barrier(0);
+            apply(IC<3>{});
+          }
+          if constexpr (R > 4) {
+            __builtin_amdgcn_sched_barrier(0);
+            apply(IC<4>{});
+          }
+        }
+        o += R;
       } else if (type == OP_PHASE) {
         kptr<T> d = coef + (int64_t)op->slot * 8;
         const BitSel c = mkbit(ck, cb, tl, base);

@@ -331,6 +331,7 @@ struct PassEmitter {
   std::vector<int> lidx;  // physical -> local index (-1 = non-local)
 
   bool allow_absorb = true;
+  bool allow_fused_bits = false;  // OP_UALL / OP_RYALL (single-state kernels with r <= 4 only)
 
   PassEmitter(Plan& p, int n_, int m_, int r_, uint64_t Lmask) : plan(p), n(n_), m(m_), r(r_), lidx(n_, -1) {
     for (int q = 0; q < n; ++q)
@@ -644,6 +645,39 @@ struct PassEmitter {
       const auto& its = sb[si].items;
       for (size_t ii = 0; ii < its.size(); ++ii) {
         const PGate* g = its[ii];
+        // r uncontrolled rotations of one kind on all r register bits (distinct qubits,
+        // so they commute): one op applying them bit by bit
+        if (allow_fused_bits && r <= 4 && (g->kind == PG_U || g->kind == PG_RY) && g->q2 < 0 &&
+            ii + r <= its.size()) {
+          std::vector<int> slot_of(r, -1);
+          bool full = true;
+          for (int k = 0; k < r && full; ++k) {
+            const PGate* h = its[ii + k];
+            const BitRef b = bitref(h->q, rb);
+            if (h->kind != g->kind || h->q2 >= 0 || b.kind != BK_REG || slot_of[b.idx] >= 0) full = false;
+            else slot_of[b.idx] = (int)(ii + k);
+          }
+          if (full) {
+            DevOp head;
+            std::memset(&head, 0, sizeof(head));
+            head.type = g->kind == PG_U ? OP_UALL : OP_RYALL;
+            head.slot = r;
+            const int at = (int)plan.ops.size() - st.op_begin;
+            plan.ops.push_back(head);
+            for (int j = 0; j < r; ++j) {
+              const PGate* h = its[slot_of[j]];
+              plan.ops.push_back(to_devop(*h, rb));
+              for (int src : h->srcs) {
+                plan.order.push_back(pass_no);
+                plan.order.push_back(si);
+                plan.order.push_back(at);
+                plan.order.push_back(src);
+              }
+            }
+            ii += r - 1;
+            continue;
+          }
+        }
         if (g->kind == PG_MEAS_Z) {  // a run of diagonal terms becomes one grouped op
           size_t jj = ii;
           while (jj < its.size() && its[jj]->kind == PG_MEAS_Z) ++jj;
@@ -806,6 +840,7 @@ int plan_forward(int n, const std::vector<PGate>& gates, const std::vector<PGate
     if (!last || o.store_final || !mLs.empty()) flags |= PF_STORE_A;
     PassEmitter em(plan, n, m, r, Ls[p]);
     em.allow_absorb = o.absorb;
+    em.allow_fused_bits = true;
     std::vector<const PGate*> mod;
     for (int idx : lists[p]) mod.push_back(&gates[idx]);
     em.emit(mod, last ? fin : std::vector<const PGate*>{}, flags, c_low, p);

@@ -34,6 +34,8 @@ enum OpType : uint8_t {
   OP_H_F = 12,    // b_i += c i^ph (-1)^{z(i^f)} a_{i^f}
   OP_MEAS_ZS = 13,// group of diagonal terms: the next 'slot' ops are term records (rz, tz, pz, c);
                   // acc += sum_t c_t (-1)^{thread/tile parity} W[rz_t], W = Walsh transform of |a_i|^2
+  OP_UALL = 14,   // one uncontrolled op per register bit: the next r ops are OP_U (or, with j = 1 in the
+  OP_RYALL = 15,  // header, OP_RY) records for register bits 0..r-1 in order (gates on distinct qubits)
 };
 
 // Bit reference kinds for controls, diagonal bits and z-masks.
