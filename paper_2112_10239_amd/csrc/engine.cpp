@@ -71,6 +71,7 @@ static double pass_bytes(const PassDesc& p, int rows, int c128) {
 // Tuning knobs read once from the environment (for A/B measurements):
 // QSIM_FWD_R = register bits of complex64 forward passes (4 or 5, default 4),
 // QSIM_FWD_M = tile qubits of complex64 forward passes (12..14, default 13),
+// QSIM_FWD_CLOW = index bits always local for coalescing (3..6, default 4),
 // QSIM_ABSORB = 0 disables CNOT exit permutations.
 static int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
@@ -109,11 +110,15 @@ PlanOptions fwd_options(int c128) {
   // other's arithmetic (measured faster than one 2^14 tile with 32 per thread).
   static const int r64 = env_int("QSIM_FWD_R", 4) == 5 ? 5 : 4;
   static const int m64 = std::min(14, std::max(12, env_int("QSIM_FWD_M", 13)));
+  // four always-local low bits: 128-byte contiguous segments per access (a full
+  // cache line) while leaving more local positions for gates (23 passes instead
+  // of 33 at six for the n=30 workload; measured faster)
+  static const int clow = std::min(6, std::max(3, env_int("QSIM_FWD_CLOW", 4)));
   static const bool absorb = env_int("QSIM_ABSORB", 1) != 0;
   PlanOptions o;
   o.m_max = c128 ? 13 : m64;
   o.r = c128 ? 4 : r64;
-  o.c_low = 6;
+  o.c_low = clow;
   o.absorb = absorb;
   return o;
 }
