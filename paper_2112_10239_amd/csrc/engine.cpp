@@ -72,6 +72,7 @@ static double pass_bytes(const PassDesc& p, int rows, int c128) {
 // QSIM_FWD_R = register bits of complex64 forward passes (4 or 5, default 4),
 // QSIM_FWD_M = tile qubits of complex64 forward passes (12..14, default 13),
 // QSIM_FWD_CLOW = index bits always local for coalescing (3..6, default 4),
+// QSIM_DUAL_CLOW = the same for dual-state (adjoint) passes (default 6),
 // QSIM_ABSORB = 0 disables CNOT exit permutations.
 static int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
@@ -135,7 +136,8 @@ PlanOptions dual_options(int c128) {
   o.absorb = absorb;
   o.m_max = c128 ? 12 : 13;
   o.r = c128 ? 3 : 4;
-  o.c_low = 6;
+  static const int clow = std::min(6, std::max(3, env_int("QSIM_DUAL_CLOW", 6)));
+  o.c_low = clow;
   o.fuse = false;
   return o;
 }
