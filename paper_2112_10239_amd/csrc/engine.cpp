@@ -69,7 +69,7 @@ static double pass_bytes(const PassDesc& p, int rows, int c128) {
 }
 
 // Tuning knobs read once from the environment (for A/B measurements):
-// QSIM_FWD_R = register bits of complex64 forward passes (4 or 5, default 4),
+// QSIM_FWD_R = register bits of complex64 forward passes (3..5, default 4),
 // QSIM_FWD_M = tile qubits of complex64 forward passes (12..14, default 13),
 // QSIM_FWD_CLOW = index bits always local for coalescing (3..6, default 4),
 // QSIM_DUAL_CLOW = the same for dual-state (adjoint) passes (default 6),
@@ -109,7 +109,7 @@ PlanOptions fwd_options(int c128) {
   // 2^13-amplitude tiles with 16 per thread: two 512-thread workgroups per CU
   // (64 KiB of LDS each), so one workgroup's exchanges and barriers overlap the
   // other's arithmetic (measured faster than one 2^14 tile with 32 per thread).
-  static const int r64 = env_int("QSIM_FWD_R", 4) == 5 ? 5 : 4;
+  static const int r64 = std::min(5, std::max(3, env_int("QSIM_FWD_R", 4)));
   static const int m64 = std::min(14, std::max(12, env_int("QSIM_FWD_M", 13)));
   // four always-local low bits: 128-byte contiguous segments per access (a full
   // cache line) while leaving more local positions for gates (23 passes instead
@@ -118,7 +118,7 @@ PlanOptions fwd_options(int c128) {
   static const bool absorb = env_int("QSIM_ABSORB", 1) != 0;
   PlanOptions o;
   o.m_max = c128 ? 13 : m64;
-  o.r = c128 ? 4 : r64;
+  o.r = c128 ? 4 : std::max(r64, o.m_max - 10);  // at most 1024 threads per workgroup
   o.c_low = clow;
   o.absorb = absorb;
   return o;

@@ -1055,6 +1055,19 @@ bool fwd_prefetch() {
   return on;
 }
 
+// Workgroups of a kernel resident on one CU at once (occupancy query; at least 1).
+template <class K>
+int resident_per_cu(K kernel, int threads, size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kernel), threads, lds) !=
+          hipSuccess ||
+      nb < 1) {
+    (void)hipGetLastError();
+    nb = std::max(1, std::min((int)((size_t)max_lds_bytes() / lds), 2048 / threads));
+  }
+  return nb;
+}
+
 template <class T, int R, bool DUAL, bool PF, bool TAIL = false>
 hipError_t launch_pass_t(const PassLaunch& L, hipStream_t stream) {
   const int m = L.h_pass->m, n = L.h_pass->n;
@@ -1063,8 +1076,8 @@ hipError_t launch_pass_t(const PassLaunch& L, hipStream_t stream) {
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = std::max(64, 1 << (m - R));
-  // persistent workgroups: as many as fit on the device at once (LDS and thread limits)
-  const int per_cu = std::max(1, std::min((int)((size_t)max_lds_bytes() / lds), 2048 / threads));
+  // persistent workgroups: as many as fit on the device at once (registers, LDS, threads)
+  const int per_cu = resident_per_cu(kern, threads, lds);
   const int64_t total = (int64_t)L.rows << (n - m);
   const int64_t grid = std::min<int64_t>(total, (int64_t)device_cus() * per_cu);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, stream, L.d_pass, L.d_stages, L.d_ops,
@@ -1081,7 +1094,14 @@ hipError_t launch_pass_r(const PassLaunch& L, hipStream_t stream) {
   switch (L.h_pass->r) {
     case 1: return launch_pass_t<T, 1, DUAL, false>(L, stream);
     case 2: return launch_pass_t<T, 2, DUAL, false>(L, stream);
-    case 3: return launch_pass_t<T, 3, DUAL, false>(L, stream);
+    case 3:
+      if constexpr (!DUAL && sizeof(T) == 4) {
+        // 8 amplitudes per thread leave room for a register prefetch of the next tile
+        const PassDesc& p = *L.h_pass;
+        if (fwd_prefetch() && p.m - 3 >= 6 && (p.flags & PF_STORE_A) && p.store_stage == p.stage_end - 1)
+          return launch_pass_t<T, 3, false, true, true>(L, stream);
+      }
+      return launch_pass_t<T, 3, DUAL, false>(L, stream);
     case 4:
       if constexpr (DUAL && sizeof(T) == 8) return hipErrorInvalidValue;
       else return launch_pass_t<T, 4, DUAL, DUAL && sizeof(T) == 4>(L, stream);
@@ -1118,7 +1138,7 @@ hipError_t launch_multi_t(const PassItem* items, int n_items, int64_t total, int
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = std::max(64, 1 << (m_max - R));
-  const int per_cu = std::max(1, std::min((int)((size_t)max_lds_bytes() / lds), 2048 / threads));
+  const int per_cu = resident_per_cu(kern, threads, lds);
   const int64_t grid = std::min<int64_t>(total, (int64_t)device_cus() * per_cu);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, stream, items, n_items, m_max, total);
   return hipGetLastError();
