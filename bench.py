@@ -100,7 +100,7 @@ def bench_dense(Q, W, steps, warmup):
         roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm_frac)
     else:
         roof = dict(bound="alu", achieved=tflops, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=alu_frac)
-    roof.update(traffic=load_traffic("dense_pass_n30"), kernel="k_pass<float, 4, false, false>",
+    roof.update(traffic=load_traffic("dense_pass_n30"), kernel="k_pass<float, 4, false, false, false>",
                 launches_per_step=launches / steps, avg_launch_ms=avg_ms, algorithmic_bytes_per_launch=avg_bytes,
                 algorithmic_flops_per_launch=avg_flops, hbm_GBs=gbs, hbm_frac=hbm_frac, alu_TFLOPs=tflops,
                 alu_frac=alu_frac, load_store_passes_GBs=gate_gbs, copy_kernel_GBs=copy_gbs)
