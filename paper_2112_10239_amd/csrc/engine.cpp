@@ -92,6 +92,8 @@ static double pass_flops_per_amp(const Plan& P, const PassDesc& pd) {
       const DevOp& op = P.ops[o];
       switch (op.type) {
         case OP_U: f += 16; break;
+        case OP_UTAB: f += 4 * P.r + 6; break;  // a real 2x2 per register bit + the post table
+        case OP_DTAB: f += 6; break;
         case OP_RY: f += 8; break;
         case OP_PHASE: f += 6; break;
         case OP_MEAS_ZS: f += 3 + 2.0 * op.slot; o += op.slot; break;
@@ -116,17 +118,22 @@ PlanOptions fwd_options(int c128) {
   // of 33 at six for the n=30 workload; measured faster)
   static const int clow = std::min(6, std::max(3, env_int("QSIM_FWD_CLOW", 4)));
   static const bool absorb = env_int("QSIM_ABSORB", 1) != 0;
+  // uncontrolled rotations on a stage's register bits as one factored op (two
+  // multiply-adds per amplitude and bit plus one diagonal table) in float plans
+  static const bool factored = env_int("QSIM_FACTORED", 1) != 0;
   PlanOptions o;
   o.m_max = c128 ? 13 : m64;
   o.r = c128 ? 4 : std::max(r64, o.m_max - 10);  // at most 1024 threads per workgroup
   o.c_low = clow;
   o.absorb = absorb;
+  o.factored = factored && !c128 && o.r <= 4;
   return o;
 }
 
 PlanOptions cone_options(int c128) {
   PlanOptions o = fwd_options(c128);
   o.r = 4;  // the cone kernel keeps 16 amplitudes per thread
+  o.factored = false;
   return o;
 }
 

@@ -215,6 +215,35 @@ __device__ __forceinline__ void ap_x(cpx<T>* a, const BitSel& c) {
   }
 }
 
+// Real factor T = [[1, -k], [k, 1]] of a factored rotation on register bit J
+// (|k| <= 1; the diagonal factors are in the tables): one multiply-add per
+// output component.
+template <class T, int R, int J>
+__device__ __forceinline__ void ap_tan(cpx<T>* a, T k) {
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    if (i & (1 << J)) continue;
+    const int i1 = i | (1 << J);
+    const cpx<T> x0 = a[i], x1 = a[i1];
+    a[i].x = x0.x - k * x1.x;
+    a[i].y = x0.y - k * x1.y;
+    a[i1].x = x1.x + k * x0.x;
+    a[i1].y = x1.y + k * x0.y;
+  }
+}
+
+// Diagonal over the register index: a[i] *= d[i] (complex, one per register value).
+template <class T, int R>
+__device__ __forceinline__ void ap_table(cpx<T>* a, kptr<T> d) {
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const T dr = d[2 * i], di = d[2 * i + 1];
+    const cpx<T> x = a[i];
+    a[i].x = dr * x.x - di * x.y;
+    a[i].y = dr * x.y + di * x.x;
+  }
+}
+
 template <class T, int R>
 __device__ __forceinline__ void ap_phase(cpx<T>* a, kptr<T> d, const BitSel& b) {
   const T d0r = d[0], d0i = d[1], d1r = d[2], d1i = d[3];
@@ -501,8 +530,10 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
   }
   double acc = 0.0;
   const int s0 = P->stage_begin, s1 = P->stage_end, sst = P->store_stage;
+  uint32_t pend = 0;  // register i holds the amplitude of register index i ^ pend
   for (int s = s0; s < s1; ++s) {
     kptr<StageDesc> S = SD + s;
+    pend = 0;
     const uint32_t tl = thread_local_index<R>(S, m, tid);
     const KWords<2> rbw(S->rb);
     uint32_t rl[R];
@@ -619,6 +650,31 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
           }
         }
         o += R;
+      } else if (!DUAL && R <= 4 && std::is_same<T, float>::value && type == OP_UTAB) {
+        // rotations U_j = X^f P_j T_j E_j on every register bit (the last op of its
+        // stage; the E table, when needed, is an OP_DTAB just before): each real T_j,
+        // the P table; the swaps X^f stay pending as an XOR mask on the register
+        // index, which the stage's exit addressing applies (block: 32 + 32 table
+        // scalars, k per bit, swap mask as a raw word)
+        const kptr<T> blk = coef + (int64_t)op->slot * 8;
+        ap_tan<T, R, 0>(a, blk[64]);
+        if constexpr (R > 1) {
+          __builtin_amdgcn_sched_barrier(0);
+          ap_tan<T, R, 1>(a, blk[65]);
+        }
+        if constexpr (R > 2) {
+          __builtin_amdgcn_sched_barrier(0);
+          ap_tan<T, R, 2>(a, blk[66]);
+        }
+        if constexpr (R > 3) {
+          __builtin_amdgcn_sched_barrier(0);
+          ap_tan<T, R, 3>(a, blk[67]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        ap_table<T, R>(a, blk);
+        pend = *(kptr<uint32_t>)(blk + 68) & (uint32_t)(NR - 1);
+      } else if (!DUAL && R <= 4 && std::is_same<T, float>::value && type == OP_DTAB) {
+        ap_table<T, R>(a, coef + (int64_t)op->slot * 8 + 32);
       } else if (type == OP_PHASE) {
         kptr<T> d = coef + (int64_t)op->slot * 8;
         const BitSel c = mkbit(ck, cb, tl, base);
@@ -633,7 +689,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         T p[NR];  // |a_i|^2
 #pragma unroll
         for (int i = 0; i < NR; ++i) p[i] = a[i].x * a[i].x + a[i].y * a[i].y;
-        const uint32_t par = (__popc(tl & op->tz) + __popcll(base & op->pz)) & 1;
+        const uint32_t par = (__popc(tl & op->tz) + __popcll(base & op->pz) + __popc(op->rz & pend)) & 1;
         const double v = (double)meas_zp<T, R>(p, op->rz);
         acc += op->c * (par ? -v : v);
       } else if (type == OP_MEAS_ZS) {
@@ -656,7 +712,9 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         T part = 0;
         for (int k = 1; k <= nt; ++k) {
           kptr<DevOp> tr = OPS + o + k;
-          const uint32_t par = (__popc(tl & tr->tz) + __popcll(base & tr->pz)) & 1;
+          // with pending register swaps, register i holds index i ^ pend: the term's
+          // sign gains the parity of rz & pend
+          const uint32_t par = (__popc(tl & tr->tz) + __popcll(base & tr->pz) + __popc(tr->rz & pend)) & 1;
           T wv = 0;
           if (tr->rz == 0u) {
             wv = wt[0];
@@ -669,7 +727,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         acc += (double)part;
         o += nt;
       } else if (type == OP_MEAS_F) {
-        const uint32_t par = (__popc(tl & op->tz) + __popcll(base & op->pz)) & 1;
+        const uint32_t par = (__popc(tl & op->tz) + __popcll(base & op->pz) + __popc(op->rz & pend)) & 1;
         for_mask<NR>(op->fr, [&](auto FC) __attribute__((always_inline)) {
           constexpr int F = decltype(FC)::value;
           acc += op->c * meas_f<T, R, F>(a, op->rz, par, ph);
@@ -703,14 +761,18 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     if (!TAIL && s == sst) {
       const bool st_a = (flags & PF_STORE_A) != 0, st_b = DUAL && (flags & PF_STORE_B) != 0;
       uint64_t gr[R];
-      const uint64_t gt = stage_gaddr<R>(P, S, tid, base, gr);
+      uint64_t gt = stage_gaddr<R>(P, S, tid, base, gr);
+      // gt has zeros at the register bits, so index i ^ pend is gt ^ (bits of pend) ^ (bits of i)
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if ((pend >> j) & 1u) gt ^= gr[j];
       if (active) {
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
           uint64_t g = gt;
 #pragma unroll
           for (int j = 0; j < R; ++j)
-            if ((i >> j) & 1) g |= gr[j];
+            if ((i >> j) & 1) g ^= gr[j];
           if (st_a) st_amp(A + g, a[i]);
           if constexpr (DUAL) {
             if (st_b) st_amp(B + g, b[i]);
@@ -732,7 +794,9 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
           uint32_t wa = 0;  // affine part: tile bits (uniform)
           for (int j = 0; j < n_aff; ++j)
             if ((base >> kb(&S->aff_pos[j])) & 1) wa ^= kh(&S->aff_mask[j]);
-          const uint32_t w_b = swz(w ^ wa) * (uint32_t)sizeof(cpx<T>);
+          // register i holds index i ^ pend; preg is linear, so its image is preg(i) ^ preg(pend)
+          const uint32_t wp = pend ? kh(&S->preg[pend]) : 0u;
+          const uint32_t w_b = swz(w ^ wa ^ wp) * (uint32_t)sizeof(cpx<T>);
           const KWords<(1 << R) / 2> preg(S->preg);
 #pragma unroll
           for (int i = 0; i < NR; ++i) {
@@ -741,9 +805,14 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
             if constexpr (DUAL) st_amp(l + tsize, b[i]);
           }
         } else {
+          uint32_t rp = 0;  // roff(pend)
+#pragma unroll
+          for (int j = 0; j < R; ++j)
+            if ((pend >> j) & 1u) rp |= rl[j];
+          const uint32_t wl_b = tl_b ^ (swz(rp) * (uint32_t)sizeof(cpx<T>));
 #pragma unroll
           for (int i = 0; i < NR; ++i) {
-            cpx<T>* l = slot(tl_b, roff(i));
+            cpx<T>* l = slot(wl_b, roff(i));
             st_amp(l, a[i]);
             if constexpr (DUAL) st_amp(l + tsize, b[i]);
           }
@@ -758,13 +827,16 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     // compiler count them, so waiting for a prefetched tile does not also wait
     // for these stores to complete.
     uint64_t gr[R];
-    const uint64_t gt = stage_gaddr<R>(P, SD + (s1 - 1), tid, base, gr);
+    uint64_t gt = stage_gaddr<R>(P, SD + (s1 - 1), tid, base, gr);
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if ((pend >> j) & 1u) gt ^= gr[j];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       uint64_t g = gt;
 #pragma unroll
       for (int j = 0; j < R; ++j)
-        if ((i >> j) & 1) g |= gr[j];
+        if ((i >> j) & 1) g ^= gr[j];
       st_amp(A + g, a[i]);
     }
   }

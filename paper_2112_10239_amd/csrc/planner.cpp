@@ -48,8 +48,22 @@ std::string validate_circuit(const CircuitDesc& c) {
       case G_RZ:
         if (x.param >= c.n_params) return at + "parameter index out of range";
         break;
-      case G_U1:
+      case G_U1: {  // the factored rotation form relies on unitarity
+        double err = 0;
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) {
+            double re = (i == j) ? -1.0 : 0.0, im = 0.0;  // (U^dagger U - I)_ij
+            for (int k = 0; k < 2; ++k) {
+              const double ar = x.mat[(k * 2 + i) * 2], ai = -x.mat[(k * 2 + i) * 2 + 1];
+              const double br = x.mat[(k * 2 + j) * 2], bi = x.mat[(k * 2 + j) * 2 + 1];
+              re += ar * br - ai * bi;
+              im += ar * bi + ai * br;
+            }
+            err = std::max(err, std::max(std::fabs(re), std::fabs(im)));
+          }
+        if (!(err <= 1e-8)) return at + "U1 matrix is not unitary";
         break;
+      }
       default:
         return at + "unknown gate kind";
     }
@@ -116,6 +130,20 @@ void forward_pgates(const CircuitDesc& c, bool fuse, std::vector<PGate>& out, st
   }
   for (auto& p : out) {
     if (p.kind == PG_U || p.kind == PG_RY || p.kind == PG_PHASE) {
+      // RY's then RZ's: the factored form needs no pre-diagonal
+      bool seen_diag = false, seen_ry = false, ok = true;
+      for (int g : p.srcs) {
+        const int k = c.gates[g].kind;
+        if (k == G_RY) {
+          ok = ok && !seen_diag;
+          seen_ry = true;
+        } else if (k == G_RZ) {
+          seen_diag = true;
+        } else {
+          ok = false;
+        }
+      }
+      p.real_pre = ok && seen_ry;
       p.slot = (int)slots.size();
       slots.push_back(p);
     }
@@ -190,7 +218,7 @@ void term_pgates(const std::vector<Term>& terms, bool happly, std::vector<PGate>
 
 namespace {
 
-bool is_term(const PGate& g) { return g.kind >= PG_MEAS_Z; }
+bool is_term(const PGate& g) { return g.kind >= PG_MEAS_Z && g.kind <= PG_H_F; }
 
 // Qubits that must be local (register-resident) for g to be applied.
 uint64_t need_mask(const PGate& g) {
@@ -332,6 +360,7 @@ struct PassEmitter {
 
   bool allow_absorb = true;
   bool allow_fused_bits = false;  // OP_UALL / OP_RYALL (single-state kernels with r <= 4 only)
+  bool allow_factored = false;    // OP_UTAB (single-state float kernels with r <= 4 only)
 
   PassEmitter(Plan& p, int n_, int m_, int r_, uint64_t Lmask) : plan(p), n(n_), m(m_), r(r_), lidx(n_, -1) {
     for (int q = 0; q < n; ++q)
@@ -645,6 +674,64 @@ struct PassEmitter {
       const auto& its = sb[si].items;
       for (size_t ii = 0; ii < its.size(); ++ii) {
         const PGate* g = its[ii];
+        // a run of uncontrolled rotations on distinct register bits that ends the
+        // stage's ops (they commute): one factored op, U_j = X^f P_j T_j E_j with
+        // diagonal P_j, E_j, a real T_j of two multiply-adds per amplitude and a
+        // swap X^f left to the stage's exit addressing; the P's (and E's) form one
+        // table over the register index.  Taken when cheaper than the rotations one
+        // by one (instructions per amplitude pair: 16 per general rotation, 8 per
+        // RY; factored 4 per register bit, 8 per table).
+        if (allow_factored && r <= 4 && (g->kind == PG_U || g->kind == PG_RY) && g->q2 < 0) {
+          std::vector<int> member(r, -1);
+          size_t jj = ii;
+          int cost = 0;
+          bool pre = false;
+          for (; jj < its.size(); ++jj) {
+            const PGate* h = its[jj];
+            if ((h->kind != PG_U && h->kind != PG_RY) || h->q2 >= 0) break;
+            const BitRef b = bitref(h->q, rb);
+            if (b.kind != BK_REG || member[b.idx] >= 0) break;
+            member[b.idx] = (int)jj;
+            cost += h->kind == PG_U ? 16 : 8;
+            pre = pre || !h->real_pre;
+          }
+          if (jj == its.size() && cost > 4 * r + 8 + (pre ? 8 : 0)) {
+            DevOp head;
+            std::memset(&head, 0, sizeof(head));
+            head.type = OP_UTAB;
+            head.j = pre ? 1 : 0;
+            head.slot = (int)plan.slots.size();
+            PGate tab;
+            tab.kind = PG_TAB;
+            tab.q = r;
+            for (int j = 0; j < r; ++j) {
+              tab.srcs.push_back(member[j] >= 0 ? its[member[j]]->slot : -1);
+              if (member[j] >= 0) head.fr |= 1u << j;
+            }
+            for (int chunk = 0; chunk < kTabSlots; ++chunk) {
+              tab.gen = chunk;
+              tab.slot = (int)plan.slots.size();
+              plan.slots.push_back(tab);
+            }
+            if (pre) {
+              DevOp d = head;
+              d.type = OP_DTAB;
+              plan.ops.push_back(d);
+            }
+            const int at = (int)plan.ops.size() - st.op_begin;
+            plan.ops.push_back(head);
+            for (int j = 0; j < r; ++j)
+              if (member[j] >= 0)
+                for (int src : its[member[j]]->srcs) {
+                  plan.order.push_back(pass_no);
+                  plan.order.push_back(si);
+                  plan.order.push_back(at);
+                  plan.order.push_back(src);
+                }
+            ii = jj - 1;
+            continue;
+          }
+        }
         // r uncontrolled rotations of one kind on all r register bits (distinct qubits,
         // so they commute): one op applying them bit by bit
         if (allow_fused_bits && r <= 4 && (g->kind == PG_U || g->kind == PG_RY) && g->q2 < 0 &&
@@ -841,6 +928,7 @@ int plan_forward(int n, const std::vector<PGate>& gates, const std::vector<PGate
     PassEmitter em(plan, n, m, r, Ls[p]);
     em.allow_absorb = o.absorb;
     em.allow_fused_bits = true;
+    em.allow_factored = o.factored && !plan.slots.empty();
     std::vector<const PGate*> mod;
     for (int idx : lists[p]) mod.push_back(&gates[idx]);
     em.emit(mod, last ? fin : std::vector<const PGate*>{}, flags, c_low, p);
@@ -1015,6 +1103,92 @@ M2 gate_m2(const Gate& g, const double* th) {
   return u;
 }
 
+// Matrix of a coefficient slot: product of its source gates, adjoint if flagged.
+M2 slot_m2(const CircuitDesc& c, const PGate& p, const double* th) {
+  M2 M;
+  M.a[0][0] = 1; M.a[0][1] = 0; M.a[1][0] = 0; M.a[1][1] = 1;
+  for (int g : p.srcs) M = mul(gate_m2(c.gates[g], th), M);
+  if (p.inverse) {
+    M2 h;
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) h.a[i][j] = std::conj(M.a[j][i]);
+    M = h;
+  }
+  return M;
+}
+
+// Factored form of a unitary 2x2: U = diag(p0, p1) K diag(1, e) with
+// K = [[1, -k], [k, 1]] when |u00| >= |u01| (cot = false), else [[k, -1], [1, k]];
+// |k| <= 1 either way.  Unitarity (orthogonal rows) makes the remaining entries
+// agree: tan form k e = -u01/u00, p0 = u00, p1 = u11/e; cot form k e = u11/u10,
+// p1 = u10, p0 = -u01/e.  The sign of k is chosen so that Re e >= 0, which makes
+// e = 1 (snapped) whenever k e is real, as for any RZ-after-RY product.  The cot
+// form is rewritten for the kernel as diag(p0, p1) [[k, -1], [1, k]] =
+// X diag(p1, -p0) [[1, k], [-k, 1]].
+struct KForm {
+  bool cot = false;
+  double k = 0;
+  cd p0 = 1, p1 = 1, e = 1;
+};
+
+KForm kform(const M2& M) {
+  KForm f;
+  const cd m00 = M.a[0][0], m01 = M.a[0][1], m10 = M.a[1][0], m11 = M.a[1][1];
+  f.cot = std::abs(m01) > std::abs(m00);
+  const cd z = f.cot ? m11 / m10 : -m01 / m00;
+  const double az = std::abs(z);
+  if (az > 0) {
+    f.k = z.real() >= 0 ? az : -az;
+    f.e = z / f.k;
+    if (std::abs(f.e - 1.0) <= 1e-13) f.e = 1;
+  }
+  if (f.cot) {
+    f.p1 = m10;
+    f.p0 = -m01 / f.e;
+  } else {
+    f.p0 = m00;
+    f.p1 = m11 / f.e;
+  }
+  return f;
+}
+
+// The whole coefficient block of a PG_TAB group (layout in planner.h).
+void tab_block(const CircuitDesc& c, const std::vector<PGate>& slots, const PGate& p, const double* th,
+               double* blk) {
+  for (int k = 0; k < 8 * kTabSlots; ++k) blk[k] = 0;
+  KForm f[4];
+  uint32_t form = 0, pre = 0;
+  const int r = (int)p.srcs.size();
+  for (int j = 0; j < r && j < 4; ++j) {
+    if (p.srcs[j] < 0) continue;
+    f[j] = kform(slot_m2(c, slots[p.srcs[j]], th));
+    if (f[j].cot) {  // X diag(p1, -p0) T(-k)
+      form |= 1u << j;
+      const cd p0 = f[j].p0;
+      f[j].p0 = f[j].p1;
+      f[j].p1 = -p0;
+      f[j].k = -f[j].k;
+    }
+    if (f[j].e != 1.0) pre = 1;
+    blk[64 + j] = f[j].k;
+  }
+  for (int i = 0; i < 16; ++i) {
+    cd post = 1, pe = 1;
+    for (int j = 0; j < r && j < 4; ++j) {
+      if (p.srcs[j] < 0) continue;
+      const bool one = (i >> j) & 1;
+      post *= one ? f[j].p1 : f[j].p0;
+      if (one) pe *= f[j].e;
+    }
+    blk[2 * i] = post.real();
+    blk[2 * i + 1] = post.imag();
+    blk[32 + 2 * i] = pe.real();
+    blk[32 + 2 * i + 1] = pe.imag();
+  }
+  blk[68] = form;
+  blk[69] = pre;
+}
+
 }  // namespace
 
 template <class T>
@@ -1025,17 +1199,24 @@ void build_coefficients(const CircuitDesc& c, const std::vector<PGate>& slots, c
     T* row = out + (size_t)b * row_stride;
     for (size_t s = 0; s < slots.size(); ++s) {
       const PGate& p = slots[s];
-      M2 M;
-      M.a[0][0] = 1; M.a[0][1] = 0; M.a[1][0] = 0; M.a[1][1] = 1;
-      for (int g : p.srcs) M = mul(gate_m2(c.gates[g], th), M);
-      if (p.inverse) {
-        M2 h;
-        for (int i = 0; i < 2; ++i)
-          for (int j = 0; j < 2; ++j) h.a[i][j] = std::conj(M.a[j][i]);
-        M = h;
-      }
       T* o = row + s * 8;
       for (int k = 0; k < 8; ++k) o[k] = 0;
+      if (p.kind == PG_TAB) {
+        double blk[8 * kTabSlots];
+        tab_block(c, slots, p, th, blk);
+        const int c0 = p.gen * 8;
+        for (int k = 0; k < 8; ++k) {
+          const int e = c0 + k;
+          if (e == 68 || e == 69) {  // raw 32-bit words in the scalar's low bytes
+            const uint32_t w = (uint32_t)blk[e];
+            std::memcpy(&o[k], &w, sizeof(w));
+          } else {
+            o[k] = (T)blk[e];
+          }
+        }
+        continue;
+      }
+      const M2 M = slot_m2(c, p, th);
       if (p.kind == PG_RY) {
         o[0] = (T)M.a[0][0].real();
         o[1] = (T)M.a[1][0].real();

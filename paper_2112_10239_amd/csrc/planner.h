@@ -31,7 +31,25 @@ struct CircuitDesc {
 
 // Planner-level operation ("pgate"): a fused gate, a gradient probe, or a
 // measurement / H-apply term.
-enum PGKind { PG_U, PG_RY, PG_X, PG_PHASE, PG_CZ, PG_GRAD, PG_MEAS_Z, PG_MEAS_F, PG_H_Z, PG_H_F };
+enum PGKind { PG_U, PG_RY, PG_X, PG_PHASE, PG_CZ, PG_GRAD, PG_MEAS_Z, PG_MEAS_F, PG_H_Z, PG_H_F, PG_TAB };
+
+// PG_TAB coefficient slots: kTabSlots consecutive slots hold the block of one
+// OP_UTAB op: uncontrolled rotations on the register bits of a stage (identity
+// on bits without one), each written as U_j = X^{f_j} P_j T_j E_j with
+// T_j = [[1, -k_j], [k_j, 1]], |k_j| <= 1, diagonal P_j and E_j = diag(1, e_j),
+// and X^{f_j} a swap of the bit's two values (needed when |u01| > |u00|).  The
+// swaps of all bits commute past everything else and leave the registers
+// permuted: register i holds the amplitude of register index i ^ F, which the
+// stage's exit (LDS write or store) absorbs into its addresses.  A PG_TAB
+// slot's srcs list, per register bit, the coefficient slot of the rotation on
+// it (-1: none); its gen field is the chunk it holds.
+// Block layout in scalars (T = float or double):
+//   [0, 32)  post table: 16 complex products of the P_j over the register bits
+//   [32, 64) pre table: 16 complex products of the E_j
+//   [64, 68) k per register bit
+//   [68]     F (swap mask) as raw 32-bit bits
+//   [69]     nonzero raw bits when the pre table is not all ones
+constexpr int kTabSlots = 9;
 
 struct PGate {
   int kind = PG_U;
@@ -40,6 +58,7 @@ struct PGate {
   int slot = -1; // coefficient slot, or gradient slot for PG_GRAD
   int gen = 0;   // PG_GRAD generator: 'X', 'Y' or 'Z'
   bool inverse = false;   // coefficient = adjoint of the product
+  bool real_pre = false;  // product is RY's followed by RZ's: U = diag(..) K with real K
   std::vector<int> srcs;  // source gates, in application order
   uint64_t fmask = 0, zmask = 0;  // terms: flip (X|Y) and sign (Y|Z) masks, physical
   int ph = 0;                     // terms: i^ph
@@ -71,6 +90,8 @@ struct PlanOptions {
   bool fuse = true;     // fuse runs of single-qubit gates on one qubit
   int max_grad = kMaxGradPerPass;  // gradient probes per pass
   bool absorb = true;   // allow CNOT runs as stage exit permutations
+  bool factored = false;  // runs of uncontrolled rotations on register bits as one OP_UTAB
+                          // (single-state float kernels with r <= 4; needs plan.slots)
 };
 
 // Validation; returns "" when fine.

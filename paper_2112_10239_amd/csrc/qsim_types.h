@@ -36,6 +36,10 @@ enum OpType : uint8_t {
                   // acc += sum_t c_t (-1)^{thread/tile parity} W[rz_t], W = Walsh transform of |a_i|^2
   OP_UALL = 14,   // one uncontrolled op per register bit: the next r ops are OP_U (or, with j = 1 in the
   OP_RYALL = 15,  // header, OP_RY) records for register bits 0..r-1 in order (gates on distinct qubits)
+  OP_UTAB = 16,   // uncontrolled rotations on every register bit, factored (see the PG_TAB block layout
+                  // in planner.h); slot = first of the block's coefficient slots; no records follow;
+                  // always the last op of its stage (its register swaps go to the stage's exit)
+  OP_DTAB = 17,   // the pre table of the OP_UTAB that follows (same slot)
 };
 
 // Bit reference kinds for controls, diagonal bits and z-masks.

@@ -131,6 +131,66 @@ def test_amplitudes(Q, eng, oracle_mod, n):
     np.testing.assert_allclose(psi, psi_o, atol=1e-12)
 
 
+def _rotation_mix(n, depth, seed):
+    """Brickwork of RY RZ (+ RX on some layers, a fixed U1 on others) and CNOTs with
+    angles that include exact multiples of pi/2: every form of the factored rotation
+    (tan form, swapped form, k = 0, pre-diagonal) appears."""
+    rng = np.random.default_rng([24, seed])
+    b = W.GateListBuilder(n)
+    special = [0.0, math.pi, -math.pi, math.pi / 2, 3 * math.pi, 2.0, -2.0]
+    h = np.array([[1, 1], [1, -1]]) / math.sqrt(2)
+    for layer in range(depth):
+        for q in range(n):
+            if layer % 3 == 2 and q % 2 == 0:
+                b.rot(W.RX, q, fixed_angle=float(special[(q + layer) % len(special)]))
+            else:
+                b.rot(W.RY, q, fixed_angle=float(special[(q + layer) % len(special)]) if q % 3 == 0 else None)
+            b.rot(W.RZ, q)
+            if layer == 1 and q % 4 == 1:
+                b.custom(q, h if q % 8 == 1 else np.array([[0, 1], [1, 0]]))
+        for q in range(layer % 2, n - 1, 2):
+            b.two(W.CNOT, q, q + 1)
+    c = b.build()
+    th = rng.uniform(-math.pi, math.pi, c.n_params)
+    th[::5] = math.pi
+    return c, th
+
+
+@pytest.mark.parametrize("n", [2, 5, 13, 14, 17])
+def test_rotation_forms_amplitudes_c64(Q, eng, oracle_mod, n):
+    """complex64 amplitudes element by element against the oracle's state vector,
+    across tiles and passes (stores and exchanges of swapped registers)."""
+    c, th = _rotation_mix(n, 6, n)
+    say("rotation forms amplitudes", n, "gates", c.n_gates)
+    psi_o = oracle_mod.statevector(c, th)
+    st = eng.create_state(n, batch=1, dtype=Q.C64)
+    st.apply_layer(c.gates, th, c.n_params, mats=c.mats)
+    psi = st.to_host()[0]
+    st.destroy()
+    np.testing.assert_allclose(psi, psi_o, atol=2e-6)
+
+
+@pytest.mark.parametrize("n", [1, 3, 14])
+def test_rotation_forms_measured_c64(Q, eng, oracle_mod, n):
+    """measurement terms on the register bits of a stage ending in rotations"""
+    c, th = _rotation_mix(n, 3, 100 + n)
+    terms = [(0.7, [(q, "Z")]) for q in range(n)] + [(0.3, [(q, "X")]) for q in range(n)]
+    terms += [(0.2, [(q, "Y"), ((q + 1) % n, "Z")]) for q in range(n - 1)]
+    H = W.Hamiltonian.from_terms(terms)
+    say("rotation forms measured", n)
+    want = oracle_mod.expect(c, H, th)
+    got = eng.expect_circuit(c, H, th, mode=Q.MODE_DENSE, dtype=0)
+    assert abs(got - want) <= tol(H, 0), (got, want)
+
+
+def test_nonunitary_u1_rejected(Q, eng):
+    b = W.GateListBuilder(2)
+    b.custom(0, np.array([[1.0, 0.0], [0.0, 0.5]]))
+    with pytest.raises(Q.QsimError) as ei:
+        eng.expect_circuit(b.build(), W.tfim(2, 1.0), [], mode=Q.MODE_DENSE)
+    assert ei.value.code == -1
+
+
 def test_batched_rows_and_layers(Q, eng, oracle_mod):
     n, depth, B = 12, 4, 5
     c = W.brickwork_ry_rz_cnot(n, depth)
