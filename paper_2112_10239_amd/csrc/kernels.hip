@@ -18,6 +18,8 @@
 // registers, fp64 across threads, one fp64 partial per tile, then a
 // fixed-order cross-tile reduction, so results do not depend on scheduling.
 #include <cstdlib>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.h"
@@ -57,6 +59,35 @@ __device__ __forceinline__ void st_amp(cpx<T>* p, const cpx<T>& a) {
   v.x = a.x;
   v.y = a.y;
   *reinterpret_cast<typename Vec2<T>::type*>(p) = v;
+}
+
+// LDS amplitude slots addressed by their full 32-bit LDS byte address.  The
+// pass kernels keep the tile at the start of dynamic LDS and have no static
+// LDS (checked at launch), so the tile starts at LDS address 0 and an offset
+// below the tile size can be XORed into a slot address.
+template <class T>
+using lds_vec2 = __attribute__((address_space(3))) typename Vec2<T>::type;
+
+template <class T>
+__device__ __forceinline__ cpx<T> ld_lds(uint32_t addr) {
+  const typename Vec2<T>::type v = *reinterpret_cast<const lds_vec2<T>*>((size_t)addr);
+  cpx<T> r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ void st_lds(uint32_t addr, const cpx<T>& a) {
+  typename Vec2<T>::type v;
+  v.x = a.x;
+  v.y = a.y;
+  *reinterpret_cast<lds_vec2<T>*>((size_t)addr) = v;
+}
+
+template <class T>
+__device__ __forceinline__ uint32_t lds_addr(cpx<T>* p) {
+  return (uint32_t)(size_t)(__attribute__((address_space(3))) char*)(reinterpret_cast<char*>(p));
 }
 
 // Pass, stage and op descriptors and gate coefficients are read-only while a
@@ -413,12 +444,16 @@ __device__ __forceinline__ uint64_t next_base(uint64_t base, uint64_t M, uint64_
 // Thread-local part of stage S's local index (thread bits deposited into tb).
 template <int R>
 __device__ __forceinline__ uint32_t thread_local_index(kptr<StageDesc> S, int m, int tid) {
-  const KWords<kMaxLocal / 4> tb(S->tb);
-  uint32_t tl = 0;
+  // tid's bits deposited into the thread bits (ascending) = a zero inserted at
+  // each register bit (ascending); bits past the tile are dropped
+  const KWords<2> rs(S->rbs);
+  uint32_t tl = (uint32_t)tid;
 #pragma unroll
-  for (int k = 0; k < kMaxLocal - R; ++k)
-    if (k < m - R) tl |= ((uint32_t)(tid >> k) & 1u) << tb.u8(k);
-  return tl;
+  for (int j = 0; j < R; ++j) {
+    const uint32_t lo = (1u << rs.u8(j)) - 1u;
+    tl = (tl & lo) | ((tl << 1) & ~(2u * lo + 1u));
+  }
+  return tl & ((1u << m) - 1u);
 }
 
 // Global offsets (physical index bits) of stage S: per-thread part and per-register-bit parts.
@@ -510,6 +545,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
   const bool active = tid < (1 << (m - R));
   const int lane = tid & 63, wave = tid >> 6, nwaves = (nthr + 63) >> 6;
   const uint32_t tsize = 1u << m;
+  const uint32_t lds0 = lds_addr(lds);
   cpx<T>* a = t.a;
   cpx<T>* b = t.b;
   const int gcount = DUAL ? P->grad_count : 0;
@@ -541,25 +577,31 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     for (int j = 0; j < R; ++j) rl[j] = 1u << rbw.u8(j);
     // The swizzle is linear over XOR and the thread and register bits are
     // disjoint, so an LDS slot is swz(tl) ^ swz(register offset): one lane
-    // value and one uniform value per register (byte offsets here).
-    auto roff = [&](int i) __attribute__((always_inline)) {
+    // value and one uniform value per register, the latter the XOR of the
+    // swizzled byte offsets of the register's bits.
+    uint32_t sb[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) sb[j] = swz(rl[j]) * (uint32_t)sizeof(cpx<T>);
+    auto soff = [&](int i) __attribute__((always_inline)) {
       uint32_t o = 0;
 #pragma unroll
       for (int j = 0; j < R; ++j)
-        if ((i >> j) & 1) o |= rl[j];
+        if ((i >> j) & 1) o ^= sb[j];
       return o;
     };
-    const uint32_t tl_b = swz(tl) * (uint32_t)sizeof(cpx<T>);
-    auto slot = [&](uint32_t lane_b, uint32_t uni) __attribute__((always_inline)) {
-      return reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(lds) + (lane_b ^ (swz(uni) * (uint32_t)sizeof(cpx<T>))));
-    };
+    // full LDS address of the thread's slot (tile at address 0), opaque to the
+    // optimiser so each access is one XOR with a uniform offset
+    uint32_t tl_b = lds0 + swz(tl) * (uint32_t)sizeof(cpx<T>);
+    asm volatile("" : "+v"(tl_b));
+
+    const uint32_t bofs = tsize * (uint32_t)sizeof(cpx<T>);  // second state's tile (dual kernels)
     if (s != s0) {
       // lanes past the tile read valid slots (their local index keeps only tile bits) and are zeroed
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
-        cpx<T>* l = slot(tl_b, roff(i));
-        a[i] = ld_amp(l);
-        if constexpr (DUAL) b[i] = ld_amp(l + tsize);
+        const uint32_t l = tl_b ^ soff(i);
+        a[i] = ld_lds<T>(l);
+        if constexpr (DUAL) b[i] = ld_lds<T>(l + bofs);
       }
       if (!active) {
 #pragma unroll
@@ -786,35 +828,49 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         if (kh(&S->has_perm)) {
           // write every amplitude to its image under the stage's exit permutation
           const KWords<kMaxLocal / 2> tcol(S->tcol);
-          uint32_t w = 0;
+          // lane bits per lane; wave bits are uniform (scalar work)
+          const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
+          uint32_t w = 0, wu = 0;
 #pragma unroll
           for (int k = 0; k < kMaxLocal - R; ++k)
-            if (k < m - R) w ^= ((uint32_t)(tid >> k) & 1u) ? tcol.u16(k) : 0u;
+            if (k < m - R) {
+              if (k < 6) w ^= ((uint32_t)(tid >> k) & 1u) ? tcol.u16(k) : 0u;
+              else wu ^= ((wv >> (k - 6)) & 1u) ? tcol.u16(k) : 0u;
+            }
           const int n_aff = (int)kh(&S->n_aff);
           uint32_t wa = 0;  // affine part: tile bits (uniform)
           for (int j = 0; j < n_aff; ++j)
             if ((base >> kb(&S->aff_pos[j])) & 1) wa ^= kh(&S->aff_mask[j]);
           // register i holds index i ^ pend; preg is linear, so its image is preg(i) ^ preg(pend)
           const uint32_t wp = pend ? kh(&S->preg[pend]) : 0u;
-          const uint32_t w_b = swz(w ^ wa ^ wp) * (uint32_t)sizeof(cpx<T>);
+          uint32_t w_b = lds0 + swz(w ^ wu ^ wa ^ wp) * (uint32_t)sizeof(cpx<T>);
+          asm volatile("" : "+v"(w_b));
           const KWords<(1 << R) / 2> preg(S->preg);
+          uint32_t pb[R];  // swizzled byte offsets of the images of the register bits
+#pragma unroll
+          for (int j = 0; j < R; ++j) pb[j] = swz(preg.u16(1 << j)) * (uint32_t)sizeof(cpx<T>);
 #pragma unroll
           for (int i = 0; i < NR; ++i) {
-            cpx<T>* l = slot(w_b, preg.u16(i));
-            st_amp(l, a[i]);
-            if constexpr (DUAL) st_amp(l + tsize, b[i]);
+            uint32_t po = 0;
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+              if ((i >> j) & 1) po ^= pb[j];
+            const uint32_t l = w_b ^ po;
+            st_lds<T>(l, a[i]);
+            if constexpr (DUAL) st_lds<T>(l + bofs, b[i]);
           }
         } else {
-          uint32_t rp = 0;  // roff(pend)
+          uint32_t rp = 0;  // offset of register index pend
 #pragma unroll
           for (int j = 0; j < R; ++j)
-            if ((pend >> j) & 1u) rp |= rl[j];
-          const uint32_t wl_b = tl_b ^ (swz(rp) * (uint32_t)sizeof(cpx<T>));
+            if ((pend >> j) & 1u) rp ^= sb[j];
+          uint32_t wl_b = tl_b ^ rp;
+          asm volatile("" : "+v"(wl_b));
 #pragma unroll
           for (int i = 0; i < NR; ++i) {
-            cpx<T>* l = slot(wl_b, roff(i));
-            st_amp(l, a[i]);
-            if constexpr (DUAL) st_amp(l + tsize, b[i]);
+            const uint32_t l = wl_b ^ soff(i);
+            st_lds<T>(l, a[i]);
+            if constexpr (DUAL) st_lds<T>(l + bofs, b[i]);
           }
         }
       }
@@ -1099,11 +1155,27 @@ __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, fl
   for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
+// Kernels running tiles: the dynamic LDS size allowance, and a check that the
+// kernel has no static LDS, so the tile buffer (the start of dynamic LDS) sits
+// at LDS address 0 as the XOR slot addressing assumes.
 template <class K>
 hipError_t allow_lds(K kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::map<const void*, hipError_t> checked;
+  const void* f = reinterpret_cast<const void*>(kernel);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = checked.find(f);
+    if (it == checked.end()) {
+      hipFuncAttributes fa;
+      hipError_t e = hipFuncGetAttributes(&fa, f);
+      if (e == hipSuccess && fa.sharedSizeBytes != 0) e = hipErrorInvalidDeviceFunction;
+      it = checked.emplace(f, e).first;
+    }
+    if (it->second != hipSuccess) return it->second;
+  }
   if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 int device_cus() {

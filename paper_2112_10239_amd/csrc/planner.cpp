@@ -663,6 +663,11 @@ struct PassEmitter {
         st.rpos[j] = (uint8_t)L[rb[j]];
       }
       {
+        std::vector<int> srt(rb.begin(), rb.begin() + r);
+        std::sort(srt.begin(), srt.end());
+        for (int j = 0; j < r; ++j) st.rbs[j] = (uint8_t)srt[j];
+      }
+      {
         int t = 0;
         for (int k = 0; k < m; ++k)
           if (!rb_has(rb, k)) {

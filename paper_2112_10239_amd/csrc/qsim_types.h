@@ -83,8 +83,9 @@ struct StageDesc {
   uint16_t aff_mask[kMaxAffine];    // xor into the image when that bit is 1
   uint8_t tpos[kMaxLocal];  // physical bit of thread bit k (the pass's lpos[tb[k]])
   uint8_t rpos[8];          // physical bit of register bit j (lpos[rb[j]])
+  uint8_t rbs[8];           // register bits as local indices, ascending (r used)
 };
-static_assert(sizeof(StageDesc) == 180, "StageDesc layout");
+static_assert(sizeof(StageDesc) == 188, "StageDesc layout");
 
 enum PassFlags : int32_t {
   PF_INIT = 1,      // first stage generates |0...0> instead of loading a
