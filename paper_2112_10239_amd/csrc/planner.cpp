@@ -21,6 +21,7 @@
 #include <complex>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 namespace qsim {
 
@@ -302,6 +303,8 @@ struct StageBuild {
 // Relative costs used to choose between stage layouts (one LDS exchange of the
 // tile versus register ops), in units of one general 2x2 op.
 constexpr double kCostExchange = 2.0;
+constexpr double kCostExchangeFactored = 1.35;
+constexpr double kCostFactored = 1.2;
 double op_cost(const PGate& g) {
   switch (g.kind) {
     case PG_U: return 1.0;
@@ -361,6 +364,7 @@ struct PassEmitter {
   bool allow_absorb = true;
   bool allow_fused_bits = false;  // OP_UALL / OP_RYALL (single-state kernels with r <= 4 only)
   bool allow_factored = false;    // OP_UTAB (single-state float kernels with r <= 4 only)
+  int io_lo = -1;                 // see PlanOptions::io_lo
 
   PassEmitter(Plan& p, int n_, int m_, int r_, uint64_t Lmask) : plan(p), n(n_), m(m_), r(r_), lidx(n_, -1) {
     for (int q = 0; q < n; ++q)
@@ -463,8 +467,9 @@ struct PassEmitter {
   // qubits move to the next stage.
   std::vector<StageBuild> build_stages(const std::vector<const PGate*>& mod, const std::vector<const PGate*>& ro,
                                        bool loads, bool stores, int c_low, bool absorb, int& store_rel) const {
-    const int lo_load = loads ? c_low : 0;
-    const int lo_store = stores ? c_low : 0;
+    const int lo_io = io_lo >= 0 ? std::min(io_lo, c_low) : c_low;
+    const int lo_load = loads ? lo_io : 0;
+    const int lo_store = stores ? lo_io : 0;
     std::vector<StageBuild> sb;
     std::vector<const PGate*> pending = mod;
     bool first = true;
@@ -554,10 +559,35 @@ struct PassEmitter {
     }
   }
 
-  static double stages_cost(const std::vector<StageBuild>& sb) {
-    double c = kCostExchange * (double)(sb.size() - 1);
-    for (const StageBuild& s : sb)
-      for (const PGate* g : s.items) c += op_cost(*g);
+  double stages_cost(const std::vector<StageBuild>& sb) const {
+    if (!allow_factored || r > 4) {
+      double c = kCostExchange * (double)(sb.size() - 1);
+      for (const StageBuild& s : sb)
+        for (const PGate* g : s.items) c += op_cost(*g);
+      return c;
+    }
+    // With factored rotations (in units of one general rotation applied alone,
+    // from timings of the single-state pass kernel): an exchange costs about
+    // 1.35, the trailing run of uncontrolled rotations on distinct register bits
+    // about 1.2 when it becomes one factored op.
+    double c = kCostExchangeFactored * (double)(sb.size() - 1);
+    for (const StageBuild& s : sb) {
+      size_t tail = s.items.size();  // start of the longest suffix of such rotations
+      std::vector<char> used(r, 0);
+      int direct = 0;  // instructions per pair, one by one (16 per general rotation, 8 per RY)
+      while (tail > 0) {
+        const PGate* h = s.items[tail - 1];
+        if ((h->kind != PG_U && h->kind != PG_RY) || h->q2 >= 0) break;
+        const BitRef b = bitref(h->q, s.rb);
+        if (b.kind != BK_REG || used[b.idx]) break;
+        used[b.idx] = 1;
+        direct += h->kind == PG_U ? 16 : 8;
+        --tail;
+      }
+      const bool fac = tail < s.items.size() && direct > 4 * r + 8;
+      for (size_t i = 0; i < (fac ? tail : s.items.size()); ++i) c += op_cost(*s.items[i]);
+      if (fac) c += kCostFactored;
+    }
     return c;
   }
 
@@ -934,6 +964,7 @@ int plan_forward(int n, const std::vector<PGate>& gates, const std::vector<PGate
     em.allow_absorb = o.absorb;
     em.allow_fused_bits = true;
     em.allow_factored = o.factored && !plan.slots.empty();
+    em.io_lo = o.io_lo;
     std::vector<const PGate*> mod;
     for (int idx : lists[p]) mod.push_back(&gates[idx]);
     em.emit(mod, last ? fin : std::vector<const PGate*>{}, flags, c_low, p);
@@ -1157,16 +1188,16 @@ KForm kform(const M2& M) {
   return f;
 }
 
-// The whole coefficient block of a PG_TAB group (layout in planner.h).
-void tab_block(const CircuitDesc& c, const std::vector<PGate>& slots, const PGate& p, const double* th,
-               double* blk) {
+// The whole coefficient block of a PG_TAB group (layout in planner.h), from
+// the matrices of the member slots.
+void tab_block(const std::vector<M2>& ms, const PGate& p, double* blk) {
   for (int k = 0; k < 8 * kTabSlots; ++k) blk[k] = 0;
   KForm f[4];
   uint32_t form = 0, pre = 0;
   const int r = (int)p.srcs.size();
   for (int j = 0; j < r && j < 4; ++j) {
     if (p.srcs[j] < 0) continue;
-    f[j] = kform(slot_m2(c, slots[p.srcs[j]], th));
+    f[j] = kform(ms[p.srcs[j]]);
     if (f[j].cot) {  // X diag(p1, -p0) T(-k)
       form |= 1u << j;
       const cd p0 = f[j].p0;
@@ -1197,31 +1228,18 @@ void tab_block(const CircuitDesc& c, const std::vector<PGate>& slots, const PGat
 }  // namespace
 
 template <class T>
-void build_coefficients(const CircuitDesc& c, const std::vector<PGate>& slots, const double* params, int batch,
-                        int64_t row_stride, T* out) {
-  for (int b = 0; b < batch; ++b) {
+static void build_rows(const CircuitDesc& c, const std::vector<PGate>& slots, const double* params, int b0, int b1,
+                       int64_t row_stride, T* out) {
+  std::vector<M2> ms(slots.size());
+  for (int b = b0; b < b1; ++b) {
     const double* th = params ? params + (size_t)b * c.n_params : nullptr;
     T* row = out + (size_t)b * row_stride;
     for (size_t s = 0; s < slots.size(); ++s) {
       const PGate& p = slots[s];
+      if (p.kind == PG_TAB) continue;
       T* o = row + s * 8;
       for (int k = 0; k < 8; ++k) o[k] = 0;
-      if (p.kind == PG_TAB) {
-        double blk[8 * kTabSlots];
-        tab_block(c, slots, p, th, blk);
-        const int c0 = p.gen * 8;
-        for (int k = 0; k < 8; ++k) {
-          const int e = c0 + k;
-          if (e == 68 || e == 69) {  // raw 32-bit words in the scalar's low bytes
-            const uint32_t w = (uint32_t)blk[e];
-            std::memcpy(&o[k], &w, sizeof(w));
-          } else {
-            o[k] = (T)blk[e];
-          }
-        }
-        continue;
-      }
-      const M2 M = slot_m2(c, p, th);
+      const M2 M = ms[s] = slot_m2(c, p, th);
       if (p.kind == PG_RY) {
         o[0] = (T)M.a[0][0].real();
         o[1] = (T)M.a[1][0].real();
@@ -1235,7 +1253,43 @@ void build_coefficients(const CircuitDesc& c, const std::vector<PGate>& slots, c
         o[6] = (T)M.a[1][1].real(); o[7] = (T)M.a[1][1].imag();
       }
     }
+    // factored groups: one block over kTabSlots consecutive slots, from the member matrices
+    for (size_t s = 0; s < slots.size(); ++s) {
+      const PGate& p = slots[s];
+      if (p.kind != PG_TAB || p.gen != 0) continue;
+      double blk[8 * kTabSlots];
+      tab_block(ms, p, blk);
+      T* o = row + s * 8;
+      for (int e = 0; e < 8 * kTabSlots; ++e) {
+        if (e == 68 || e == 69) {  // raw 32-bit words in the scalar's low bytes
+          const uint32_t w = (uint32_t)blk[e];
+          o[e] = 0;
+          std::memcpy(&o[e], &w, sizeof(w));
+        } else {
+          o[e] = (T)blk[e];
+        }
+      }
+    }
   }
+}
+
+template <class T>
+void build_coefficients(const CircuitDesc& c, const std::vector<PGate>& slots, const double* params, int batch,
+                        int64_t row_stride, T* out) {
+  // rows are independent: large batches are split over a few host threads
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::min({hw, 16, batch / 16});
+  if (nt <= 1) {
+    build_rows<T>(c, slots, params, 0, batch, row_stride, out);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int per = (batch + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int b0 = t * per, b1 = std::min(batch, b0 + per);
+    if (b0 < b1) th.emplace_back(build_rows<T>, std::cref(c), std::cref(slots), params, b0, b1, row_stride, out);
+  }
+  for (auto& x : th) x.join();
 }
 
 template void build_coefficients<float>(const CircuitDesc&, const std::vector<PGate>&, const double*, int, int64_t,

@@ -90,6 +90,8 @@ struct PlanOptions {
   bool fuse = true;     // fuse runs of single-qubit gates on one qubit
   int max_grad = kMaxGradPerPass;  // gradient probes per pass
   bool absorb = true;   // allow CNOT runs as stage exit permutations
+  int io_lo = -1;       // lowest local bit a register bit may use in a stage that loads or
+                        // stores (HBM coalescing); -1: c_low
   bool factored = false;  // runs of uncontrolled rotations on register bits as one OP_UTAB
                           // (single-state float kernels with r <= 4; needs plan.slots)
 };
