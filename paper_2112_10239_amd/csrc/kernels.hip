@@ -1081,8 +1081,19 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const double* __restrict__ 
                                                      double* out) {
   __shared__ double sh[256];
   const int64_t row = blockIdx.x;
+  const double* pr = part + row * per_row;
   double s = 0.0;
-  for (int64_t k = threadIdx.x; k < per_row; k += 256) s += part[row * per_row + k];
+  int64_t k = threadIdx.x;
+  // each thread adds its values in index order; loads are issued 16 at a time
+  // so their latencies overlap (the sum order is unchanged)
+  for (; k + 15 * 256 < per_row; k += 16 * 256) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = pr[k + u * 256];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += v[u];
+  }
+  for (; k < per_row; k += 256) s += pr[k];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {

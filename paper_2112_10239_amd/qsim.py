@@ -135,27 +135,38 @@ def strerror(code: int) -> str:
 # marshalling of circuits and Hamiltonians
 # ---------------------------------------------------------------------------
 
+_GATE_NP = np.dtype({"names": ["kind", "q0", "q1", "param", "angle", "mat"],
+                     "formats": [np.uint8, np.int32, np.int32, np.int32, np.float64, np.uint64],
+                     "offsets": [Gate.kind.offset, Gate.q0.offset, Gate.q1.offset, Gate.param.offset,
+                                 Gate.angle.offset, Gate.mat.offset],
+                     "itemsize": ctypes.sizeof(Gate)})
+
+
 class CCircuit:
     """A ctypes view of a gate list; keeps the backing arrays alive."""
 
     def __init__(self, n: int, gates: np.ndarray, n_params: int, mats: dict | None = None):
         self._mats = {}
         g = gates
-        arr = (Gate * max(1, len(g)))()
-        for i in range(len(g)):
-            e = arr[i]
-            e.kind = int(g["kind"][i])
-            e.q0 = int(g["q0"][i])
-            e.q1 = int(g["q1"][i])
-            e.param = int(g["param"][i])
-            e.angle = float(g["angle"][i])
-            if mats and i in mats:
-                m = np.asarray(mats[i], dtype=np.complex128).reshape(2, 2)
-                buf = np.empty(8, dtype=np.float64)
-                buf[0::2] = m.real.ravel()
-                buf[1::2] = m.imag.ravel()
-                self._mats[i] = buf
-                e.mat = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        # filled column by column through a numpy view of the ctypes array
+        rec = np.zeros(max(1, len(g)), dtype=_GATE_NP)
+        if len(g):
+            rec["kind"][: len(g)] = g["kind"]
+            rec["q0"][: len(g)] = g["q0"]
+            rec["q1"][: len(g)] = g["q1"]
+            rec["param"][: len(g)] = g["param"]
+            rec["angle"][: len(g)] = g["angle"]
+        for i, mat in (mats or {}).items():
+            if not 0 <= i < len(g):
+                continue
+            m = np.asarray(mat, dtype=np.complex128).reshape(2, 2)
+            buf = np.empty(8, dtype=np.float64)
+            buf[0::2] = m.real.ravel()
+            buf[1::2] = m.imag.ravel()
+            self._mats[i] = buf
+            rec["mat"][i] = buf.ctypes.data
+        self._rec = rec
+        arr = (Gate * len(rec)).from_buffer(rec)
         self._arr = arr
         self.c = Circuit(n, len(g), n_params, 0, arr)
         self.n, self.n_params = n, n_params
