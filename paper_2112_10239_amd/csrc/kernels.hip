@@ -612,7 +612,41 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
       }
     }
 
-    for (int o = S->op_begin; o < S->op_end; ++o) {
+    // Rotations U_j = X^f P_j T_j E_j on every register bit (the last op of its
+    // stage; the E table, when needed, is an OP_DTAB just before): each real T_j,
+    // the P table; the swaps X^f stay pending as an XOR mask on the register
+    // index, which the stage's exit addressing applies (block: 32 + 32 table
+    // scalars, k per bit, swap mask as a raw word).
+    auto utab = [&](kptr<DevOp> op) __attribute__((always_inline)) {
+      if constexpr (!DUAL && R <= 4 && std::is_same<T, float>::value) {
+        const kptr<T> blk = coef + (int64_t)op->slot * 8;
+        ap_tan<T, R, 0>(a, blk[64]);
+        if constexpr (R > 1) {
+          __builtin_amdgcn_sched_barrier(0);
+          ap_tan<T, R, 1>(a, blk[65]);
+        }
+        if constexpr (R > 2) {
+          __builtin_amdgcn_sched_barrier(0);
+          ap_tan<T, R, 2>(a, blk[66]);
+        }
+        if constexpr (R > 3) {
+          __builtin_amdgcn_sched_barrier(0);
+          ap_tan<T, R, 3>(a, blk[67]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        ap_table<T, R>(a, blk);
+        pend = *(kptr<uint32_t>)(blk + 68) & (uint32_t)(NR - 1);
+      }
+    };
+    // a factored op ends its stage: it runs after the op loop, outside the
+    // op dispatch (the loop is empty for the common stage holding only it)
+    int o_end = S->op_end;
+    bool last_utab = false;
+    if constexpr (!DUAL && R <= 4 && std::is_same<T, float>::value) {
+      last_utab = o_end > S->op_begin && (*(kptr<uint32_t>)(OPS + (o_end - 1)) & 0xffu) == OP_UTAB;
+      if (last_utab) --o_end;
+    }
+    for (int o = S->op_begin; o < o_end; ++o) {
       kptr<DevOp> op = OPS + o;
       // type, j, ck, cb | ck2, cb2, ph, pad
       const uint32_t w0 = *(kptr<uint32_t>)op, w1 = *((kptr<uint32_t>)op + 1);
@@ -692,29 +726,6 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
           }
         }
         o += R;
-      } else if (!DUAL && R <= 4 && std::is_same<T, float>::value && type == OP_UTAB) {
-        // rotations U_j = X^f P_j T_j E_j on every register bit (the last op of its
-        // stage; the E table, when needed, is an OP_DTAB just before): each real T_j,
-        // the P table; the swaps X^f stay pending as an XOR mask on the register
-        // index, which the stage's exit addressing applies (block: 32 + 32 table
-        // scalars, k per bit, swap mask as a raw word)
-        const kptr<T> blk = coef + (int64_t)op->slot * 8;
-        ap_tan<T, R, 0>(a, blk[64]);
-        if constexpr (R > 1) {
-          __builtin_amdgcn_sched_barrier(0);
-          ap_tan<T, R, 1>(a, blk[65]);
-        }
-        if constexpr (R > 2) {
-          __builtin_amdgcn_sched_barrier(0);
-          ap_tan<T, R, 2>(a, blk[66]);
-        }
-        if constexpr (R > 3) {
-          __builtin_amdgcn_sched_barrier(0);
-          ap_tan<T, R, 3>(a, blk[67]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        ap_table<T, R>(a, blk);
-        pend = *(kptr<uint32_t>)(blk + 68) & (uint32_t)(NR - 1);
       } else if (!DUAL && R <= 4 && std::is_same<T, float>::value && type == OP_DTAB) {
         ap_table<T, R>(a, coef + (int64_t)op->slot * 8 + 32);
       } else if (type == OP_PHASE) {
@@ -799,6 +810,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         }
       }
     }
+    if (last_utab) utab(OPS + o_end);
 
     if (!TAIL && s == sst) {
       const bool st_a = (flags & PF_STORE_A) != 0, st_b = DUAL && (flags & PF_STORE_B) != 0;

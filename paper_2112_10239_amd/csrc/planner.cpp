@@ -1040,6 +1040,17 @@ int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, P
 void append_diag_measure(Plan& plan, const std::vector<PGate>& meas) {
   if (meas.empty() || plan.passes.empty()) return;
   PassDesc& pd = plan.passes.back();
+  if (plan.stages.back().op_end > plan.stages.back().op_begin &&
+      plan.ops[plan.stages.back().op_end - 1].type == OP_UTAB) {
+    // a factored op ends its stage: measure in a stage of its own with the same
+    // register bits (the exchange between them applies the op's register swaps)
+    StageDesc nx = plan.stages.back();  // the last stage of a pass has no exit permutation
+    nx.has_perm = 0;
+    nx.n_aff = 0;
+    nx.op_begin = nx.op_end = (int)plan.ops.size();
+    plan.stages.push_back(nx);
+    pd.stage_end = (int)plan.stages.size();
+  }
   StageDesc& st = plan.stages.back();
   uint64_t L = 0;
   for (int k = 0; k < pd.m; ++k) L |= 1ull << pd.lpos[k];
