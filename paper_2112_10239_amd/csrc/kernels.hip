@@ -487,12 +487,34 @@ __device__ __forceinline__ void tile_load(kptr<PassDesc> P, kptr<StageDesc> S0, 
   z.y = 0;
   if (ld_a || ld_b) {
     uint64_t gr[R];
-    const uint64_t gt = stage_gaddr<R>(P, S0, tid, base, gr);
+    uint64_t gt;
+    if (P->entry_perm) {
+      // registers read from their sources under the inverse of the entry
+      // permutation: source offsets XOR over the thread's bits (lane bits per
+      // lane, wave bits and the tile's affine terms uniform) and register bits
+      const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
+      uint64_t gl = 0, gu = base;
+#pragma unroll
+      for (int k = 0; k < kMaxLocal - R; ++k)
+        if (k < m - R) {
+          const uint64_t c = *((kptr<uint64_t>)&P->ecol[0] + k);
+          if (k < 6) gl ^= ((uint32_t)(tid >> k) & 1u) ? c : 0ull;
+          else gu ^= ((wv >> (k - 6)) & 1u) ? c : 0ull;
+        }
+      const int na = P->n_eaff;
+      for (int j = 0; j < na; ++j)
+        if ((base >> kb(&P->eaff_pos[j])) & 1ull) gu ^= *((kptr<uint64_t>)&P->eaff[0] + j);
+      gt = gl ^ gu;
+#pragma unroll
+      for (int j = 0; j < R; ++j) gr[j] = *((kptr<uint64_t>)&P->ereg[0] + j);
+    } else {
+      gt = stage_gaddr<R>(P, S0, tid, base, gr);
+    }
     auto addr = [&](int i) __attribute__((always_inline)) {
       uint64_t g = gt;
 #pragma unroll
       for (int j = 0; j < R; ++j)
-        if ((i >> j) & 1) g |= gr[j];
+        if ((i >> j) & 1) g ^= gr[j];
       return g;
     };
     if (ld_a) {

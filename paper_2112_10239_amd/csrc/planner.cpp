@@ -365,6 +365,7 @@ struct PassEmitter {
   bool allow_fused_bits = false;  // OP_UALL / OP_RYALL (single-state kernels with r <= 4 only)
   bool allow_factored = false;    // OP_UTAB (single-state float kernels with r <= 4 only)
   int io_lo = -1;                 // see PlanOptions::io_lo
+  bool allow_entry = false;       // fold a permute-only first stage into the loads
 
   PassEmitter(Plan& p, int n_, int m_, int r_, uint64_t Lmask) : plan(p), n(n_), m(m_), r(r_), lidx(n_, -1) {
     for (int q = 0; q < n; ++q)
@@ -592,6 +593,96 @@ struct PassEmitter {
   }
 
   // Fill the exit permutation of a stage from its CNOT run.
+  // Images of a stage's CNOT run on the local index: l -> M l ^ b(tile), with
+  // col[k] = M e_k and b = XOR of the masks of the affine terms whose
+  // (physical, non-local) control bit is set in the tile.
+  void perm_images(const StageBuild& s, std::vector<uint32_t>& col,
+                   std::vector<std::pair<int, uint32_t>>& aff) const {
+    col.assign(m, 0);
+    for (int k = 0; k < m; ++k) col[k] = 1u << k;
+    aff.clear();
+    auto lbit = [&](uint32_t v, int c) { return (v >> c) & 1u; };
+    for (const PGate* g : s.perm) {
+      const int t = lidx[g->q];     // target is local
+      const int cq = g->q2;         // control: local or non-local
+      const int c = lidx[cq];
+      for (int k = 0; k < m; ++k)
+        if (c >= 0 && lbit(col[k], c)) col[k] ^= 1u << t;
+      for (auto& a : aff)
+        if (c >= 0 && lbit(a.second, c)) a.second ^= 1u << t;
+      if (c < 0) {
+        bool found = false;
+        for (auto& a : aff)
+          if (a.first == cq) {
+            a.second ^= 1u << t;
+            found = true;
+          }
+        if (!found) aff.push_back({cq, 1u << t});
+      }
+    }
+  }
+
+  // Physical index bits of a local index value.
+  uint64_t phys(uint32_t l) const {
+    uint64_t v = 0;
+    for (int k = 0; k < m; ++k)
+      if ((l >> k) & 1u) v |= 1ull << L[k];
+    return v;
+  }
+
+  // The first stage of a loading pass only permutes: fold its CNOT run into the
+  // loads of the next stage (registers read from M^-1 (l ^ b)) and drop it.
+  bool fold_entry(std::vector<StageBuild>& sb, PassDesc& pd) const {
+    if (sb.size() < 2 || !sb[0].items.empty() || sb[0].perm.empty()) return false;
+    std::vector<uint32_t> col;
+    std::vector<std::pair<int, uint32_t>> aff;
+    perm_images(sb[0], col, aff);
+    int na = 0;
+    for (auto& a : aff) na += a.second != 0;
+    if (na > kMaxAffine) return false;
+    // inverse of M over GF(2): rows of [M | I] reduced
+    std::vector<uint64_t> row(m, 0);  // low 32 bits: M's row, high: the identity's
+    for (int t = 0; t < m; ++t) {
+      uint32_t rv = 0;
+      for (int k = 0; k < m; ++k) rv |= ((col[k] >> t) & 1u) << k;
+      row[t] = rv | (1ull << (32 + t));
+    }
+    for (int c = 0; c < m; ++c) {
+      int piv = -1;
+      for (int t = c; t < m; ++t)
+        if ((row[t] >> c) & 1ull) {
+          piv = t;
+          break;
+        }
+      if (piv < 0) return false;
+      std::swap(row[c], row[piv]);
+      for (int t = 0; t < m; ++t)
+        if (t != c && ((row[t] >> c) & 1ull)) row[t] ^= row[c];
+    }
+    auto minv = [&](uint32_t v) {  // M^-1 v
+      uint32_t out = 0;
+      for (int t = 0; t < m; ++t) {
+        const uint32_t rinv = (uint32_t)(row[t] >> 32);
+        out |= (uint32_t)(__builtin_popcount(rinv & v) & 1) << t;
+      }
+      return out;
+    };
+    const StageBuild& s1 = sb[1];
+    pd.entry_perm = 1;
+    int t = 0;
+    for (int k = 0; k < m; ++k)
+      if (!rb_has(s1.rb, k)) pd.ecol[t++] = phys(minv(1u << k));
+    for (int j = 0; j < r; ++j) pd.ereg[j] = phys(minv(1u << s1.rb[j]));
+    pd.n_eaff = 0;
+    for (auto& a : aff)
+      if (a.second) {
+        pd.eaff_pos[pd.n_eaff] = (uint8_t)a.first;
+        pd.eaff[pd.n_eaff] = phys(minv(a.second));
+        ++pd.n_eaff;
+      }
+    return true;
+  }
+
   void fill_perm(const StageBuild& s, StageDesc& st) const {
     st.has_perm = 0;
     st.n_aff = 0;
@@ -672,6 +763,19 @@ struct PassEmitter {
     pd.m = m;
     pd.r = r;
     pd.flags = flags;
+    const int pass_no0 = (int)plan.passes.size();
+    if (allow_entry && (flags & PF_LOAD_A) && !(flags & (PF_LOAD_B | PF_INIT)) && store_rel != 0 &&
+        fold_entry(sb, pd)) {
+      for (const PGate* g : sb[0].perm)
+        for (int src : g->srcs) {  // applied while loading: ahead of the first stage's ops
+          plan.order.push_back(pass_no0);
+          plan.order.push_back(0);
+          plan.order.push_back(-1);
+          plan.order.push_back(src);
+        }
+      sb.erase(sb.begin());
+      if (store_rel > 0) --store_rel;
+    }
     pd.stage_begin = (int)plan.stages.size();
     pd.meas_index = -1;
     pd.store_stage = store_rel >= 0 ? pd.stage_begin + store_rel : -1;
@@ -965,6 +1069,7 @@ int plan_forward(int n, const std::vector<PGate>& gates, const std::vector<PGate
     em.allow_fused_bits = true;
     em.allow_factored = o.factored && !plan.slots.empty();
     em.io_lo = o.io_lo;
+    em.allow_entry = o.factored && o.entry_perm;
     std::vector<const PGate*> mod;
     for (int idx : lists[p]) mod.push_back(&gates[idx]);
     em.emit(mod, last ? fin : std::vector<const PGate*>{}, flags, c_low, p);

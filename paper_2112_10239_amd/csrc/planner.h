@@ -92,6 +92,7 @@ struct PlanOptions {
   bool absorb = true;   // allow CNOT runs as stage exit permutations
   int io_lo = -1;       // lowest local bit a register bit may use in a stage that loads or
                         // stores (HBM coalescing); -1: c_low
+  bool entry_perm = true;  // with factored: a permute-only first stage folded into the loads
   bool factored = false;  // runs of uncontrolled rotations on register bits as one OP_UTAB
                           // (single-state float kernels with r <= 4; needs plan.slots)
 };

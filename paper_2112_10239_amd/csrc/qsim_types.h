@@ -107,7 +107,17 @@ struct PassDesc {
   int32_t store_stage;    // absolute stage index after whose ops a (and b) are stored
   uint8_t lpos[kMaxLocal];   // physical bit of local index k
   uint8_t npos[kMaxQubits];  // physical bits of the non-local index, ascending (n - m used)
+  // Entry permutation: a CNOT run that the planner applies while loading (the
+  // first stage's registers are read from their sources under its inverse).
+  // Source offsets are in physical index bits and XOR together.
+  int32_t entry_perm;          // 1 when the loads go through the entry permutation
+  int32_t n_eaff;              // affine terms used
+  uint64_t ecol[kMaxLocal];    // source offset of the first stage's thread bit k
+  uint64_t ereg[8];            // source offset of its register bit j
+  uint64_t eaff[kMaxAffine];   // xor into the source offset when the tile's bit eaff_pos[j] is 1
+  uint8_t eaff_pos[kMaxAffine];
 };
+static_assert(sizeof(PassDesc) == 368, "PassDesc layout");
 
 // One light cone (or one small whole circuit) run by a single workgroup.
 struct ConeDesc {
