@@ -472,6 +472,33 @@ __device__ __forceinline__ uint64_t stage_gaddr(kptr<PassDesc> P, kptr<StageDesc
   return gt;
 }
 
+// Global offsets of the stage that stores: through the pass's exit permutation
+// (destination offsets of the thread bits, lane bits per lane and wave bits and
+// the tile's affine terms uniform, and of the register bits) when it has one.
+template <int R>
+__device__ __forceinline__ uint64_t store_gaddr(kptr<PassDesc> P, kptr<StageDesc> S, int tid, uint64_t base,
+                                                uint64_t* gr) {
+  if (P->exit_perm) {
+    const int m = P->m;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
+    uint64_t gl = 0, gu = base;
+#pragma unroll
+    for (int k = 0; k < kMaxLocal - R; ++k)
+      if (k < m - R) {
+        const uint64_t c = *((kptr<uint64_t>)&P->xcol[0] + k);
+        if (k < 6) gl ^= ((uint32_t)(tid >> k) & 1u) ? c : 0ull;
+        else gu ^= ((wv >> (k - 6)) & 1u) ? c : 0ull;
+      }
+    const int na = P->n_xaff;
+    for (int j = 0; j < na; ++j)
+      if ((base >> kb(&P->xaff_pos[j])) & 1ull) gu ^= *((kptr<uint64_t>)&P->xaff[0] + j);
+#pragma unroll
+    for (int j = 0; j < R; ++j) gr[j] = *((kptr<uint64_t>)&P->xreg[0] + j);
+    return gl ^ gu;
+  }
+  return stage_gaddr<R>(P, S, tid, base, gr);
+}
+
 // First stage of a tile: load a (and b) from HBM, or generate |0...0>.  Lanes
 // past the tile (tiles of fewer than 64 threads' worth of amplitudes) read a
 // valid slot of their tile too; tile_run zeroes them.
@@ -837,8 +864,8 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     if (!TAIL && s == sst) {
       const bool st_a = (flags & PF_STORE_A) != 0, st_b = DUAL && (flags & PF_STORE_B) != 0;
       uint64_t gr[R];
-      uint64_t gt = stage_gaddr<R>(P, S, tid, base, gr);
-      // gt has zeros at the register bits, so index i ^ pend is gt ^ (bits of pend) ^ (bits of i)
+      uint64_t gt = store_gaddr<R>(P, S, tid, base, gr);
+      // offsets combine by XOR, so index i ^ pend is gt ^ (bits of pend) ^ (bits of i)
 #pragma unroll
       for (int j = 0; j < R; ++j)
         if ((pend >> j) & 1u) gt ^= gr[j];
@@ -917,7 +944,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     // compiler count them, so waiting for a prefetched tile does not also wait
     // for these stores to complete.
     uint64_t gr[R];
-    uint64_t gt = stage_gaddr<R>(P, SD + (s1 - 1), tid, base, gr);
+    uint64_t gt = store_gaddr<R>(P, SD + (s1 - 1), tid, base, gr);
 #pragma unroll
     for (int j = 0; j < R; ++j)
       if ((pend >> j) & 1u) gt ^= gr[j];

@@ -366,6 +366,7 @@ struct PassEmitter {
   bool allow_factored = false;    // OP_UTAB (single-state float kernels with r <= 4 only)
   int io_lo = -1;                 // see PlanOptions::io_lo
   bool allow_entry = false;       // fold a permute-only first stage into the loads
+  bool allow_exit = false;        // apply the last stage's CNOT run in the store addresses
 
   PassEmitter(Plan& p, int n_, int m_, int r_, uint64_t Lmask) : plan(p), n(n_), m(m_), r(r_), lidx(n_, -1) {
     for (int q = 0; q < n; ++q)
@@ -508,11 +509,16 @@ struct PassEmitter {
       fill_rb(s.rb, r, m, lo_load);
       sb.push_back(std::move(s));
     }
-    // a permutation is realised at an exchange: give the last one a stage to land in
+    // a permutation is realised at an exchange: give the last one a stage to land
+    // in, unless it can go into the store addresses (stored pass, nothing read after)
     if (!sb.back().perm.empty()) {
-      StageBuild s;
-      fill_rb(s.rb, r, m, lo_store);
-      sb.push_back(std::move(s));
+      bool fold = allow_exit && stores && ro.empty() && sb.size() >= 2;
+      for (int k : sb.back().rb) fold &= k >= lo_store;
+      if (!fold) {
+        StageBuild s;
+        fill_rb(s.rb, r, m, lo_store);
+        sb.push_back(std::move(s));
+      }
     }
     store_rel = -1;
     if (stores) {
@@ -940,6 +946,26 @@ struct PassEmitter {
       plan.stages.push_back(st);
     }
     pd.stage_end = (int)plan.stages.size();
+    if (!sb.back().perm.empty() && store_rel == (int)sb.size() - 1) {
+      // the last stage's CNOT run goes into the store addresses: destination
+      // offsets of its thread and register bits under l -> M l ^ b
+      std::vector<uint32_t> col;
+      std::vector<std::pair<int, uint32_t>> aff;
+      perm_images(sb.back(), col, aff);
+      const StageBuild& sl = sb.back();
+      pd.exit_perm = 1;
+      int t = 0;
+      for (int k = 0; k < m; ++k)
+        if (!rb_has(sl.rb, k)) pd.xcol[t++] = phys(col[k]);
+      for (int j = 0; j < r; ++j) pd.xreg[j] = phys(col[sl.rb[j]]);
+      pd.n_xaff = 0;
+      for (auto& a : aff)
+        if (a.second && pd.n_xaff < kMaxAffine) {
+          pd.xaff_pos[pd.n_xaff] = (uint8_t)a.first;
+          pd.xaff[pd.n_xaff] = phys(a.second);
+          ++pd.n_xaff;
+        }
+    }
     if (any_meas) {
       pd.flags |= PF_MEASURE;
       pd.meas_index = plan.n_meas++;
@@ -1070,6 +1096,7 @@ int plan_forward(int n, const std::vector<PGate>& gates, const std::vector<PGate
     em.allow_factored = o.factored && !plan.slots.empty();
     em.io_lo = o.io_lo;
     em.allow_entry = o.factored && o.entry_perm;
+    em.allow_exit = o.factored && o.entry_perm;
     std::vector<const PGate*> mod;
     for (int idx : lists[p]) mod.push_back(&gates[idx]);
     em.emit(mod, last ? fin : std::vector<const PGate*>{}, flags, c_low, p);
@@ -1145,11 +1172,13 @@ int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, P
 void append_diag_measure(Plan& plan, const std::vector<PGate>& meas) {
   if (meas.empty() || plan.passes.empty()) return;
   PassDesc& pd = plan.passes.back();
-  if (plan.stages.back().op_end > plan.stages.back().op_begin &&
-      plan.ops[plan.stages.back().op_end - 1].type == OP_UTAB) {
-    // a factored op ends its stage: measure in a stage of its own with the same
-    // register bits (the exchange between them applies the op's register swaps)
-    StageDesc nx = plan.stages.back();  // the last stage of a pass has no exit permutation
+  const bool utab_last = plan.stages.back().op_end > plan.stages.back().op_begin &&
+                         plan.ops[plan.stages.back().op_end - 1].type == OP_UTAB;
+  if (utab_last || pd.exit_perm) {
+    // a factored op ends the stage, or its CNOT run is left to the store
+    // addresses: measure in a stage of its own with the same register bits (the
+    // exchange between them applies the op's register swaps and the CNOT run)
+    StageDesc nx = plan.stages.back();
     nx.has_perm = 0;
     nx.n_aff = 0;
     nx.op_begin = nx.op_end = (int)plan.ops.size();

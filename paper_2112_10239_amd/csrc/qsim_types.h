@@ -116,8 +116,16 @@ struct PassDesc {
   uint64_t ereg[8];            // source offset of its register bit j
   uint64_t eaff[kMaxAffine];   // xor into the source offset when the tile's bit eaff_pos[j] is 1
   uint8_t eaff_pos[kMaxAffine];
+  // Exit permutation: the last stage's CNOT run applied in the store addresses
+  // (destination offsets under l -> M l ^ b, in physical index bits).
+  int32_t exit_perm;           // 1 when the stores go through the exit permutation
+  int32_t n_xaff;
+  uint64_t xcol[kMaxLocal];    // destination offset of the last stage's thread bit k
+  uint64_t xreg[8];            // destination offset of its register bit j
+  uint64_t xaff[kMaxAffine];   // xor into the destination when the tile's bit xaff_pos[j] is 1
+  uint8_t xaff_pos[kMaxAffine];
 };
-static_assert(sizeof(PassDesc) == 368, "PassDesc layout");
+static_assert(sizeof(PassDesc) == 640, "PassDesc layout");
 
 // One light cone (or one small whole circuit) run by a single workgroup.
 struct ConeDesc {
