@@ -121,12 +121,16 @@ PlanOptions fwd_options(int c128) {
   // uncontrolled rotations on a stage's register bits as one factored op (two
   // multiply-adds per amplitude and bit plus one diagonal table) in float plans
   static const bool factored = env_int("QSIM_FACTORED", 1) != 0;
+  // lowest local bit that load/store stages may hold in registers (-1: the
+  // always-local low bits stay lane bits, so every access covers whole segments)
+  static const int io_lo = std::min(6, std::max(-1, env_int("QSIM_IO_LO", -1)));
   PlanOptions o;
   o.m_max = c128 ? 13 : m64;
   o.r = c128 ? 4 : std::max(r64, o.m_max - 10);  // at most 1024 threads per workgroup
   o.c_low = clow;
   o.absorb = absorb;
   o.factored = factored && !c128 && o.r <= 4;
+  o.io_lo = io_lo;
   return o;
 }
 
@@ -134,6 +138,7 @@ PlanOptions cone_options(int c128) {
   PlanOptions o = fwd_options(c128);
   o.r = 4;  // the cone kernel keeps 16 amplitudes per thread
   o.factored = false;
+  o.io_lo = -1;
   return o;
 }
 
