@@ -19,7 +19,8 @@
  *   - RX/RY/RZ(t) = exp(-i t P / 2) with P = X/Y/Z;
  *   - CZ = diag(1,1,1,-1) on (q0, q1); CNOT has control q0 and target q1;
  *   - U1 is a fixed caller-given 2x2 unitary (row-major complex128, 8 doubles
- *     re,im interleaved);
+ *     re,im interleaved); a matrix with an entry of U^dagger U - I above 1e-8 in
+ *     magnitude is rejected with QSIM_EINVAL;
  *   - H = sum_t coeff[t] * P_t with real coefficients and Pauli strings P_t
  *     on distinct qubits; the empty string is the identity.
  *
