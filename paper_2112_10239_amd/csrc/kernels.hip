@@ -499,12 +499,65 @@ __device__ __forceinline__ uint64_t store_gaddr(kptr<PassDesc> P, kptr<StageDesc
   return stage_gaddr<R>(P, S, tid, base, gr);
 }
 
+// Product start state of a tile (first pass of a plan with leading single-qubit
+// gates folded in): prod_q (U_q|0>)_{x_q} as the tile's factor (its non-local
+// bits), the thread's (its bits) and the register factors by doubling.  Kept out
+// of line: it runs once per tile of the first pass only, and its registers stay
+// out of the pass kernel's allocation.
+template <class T, int R>
+__device__ __attribute__((noinline)) void init_product(kptr<PassDesc> P, kptr<StageDesc> S0, uint64_t base,
+                                                       kptr<T> coef, cpx<T>* a) {
+  const int m = P->m;
+  const int tid = threadIdx.x;
+  const kptr<T> f = coef + (int64_t)P->init_slot * 8;
+  const bool active = tid < (1 << (m - R));
+  T cr = 1, ci = 0;
+  const int nn = P->n - m;
+  for (int k = 0; k < nn; ++k) {
+    const int q = (int)kb(&P->npos[k]);
+    const int o = 4 * q + 2 * (int)((base >> q) & 1ull);
+    const T fr = f[o], fi = f[o + 1];
+    const T xr = cr * fr - ci * fi;
+    ci = cr * fi + ci * fr;
+    cr = xr;
+  }
+  const KWords<kMaxLocal / 4> tp(S0->tpos);
+#pragma unroll
+  for (int k = 0; k < kMaxLocal - R; ++k)
+    if (k < m - R) {
+      const int q = (int)tp.u8(k);
+      const bool one = ((tid >> k) & 1) != 0;
+      const T fr = one ? f[4 * q + 2] : f[4 * q], fi = one ? f[4 * q + 3] : f[4 * q + 1];
+      const T xr = cr * fr - ci * fi;
+      ci = cr * fi + ci * fr;
+      cr = xr;
+    }
+  const KWords<2> rp(S0->rpos);
+  a[0].x = active ? cr : T(0);
+  a[0].y = active ? ci : T(0);
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int q = (int)rp.u8(j);
+    const T f0r = f[4 * q], f0i = f[4 * q + 1], f1r = f[4 * q + 2], f1i = f[4 * q + 3];
+#pragma unroll
+    for (int i = 0; i < (1 << j); ++i) {
+      const int i1 = i | (1 << j);
+      const cpx<T> x = a[i];
+      a[i1].x = x.x * f1r - x.y * f1i;
+      a[i1].y = x.x * f1i + x.y * f1r;
+      a[i].x = x.x * f0r - x.y * f0i;
+      a[i].y = x.x * f0i + x.y * f0r;
+    }
+  }
+}
+
 // First stage of a tile: load a (and b) from HBM, or generate |0...0>.  Lanes
 // past the tile (tiles of fewer than 64 threads' worth of amplitudes) read a
 // valid slot of their tile too; tile_run zeroes them.
 template <class T, int R, bool DUAL>
 __device__ __forceinline__ void tile_load(kptr<PassDesc> P, kptr<StageDesc> S0, const cpx<T>* __restrict__ A,
-                                          const cpx<T>* __restrict__ B, uint64_t base, TileRegs<T, R, DUAL>& t) {
+                                          const cpx<T>* __restrict__ B, uint64_t base, TileRegs<T, R, DUAL>& t,
+                                          kptr<T> coef) {
   constexpr int NR = 1 << R;
   const int m = P->m, flags = P->flags;
   const int tid = threadIdx.x;
@@ -559,6 +612,15 @@ __device__ __forceinline__ void tile_load(kptr<PassDesc> P, kptr<StageDesc> S0, 
 #pragma unroll
         for (int i = 0; i < NR; ++i) t.b[i] = z;
       }
+    }
+  } else if ((flags & PF_INIT) && P->init_fac) {
+    cpx<T> tmp[NR];  // through memory: the registers of t stay registers
+    init_product<T, R>(P, S0, base, coef, tmp);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) t.a[i] = tmp[i];
+    if constexpr (DUAL) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) t.b[i] = z;
     }
   } else {
     const bool active = tid < (1 << (m - R));
@@ -1020,7 +1082,8 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass(
   const uint64_t M = nonlocal_mask(P);
   const uint64_t dstep = deposit((uint64_t)gridDim.x & (uint64_t)(tiles - 1), M);
   uint64_t base = deposit(tile, M);
-  tile_load<T, R, DUAL>(P, S0, A + row * row_stride, DUAL ? B + row * row_stride : nullptr, base, cur);
+  tile_load<T, R, DUAL>(P, S0, A + row * row_stride, DUAL ? B + row * row_stride : nullptr, base, cur,
+                        coef + row * coef_row_stride);
   while (true) {
     const int64_t wn = w + gridDim.x;
     const bool more = wn < total;
@@ -1030,7 +1093,8 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass(
     if constexpr (PF) {
       TileRegs<T, R, DUAL> nxt;
       if (more)
-        tile_load<T, R, DUAL>(P, S0, A + rown * row_stride, DUAL ? B + rown * row_stride : nullptr, basen, nxt);
+        tile_load<T, R, DUAL>(P, S0, A + rown * row_stride, DUAL ? B + rown * row_stride : nullptr, basen, nxt,
+                              coef + rown * coef_row_stride);
       double* gout = (DUAL && grad) ? grad + row * n_gslots * tiles + (int64_t)tile : nullptr;
       const double v = tile_run<T, R, DUAL, TAIL>(P, SD, OPS, A + row * row_stride,
                                                   DUAL ? B + row * row_stride : nullptr, coef + row * coef_row_stride,
@@ -1046,7 +1110,8 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass(
       if ((P->flags & PF_MEASURE) && threadIdx.x == 0)
         meas[(row * n_meas + P->meas_index) * tiles + (int64_t)tile] = v;
       if (!more) break;
-      tile_load<T, R, DUAL>(P, S0, A + rown * row_stride, DUAL ? B + rown * row_stride : nullptr, basen, cur);
+      tile_load<T, R, DUAL>(P, S0, A + rown * row_stride, DUAL ? B + rown * row_stride : nullptr, basen, cur,
+                            coef + rown * coef_row_stride);
     }
     w = wn;
     row = rown;
@@ -1090,7 +1155,7 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass_multi
     cpx<T>* A = reinterpret_cast<cpx<T>*>(it->A);
     cpx<T>* B = reinterpret_cast<cpx<T>*>(it->B);
     TileRegs<T, R, DUAL> t;
-    tile_load<T, R, DUAL>(P, SD + P->stage_begin, A, B, base, t);
+    tile_load<T, R, DUAL>(P, SD + P->stage_begin, A, B, base, t, kc(reinterpret_cast<const T*>(it->coef)));
     const double v = tile_run<T, R, DUAL>(P, SD, kc(it->ops), A, B, kc(reinterpret_cast<const T*>(it->coef)), base,
                                           t, lds, red, gacc, gout, tiles);
     if ((P->flags & PF_MEASURE) && threadIdx.x == 0) it->meas[(int64_t)P->meas_index * tiles + (int64_t)tile] = v;
@@ -1127,7 +1192,7 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_cones(
     uint64_t base = 0;
     for (int64_t t = 0; t < tiles; ++t, base = next_base(base, M, d1)) {
       TileRegs<T, R, DUAL> regs;
-      tile_load<T, R, DUAL>(pp, SD + pp->stage_begin, st, st_b, base, regs);
+      tile_load<T, R, DUAL>(pp, SD + pp->stage_begin, st, st_b, base, regs, cf);
       total += tile_run<T, R, DUAL>(pp, SD, OPS, st, st_b, cf, base, regs, lds, red, gacc, grad, 1, t > 0);
       lds_sync();
     }

@@ -1055,12 +1055,36 @@ int check_terms(const std::vector<PGate>& terms, int r, std::string& err) {
 
 }  // namespace
 
-int plan_forward(int n, const std::vector<PGate>& gates, const std::vector<PGate>& meas, const PlanOptions& o,
+int plan_forward(int n, const std::vector<PGate>& gates_in, const std::vector<PGate>& meas, const PlanOptions& o,
                  Plan& plan, std::string& err) {
   if (n > kMaxQubits) {
     err = "dense mode supports at most 40 qubits";
     return -1;
   }
+  // Product-state start: on every qubit, the fused single-qubit gate that comes
+  // before any two-qubit gate on it acts on |0>, so the first pass can generate
+  // prod_q U_q|0> instead of |0...0> and the gate leaves the plan.
+  const std::vector<PGate>* gp = &gates_in;
+  std::vector<PGate> rest;
+  std::vector<int> lead_slot(n, -1);
+  std::vector<const PGate*> lead;
+  if (o.init && o.factored && o.init_factors && !plan.slots.empty()) {
+    std::vector<char> touched(n, 0);
+    for (const PGate& g : gates_in) {
+      const bool one = (g.kind == PG_U || g.kind == PG_RY || g.kind == PG_PHASE) && g.q2 < 0;
+      if (one && !touched[g.q] && g.slot >= 0) {
+        lead_slot[g.q] = g.slot;
+        lead.push_back(&g);
+        touched[g.q] = 1;
+        continue;
+      }
+      if (g.q >= 0) touched[g.q] = 1;
+      if (g.q2 >= 0) touched[g.q2] = 1;
+      rest.push_back(g);
+    }
+    if (!lead.empty()) gp = &rest;
+  }
+  const std::vector<PGate>& gates = *gp;
   plan.n = n;
   plan.m = std::min(n, o.m_max);
   plan.r = std::min(o.r, plan.m);
@@ -1105,6 +1129,26 @@ int plan_forward(int n, const std::vector<PGate>& gates, const std::vector<PGate
     PassEmitter em(plan, n, m, r, mLs[k]);
     em.emit({}, mgroups[k], PF_LOAD_A, c_low, -1);
     ++plan.meas_passes;
+  }
+  if (!lead.empty() && !plan.passes.empty() && (plan.passes[0].flags & PF_INIT)) {
+    PGate blk;
+    blk.kind = PG_INITF;
+    blk.q = n;
+    blk.srcs = lead_slot;
+    plan.passes[0].init_fac = 1;
+    plan.passes[0].init_slot = (int)plan.slots.size();
+    for (int chunk = 0; chunk < init_slots(n); ++chunk) {
+      blk.gen = chunk;
+      blk.slot = (int)plan.slots.size();
+      plan.slots.push_back(blk);
+    }
+    for (const PGate* g : lead)  // applied by the start state: ahead of everything
+      for (int src : g->srcs) {
+        plan.order.push_back(0);
+        plan.order.push_back(0);
+        plan.order.push_back(-2);
+        plan.order.push_back(src);
+      }
   }
   return 0;
 }
@@ -1381,7 +1425,7 @@ static void build_rows(const CircuitDesc& c, const std::vector<PGate>& slots, co
     T* row = out + (size_t)b * row_stride;
     for (size_t s = 0; s < slots.size(); ++s) {
       const PGate& p = slots[s];
-      if (p.kind == PG_TAB) continue;
+      if (p.kind == PG_TAB || p.kind == PG_INITF) continue;
       T* o = row + s * 8;
       for (int k = 0; k < 8; ++k) o[k] = 0;
       const M2 M = ms[s] = slot_m2(c, p, th);
@@ -1396,6 +1440,24 @@ static void build_rows(const CircuitDesc& c, const std::vector<PGate>& slots, co
         o[2] = (T)M.a[0][1].real(); o[3] = (T)M.a[0][1].imag();
         o[4] = (T)M.a[1][0].real(); o[5] = (T)M.a[1][0].imag();
         o[6] = (T)M.a[1][1].real(); o[7] = (T)M.a[1][1].imag();
+      }
+    }
+    // product-state start: (U_q|0>)_0, (U_q|0>)_1 per qubit over init_slots(n) slots
+    for (size_t s = 0; s < slots.size(); ++s) {
+      const PGate& p = slots[s];
+      if (p.kind != PG_INITF || p.gen != 0) continue;
+      T* o = row + s * 8;
+      for (int e = 0; e < 8 * init_slots(p.q); ++e) o[e] = 0;
+      for (int q = 0; q < p.q; ++q) {
+        cd f0 = 1, f1 = 0;
+        if (p.srcs[q] >= 0) {
+          f0 = ms[p.srcs[q]].a[0][0];
+          f1 = ms[p.srcs[q]].a[1][0];
+        }
+        o[4 * q] = (T)f0.real();
+        o[4 * q + 1] = (T)f0.imag();
+        o[4 * q + 2] = (T)f1.real();
+        o[4 * q + 3] = (T)f1.imag();
       }
     }
     // factored groups: one block over kTabSlots consecutive slots, from the member matrices

@@ -31,7 +31,12 @@ struct CircuitDesc {
 
 // Planner-level operation ("pgate"): a fused gate, a gradient probe, or a
 // measurement / H-apply term.
-enum PGKind { PG_U, PG_RY, PG_X, PG_PHASE, PG_CZ, PG_GRAD, PG_MEAS_Z, PG_MEAS_F, PG_H_Z, PG_H_F, PG_TAB };
+enum PGKind { PG_U, PG_RY, PG_X, PG_PHASE, PG_CZ, PG_GRAD, PG_MEAS_Z, PG_MEAS_F, PG_H_Z, PG_H_F, PG_TAB, PG_INITF };
+
+// PG_INITF coefficient slots: init_slots(n) consecutive slots hold, per physical
+// qubit q, (U_q|0>)_0 and (U_q|0>)_1 as 4 scalars (re, im, re, im), U_q being
+// the slot in srcs[q] (-1: identity); gen is the chunk a slot holds.
+inline int init_slots(int n) { return (4 * n + 7) / 8; }
 
 // PG_TAB coefficient slots: kTabSlots consecutive slots hold the block of one
 // OP_UTAB op: uncontrolled rotations on the register bits of a stage (identity
@@ -93,6 +98,7 @@ struct PlanOptions {
   int io_lo = -1;       // lowest local bit a register bit may use in a stage that loads or
                         // stores (HBM coalescing); -1: c_low
   bool entry_perm = true;  // with factored: a permute-only first stage folded into the loads
+  bool init_factors = true;  // with factored and init: leading single-qubit gates folded into the start state
   bool factored = false;  // runs of uncontrolled rotations on register bits as one OP_UTAB
                           // (single-state float kernels with r <= 4; needs plan.slots)
 };

@@ -124,8 +124,14 @@ struct PassDesc {
   uint64_t xreg[8];            // destination offset of its register bit j
   uint64_t xaff[kMaxAffine];   // xor into the destination when the tile's bit xaff_pos[j] is 1
   uint8_t xaff_pos[kMaxAffine];
+  // Product-state start (first pass only): the circuit's leading single-qubit
+  // gates on every qubit are folded into the generated state prod_q U_q|0>; the
+  // coefficient block at init_slot holds (U_q|0>)_0 and (U_q|0>)_1 per physical
+  // qubit q (4 scalars each; 1 and 0 for qubits without such gates).
+  int32_t init_fac;            // 1 when the first pass generates the product state
+  int32_t init_slot;
 };
-static_assert(sizeof(PassDesc) == 640, "PassDesc layout");
+static_assert(sizeof(PassDesc) == 648, "PassDesc layout");
 
 // One light cone (or one small whole circuit) run by a single workgroup.
 struct ConeDesc {
