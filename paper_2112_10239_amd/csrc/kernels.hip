@@ -500,17 +500,15 @@ __device__ __forceinline__ uint64_t store_gaddr(kptr<PassDesc> P, kptr<StageDesc
 }
 
 // Product start state of a tile (first pass of a plan with leading single-qubit
-// gates folded in): prod_q (U_q|0>)_{x_q} as the tile's factor (its non-local
-// bits), the thread's (its bits) and the register factors by doubling.  Kept out
-// of line: it runs once per tile of the first pass only, and its registers stay
-// out of the pass kernel's allocation.
+// gates folded in): prod_q (U_q|0>)_{x_q}.  The factor of the tile's non-local
+// bits and the thread's bits is computed out of line (once per tile of the first
+// pass only, its registers outside the pass kernel's allocation); the register
+// factors are multiplied in by doubling at the call.
 template <class T, int R>
-__device__ __attribute__((noinline)) void init_product(kptr<PassDesc> P, kptr<StageDesc> S0, uint64_t base,
-                                                       kptr<T> coef, cpx<T>* a) {
+__device__ __attribute__((noinline)) cpx<T> init_thread_factor(kptr<PassDesc> P, kptr<StageDesc> S0, uint64_t base,
+                                                               kptr<T> f) {
   const int m = P->m;
   const int tid = threadIdx.x;
-  const kptr<T> f = coef + (int64_t)P->init_slot * 8;
-  const bool active = tid < (1 << (m - R));
   T cr = 1, ci = 0;
   const int nn = P->n - m;
   for (int k = 0; k < nn; ++k) {
@@ -532,23 +530,10 @@ __device__ __attribute__((noinline)) void init_product(kptr<PassDesc> P, kptr<St
       ci = cr * fi + ci * fr;
       cr = xr;
     }
-  const KWords<2> rp(S0->rpos);
-  a[0].x = active ? cr : T(0);
-  a[0].y = active ? ci : T(0);
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    const int q = (int)rp.u8(j);
-    const T f0r = f[4 * q], f0i = f[4 * q + 1], f1r = f[4 * q + 2], f1i = f[4 * q + 3];
-#pragma unroll
-    for (int i = 0; i < (1 << j); ++i) {
-      const int i1 = i | (1 << j);
-      const cpx<T> x = a[i];
-      a[i1].x = x.x * f1r - x.y * f1i;
-      a[i1].y = x.x * f1i + x.y * f1r;
-      a[i].x = x.x * f0r - x.y * f0i;
-      a[i].y = x.x * f0i + x.y * f0r;
-    }
-  }
+  cpx<T> c;
+  c.x = cr;
+  c.y = ci;
+  return c;
 }
 
 // First stage of a tile: load a (and b) from HBM, or generate |0...0>.  Lanes
@@ -614,10 +599,26 @@ __device__ __forceinline__ void tile_load(kptr<PassDesc> P, kptr<StageDesc> S0, 
       }
     }
   } else if ((flags & PF_INIT) && P->init_fac) {
-    cpx<T> tmp[NR];  // through memory: the registers of t stay registers
-    init_product<T, R>(P, S0, base, coef, tmp);
+    const kptr<T> f = coef + (int64_t)P->init_slot * 8;
+    const cpx<T> c = init_thread_factor<T, R>(P, S0, base, f);
+    const bool active = tid < (1 << (m - R));
+    t.a[0].x = active ? c.x : T(0);
+    t.a[0].y = active ? c.y : T(0);
+    const KWords<2> rp(S0->rpos);
 #pragma unroll
-    for (int i = 0; i < NR; ++i) t.a[i] = tmp[i];
+    for (int j = 0; j < R; ++j) {  // register factors by doubling, in place
+      const int q = (int)rp.u8(j);
+      const T f0r = f[4 * q], f0i = f[4 * q + 1], f1r = f[4 * q + 2], f1i = f[4 * q + 3];
+#pragma unroll
+      for (int i = 0; i < (1 << j); ++i) {
+        const int i1 = i | (1 << j);
+        const cpx<T> x = t.a[i];
+        t.a[i1].x = x.x * f1r - x.y * f1i;
+        t.a[i1].y = x.x * f1i + x.y * f1r;
+        t.a[i].x = x.x * f0r - x.y * f0i;
+        t.a[i].y = x.x * f0i + x.y * f0r;
+      }
+    }
     if constexpr (DUAL) {
 #pragma unroll
       for (int i = 0; i < NR; ++i) t.b[i] = z;
