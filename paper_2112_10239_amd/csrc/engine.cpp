@@ -131,6 +131,11 @@ PlanOptions fwd_options(int c128) {
   o.absorb = absorb;
   o.factored = factored && !c128 && o.r <= 4;
   o.io_lo = io_lo;
+  // permutation folds and the product-state start (with factored; default on)
+  static const int folds = env_int("QSIM_FOLDS", 7);
+  o.entry_perm = (folds & 1) != 0;
+  o.exit_perm = (folds & 2) != 0;
+  o.init_factors = (folds & 4) != 0;
   return o;
 }
 

@@ -923,6 +923,14 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
       }
     }
     if (last_utab) utab(OPS + o_end);
+    // A one-stage pass whose loads or stores go through a permutation stores to
+    // addresses other waves load from, with no exchange barrier in between: every
+    // wave's loads must be complete before any wave stores.
+    const bool cross = s0 + 1 == s1 && (P->entry_perm || P->exit_perm);
+    if (cross && (TAIL || s == sst)) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      lds_sync();
+    }
 
     if (!TAIL && s == sst) {
       const bool st_a = (flags & PF_STORE_A) != 0, st_b = DUAL && (flags & PF_STORE_B) != 0;

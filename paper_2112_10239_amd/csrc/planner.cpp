@@ -1120,7 +1120,7 @@ int plan_forward(int n, const std::vector<PGate>& gates_in, const std::vector<PG
     em.allow_factored = o.factored && !plan.slots.empty();
     em.io_lo = o.io_lo;
     em.allow_entry = o.factored && o.entry_perm;
-    em.allow_exit = o.factored && o.entry_perm;
+    em.allow_exit = o.factored && o.exit_perm;
     std::vector<const PGate*> mod;
     for (int idx : lists[p]) mod.push_back(&gates[idx]);
     em.emit(mod, last ? fin : std::vector<const PGate*>{}, flags, c_low, p);

@@ -98,6 +98,7 @@ struct PlanOptions {
   int io_lo = -1;       // lowest local bit a register bit may use in a stage that loads or
                         // stores (HBM coalescing); -1: c_low
   bool entry_perm = true;  // with factored: a permute-only first stage folded into the loads
+  bool exit_perm = true;   // with factored: the last stage's CNOT run folded into the stores
   bool init_factors = true;  // with factored and init: leading single-qubit gates folded into the start state
   bool factored = false;  // runs of uncontrolled rotations on register bits as one OP_UTAB
                           // (single-state float kernels with r <= 4; needs plan.slots)

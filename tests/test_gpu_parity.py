@@ -92,7 +92,7 @@ def test_ring_maxcut_n10_c128(Q, eng, oracle_mod):
 
 # --- dense brickwork family ---------------------------------------------------------
 
-@pytest.mark.parametrize("n,depth", [(6, 3), (10, 20), (14, 10), (15, 8), (16, 12), (19, 6), (20, 6), (20, 20)])
+@pytest.mark.parametrize("n,depth", [(6, 3), (10, 20), (14, 10), (15, 8), (16, 12), (19, 6), (20, 6), (20, 20), (21, 5)])
 def test_dense_tfim_family(Q, eng, oracle_mod, n, depth):
     say("dense tfim", n, depth)
     c = W.brickwork_ry_rz_cnot(n, depth)
