@@ -122,8 +122,11 @@ PlanOptions fwd_options(int c128) {
   // multiply-adds per amplitude and bit plus one diagonal table) in float plans
   static const bool factored = env_int("QSIM_FACTORED", 1) != 0;
   // lowest local bit that load/store stages may hold in registers (-1: the
-  // always-local low bits stay lane bits, so every access covers whole segments)
-  static const int io_lo = std::min(6, std::max(-1, env_int("QSIM_IO_LO", -1)));
+  // always-local low bits stay lane bits, so every access covers whole segments;
+  // default 0: a load/store stage may hold them too, which saves the extra stage
+  // a pass would otherwise need to store, at the price of accesses that cover
+  // each segment over several instructions; measured slightly faster)
+  static const int io_lo = std::min(6, std::max(-1, env_int("QSIM_IO_LO", 0)));
   PlanOptions o;
   o.m_max = c128 ? 13 : m64;
   o.r = c128 ? 4 : std::max(r64, o.m_max - 10);  // at most 1024 threads per workgroup
