@@ -99,21 +99,40 @@ typedef struct {
     const uint8_t* paulis;
 } qsim_hamiltonian;
 
-/* Context options; zero fields take defaults. */
+/* Context options, fixed for the context's lifetime; zero fields take the
+ * defaults (an environment variable of the same meaning, where one exists,
+ * replaces a default: QSIM_FWD_M, QSIM_FWD_R, QSIM_FWD_CLOW, QSIM_DUAL_CLOW). */
 typedef struct {
-    int32_t device;             /* HIP device ordinal */
+    int32_t device;             /* HIP device ordinal; -1 = host-only context (plans, simulated serving) */
     int32_t max_queue;          /* serving: queued + in-flight requests (default 4096) */
     int32_t cone_cap;           /* light cones above this many qubits are ETOOBIG (default 20) */
-    int32_t pad;
+    int32_t max_inflight;       /* serving: scheduler steps in flight on the device, 1..8 (default 3) */
     uint64_t hbm_budget_bytes;  /* serving: bytes of state memory in flight (default 64 GiB) */
+    int32_t tile_qubits;        /* complex64 forward passes: tiles of 2^m amplitudes, m in 12..14 (default 13) */
+    int32_t register_bits;      /* complex64 forward passes: 2^r amplitudes per thread, r in 3..5 (default 4) */
+    int32_t coalesce_bits;      /* forward passes: lowest index bits local in every pass, 3..6 (default 4) */
+    int32_t dual_coalesce_bits; /* adjoint (two-state) passes: the same, 3..6 (default 6) */
+    int32_t disable;            /* QSIM_OFF_* bits, each switching one optimisation off (default 0) */
+    int32_t reserved[3];
 } qsim_options;
+
+#define QSIM_OFF_FACTORED 1   /* rotations on a stage's register bits as one factored op */
+#define QSIM_OFF_ABSORB 2     /* runs of CNOTs applied as stage exit permutations */
+#define QSIM_OFF_ENTRY 4      /* a permute-only first stage folded into the loads */
+#define QSIM_OFF_EXIT 8       /* a pass's last CNOT run folded into the store addresses */
+#define QSIM_OFF_PRODUCT 16   /* leading single-qubit gates folded into a product start state */
+#define QSIM_OFF_PREFETCH 32  /* register prefetch of the next tile */
+#define QSIM_OFF_IO_REGS 64   /* load/store stages may hold the always-local low bits in registers */
 
 typedef struct qsim_ctx qsim_ctx;
 typedef struct qsim_state qsim_state;
 
-/* Create a context on opt->device (opt may be NULL).  Owns a HIP stream,
- * device workspaces and the plan cache. */
-int qsim_init(const qsim_options* opt, qsim_ctx** out);
+/* Create a context on opt->device (opt may be NULL: device 0, defaults).  Owns a
+ * HIP stream, device workspaces and the plan cache; *out is NULL on failure.
+ * QSIM_EDEVICE when the device does not exist.  Every evaluation of the paper's
+ * objective (Sec. 1: expectation values of circuits, Sec. 3: values and
+ * gradients) goes through a context. */
+int qsim_init(qsim_ctx** out, const qsim_options* opt);
 /* Stop the serving loop (pending tickets end with QSIM_ESHUTDOWN), free everything. */
 void qsim_finalize(qsim_ctx* ctx);
 /* Static text for a status code. */
@@ -130,10 +149,13 @@ const char* qsim_last_error(qsim_ctx* ctx);
 int qsim_create_state(qsim_ctx* ctx, int n_qubits, int batch, int dtype, void* dev_buf, void* stream,
                       qsim_state** out);
 int qsim_destroy_state(qsim_state* st);
-/* Append gates to the state's queue.  params: host float64 [batch * n_params] (row b
- * for state b), read during the call only; may be NULL when no gate has param >= 0.
+/* Append gates to the state's queue.  params: float64 [batch * n_params] (row b for
+ * state b); host memory, or device memory when params_on_device != 0 (read in the
+ * order of the state's stream; the coefficients are then built on the device and
+ * the values never reach the host).  May be NULL when no gate has param >= 0.
  * Queued gates are planned and applied at the next qsim_expect or qsim_state_to_host. */
-int qsim_apply_layer(qsim_state* st, const qsim_gate* gates, int n_gates, const double* params, int n_params);
+int qsim_apply_layer(qsim_state* st, const qsim_gate* gates, int n_gates, const double* params, int n_params,
+                     int params_on_device);
 /* out[b] = <psi_b|H|psi_b> (float64, host, [batch]); flushes queued gates. */
 int qsim_expect(qsim_state* st, const qsim_hamiltonian* H, double* out);
 /* Copy the states to host memory (batch * 2^n complex of the state's dtype); flushes. */
@@ -156,20 +178,34 @@ int qsim_reduced_density(qsim_state* st, const int32_t* qubits, int m, void* rho
 /* ---- one-call evaluation (Sec. 3: forward value) ----------------------------------- */
 
 /* out[b] = <psi(theta_b)|H|psi(theta_b)> for b < batch, theta_b = params + b*n_params
- * (host float64).  mode: dense state vector, per-term light cones, factored light
+ * (float64; host memory, or device memory when params_on_device != 0, in which
+ * case the gate coefficients are built on the device and the parameters are never
+ * copied to the host).  mode: dense state vector, per-term light cones, factored light
  * cones, or AUTO (factored light cones when n > 30, else dense).  If keep != NULL
  * (dense mode only), the final states are returned in *keep for qsim_expect_grad. */
 int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
-                        const qsim_hamiltonian* H, int mode, int dtype, void* stream, double* out,
-                        qsim_state** keep);
+                        int params_on_device, const qsim_hamiltonian* H, int mode, int dtype, void* stream,
+                        double* out, qsim_state** keep);
+
+/* Per-term values (Sec. 1 and Sec. 3: <H> = sum_t coeff[t] <P_t>):
+ * out[b * n_terms + t] = <psi(theta_b)|P_t|psi(theta_b)> without the coefficient (1
+ * for identity terms), float64, host, [batch][n_terms].  params and params_on_device
+ * as in qsim_expect_circuit.  mode: QSIM_MODE_DENSE (the final states once, then one
+ * read-only measurement pass per term), QSIM_MODE_LIGHTCONE (each term on its
+ * canonical cone), QSIM_MODE_LIGHTCONE_FACTORED (Z-strings as products of disjoint
+ * pruned factors), or AUTO (factored cones when n > 30, else dense).  Errors as for
+ * qsim_expect_circuit. */
+int qsim_expect_terms(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch, int params_on_device,
+                      const qsim_hamiltonian* H, int mode, int dtype, void* stream, double* out);
 
 /* ---- gradient (Sec. 3: full gradient; here by the adjoint method) ------------------ */
 
-/* E[b] = <H> and grad[b*n_params + j] = d<H>/dtheta_j (float64, host) for b < batch.
- * saved: final states from qsim_expect_circuit(keep) with the same circuit/params, or
- * NULL to run the forward pass first.  A saved state is consumed (its amplitudes are
- * overwritten by the backward sweep) but must still be destroyed by the caller. */
-int qsim_expect_grad(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
+/* E[b] = <H> and grad[b*n_params + j] = d<H>/dtheta_j (float64, host) for b < batch;
+ * E may be NULL.  params and params_on_device as in qsim_expect_circuit.  saved: final
+ * states from qsim_expect_circuit(keep) with the same circuit/params, or NULL to run
+ * the forward pass first.  A saved state is consumed (its amplitudes are overwritten
+ * by the backward sweep) but must still be destroyed by the caller. */
+int qsim_expect_grad(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch, int params_on_device,
                      const qsim_hamiltonian* H, int dtype, void* stream, qsim_state* saved, double* E,
                      double* grad);
 
@@ -180,11 +216,13 @@ int qsim_expect_grad(qsim_ctx* ctx, const qsim_circuit* c, const double* params,
  * or QSIM_MODE_LIGHTCONE_FACTORED / QSIM_MODE_AUTO (Z-string terms split into
  * disjoint pruned factors, shared across terms).  Inside each cone the gradient is
  * taken by the adjoint method; per-cone parameter gradients are weighted by
- * d<H>/d<cone> and summed per parameter on the device in a fixed order.  params,
- * E and grad are host buffers owned by the caller; E may be NULL.  Errors as for
- * qsim_expect_circuit; QSIM_ETOOBIG when a cone exceeds the context's cone_cap. */
+ * d<H>/d<cone> and summed per parameter on the device in a fixed order.  params and
+ * params_on_device as in qsim_expect_circuit; E and grad are host buffers owned by
+ * the caller; E may be NULL.  Errors as for qsim_expect_circuit; QSIM_ETOOBIG when a
+ * cone exceeds the context's cone_cap. */
 int qsim_expect_grad_cones(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
-                           const qsim_hamiltonian* H, int mode, int dtype, void* stream, double* E, double* grad);
+                           int params_on_device, const qsim_hamiltonian* H, int mode, int dtype, void* stream,
+                           double* E, double* grad);
 
 /* ---- light cones (Sec. 4: causality-simplified contraction) ------------------------- */
 
@@ -202,6 +240,17 @@ int qsim_lightcone_sets(const qsim_circuit* c, const qsim_hamiltonian* H, int32_
  * index) triples; cap_triples bounds it. */
 int qsim_plan_dense(const qsim_circuit* c, const qsim_hamiltonian* H, int dtype, int64_t* info, int32_t* order,
                     int cap_triples);
+
+/* Passes that qsim_expect_circuit launches for (c, H) in dense mode on ctx (with
+ * keep != 0: the variant that stores the final state), as 8 int32 per pass:
+ * flags (as in qsim_timing_get), number of stages, index of the storing stage
+ * within the pass (-1: none), 1 if the loads go through an entry permutation,
+ * 1 if the stores go through an exit permutation, measurement column (-1: none),
+ * gradient probes, tile qubits m.  Plans come from ctx's cache (a host-only
+ * context, device -1, works without a GPU).  rec holds cap records; QSIM_ETOOBIG
+ * with *count = the number needed when cap is short. */
+int qsim_plan_passes(qsim_ctx* ctx, const qsim_circuit* c, const qsim_hamiltonian* H, int dtype, int keep,
+                     int32_t* rec, int cap, int* count);
 
 /* ---- measurement ------------------------------------------------------------------ */
 
@@ -229,7 +278,17 @@ int qsim_timing_get(qsim_ctx* ctx, double* ms, double* bytes, double* flops, int
  * pass kernels are reported, and calibrates HBM byte counters. */
 int qsim_copy_probe(qsim_ctx* ctx, uint64_t bytes, int reps, double* ms);
 
-/* ---- serving (continuous batching) ----------------------------------------------- */
+/* ---- serving (continuous batching) -----------------------------------------------
+ *
+ * The paper offers the library as an efficient backend for quantum machine
+ * learning (Sec. 1; Sec. 4 names faster backends as the direction of further
+ * work), where many objective evaluations (Sec. 1: expectation values, with
+ * their gradients for the classical optimiser) are requested at once.  These
+ * calls accept such requests from any thread and share the device between
+ * them: requests are admitted in arrival order while their state memory,
+ * (1 + want_grad) * 2^n * 8 bytes plus partial sums, fits the context's
+ * hbm_budget_bytes; every running request advances one pass per scheduler step
+ * in multi-request launches; results do not depend on what else is running. */
 
 typedef struct {
     const qsim_circuit* circuit;
@@ -245,8 +304,10 @@ typedef struct {
     uint64_t queued, running;
 } qsim_server_stats;
 
-/* Enqueue a request (deep copy).  EAGAIN when the queue is full, ETOOBIG when the
- * request alone exceeds the memory budget.  Thread-safe. */
+/* Enqueue a request (deep copy of the circuit, H and parameters; complex64 dense
+ * evaluation, with the adjoint gradient when want_grad).  *ticket identifies it.
+ * EAGAIN when the queue is full, ETOOBIG when the request alone exceeds the memory
+ * budget, EINVAL for an invalid circuit or H.  Thread-safe. */
 int qsim_submit(qsim_ctx* ctx, const qsim_request* req, uint64_t* ticket);
 /* QSIM_PENDING while running; QSIM_OK once done: E[0] and, if the request asked
  * for it, grad[n_params] are written and the ticket is consumed.  A failed or
@@ -258,8 +319,12 @@ int qsim_poll(qsim_ctx* ctx, uint64_t ticket, double* E, double* grad);
 int qsim_poll_timed(qsim_ctx* ctx, uint64_t ticket, double* E, double* grad, double* times);
 /* Monotonic clock in seconds used for the serving timestamps. */
 double qsim_clock(void);
-/* Cancel a queued or running request.  Thread-safe. */
+/* Cancel a queued or running request; its next qsim_poll returns QSIM_ECANCELED.
+ * ENOTFOUND for an unknown or consumed ticket.  Thread-safe. */
 int qsim_cancel(qsim_ctx* ctx, uint64_t ticket);
+/* Counters of the serving loop since the context was created (requests by
+ * outcome, scheduler steps and launches, state bytes in flight now and at peak,
+ * requests queued and running now).  Thread-safe. */
 int qsim_server_stats_get(qsim_ctx* ctx, qsim_server_stats* out);
 
 #ifdef __cplusplus

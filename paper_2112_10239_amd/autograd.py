@@ -22,26 +22,37 @@ def _stream_handle(t: torch.Tensor):
     return None
 
 
+def _params(theta: torch.Tensor):
+    """Parameters as the library takes them: a float64 device tensor stays on the
+    device (the library builds gate coefficients from it there); host tensors go
+    as float64 arrays."""
+    th = theta.detach().reshape(theta.shape[0], -1)
+    if th.is_cuda:
+        return th.to(torch.float64).contiguous()
+    return th.to(torch.float64).contiguous().numpy()
+
+
 class Expectation(torch.autograd.Function):
     """E[b] = <psi(theta_b)|H|psi(theta_b)> for theta of shape [B, P]."""
 
     @staticmethod
     def forward(ctx, theta: torch.Tensor, engine: "qsim.Context", circuit, hamiltonian):
-        th = theta.detach().to("cpu", torch.float64).contiguous().numpy().reshape(theta.shape[0], -1)
+        th = _params(theta)
         stream = _stream_handle(theta)
         E, state = engine.expect_circuit(circuit, hamiltonian, th, mode=qsim.MODE_DENSE, dtype=qsim.C64,
                                          stream=stream, keep=True)
-        ctx.engine, ctx.circuit, ctx.hamiltonian, ctx.state, ctx.theta_np = engine, circuit, hamiltonian, state, th
+        ctx.engine, ctx.circuit, ctx.hamiltonian, ctx.state, ctx.th = engine, circuit, hamiltonian, state, th
         ctx.stream = stream
-        return torch.as_tensor(np.asarray(E, dtype=np.float64), device=theta.device).to(theta.dtype)
+        return torch.as_tensor(np.asarray(E, dtype=np.float64).reshape(-1), device=theta.device).to(theta.dtype)
 
     @staticmethod
     def backward(ctx, grad_E: torch.Tensor):
-        _, g = ctx.engine.expect_grad(ctx.circuit, ctx.hamiltonian, ctx.theta_np, dtype=qsim.C64, stream=ctx.stream,
+        _, g = ctx.engine.expect_grad(ctx.circuit, ctx.hamiltonian, ctx.th, dtype=qsim.C64, stream=ctx.stream,
                                       saved=ctx.state, want_E=False)
         ctx.state.destroy()
         ctx.state = None
-        g = torch.as_tensor(np.asarray(g).reshape(ctx.theta_np.shape), device=grad_E.device, dtype=grad_E.dtype)
+        g = torch.as_tensor(np.asarray(g).reshape(tuple(ctx.th.shape)), device=grad_E.device, dtype=grad_E.dtype)
+        ctx.th = None
         return grad_E.reshape(-1, 1) * g, None, None, None
 
 
@@ -59,11 +70,11 @@ class ExpectationCones(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, theta: torch.Tensor, engine: "qsim.Context", circuit, hamiltonian, mode: int):
-        th = theta.detach().to("cpu", torch.float64).contiguous().numpy().reshape(theta.shape[0], -1)
+        th = _params(theta)
         stream = _stream_handle(theta)
         if theta.requires_grad:
             E, g = engine.expect_grad(circuit, hamiltonian, th, dtype=qsim.C64, stream=stream, mode=mode)
-            ctx.grad = np.asarray(g).reshape(th.shape)
+            ctx.grad = np.asarray(g).reshape(tuple(th.shape))
         else:
             E = engine.expect_circuit(circuit, hamiltonian, th, mode=mode, dtype=qsim.C64, stream=stream)
             ctx.grad = None

@@ -35,13 +35,16 @@ int flush(qsim_state* st, const std::vector<Term>* terms, double* out) {
   auto dp = get_dense_plan(ctx, st->queue, terms ? *terms : std::vector<Term>{}, st->dtype == QSIM_C128, st->fresh,
                            need_store, terms != nullptr, rc);
   if (!dp) return rc;
-  rc = run_dense(ctx, ctx->ws, *dp, st->queue, st->qparams.empty() ? nullptr : st->qparams.data(), st->batch,
-                 st->dtype == QSIM_C128, st->buf, nullptr, st->stream, out);
+  const ParamSrc ps = st->qdev ? ParamSrc((const double*)st->dparams.p, true)
+                              : ParamSrc(st->qparams.empty() ? nullptr : st->qparams.data(), false);
+  rc = run_dense(ctx, ctx->ws, *dp, st->queue, ps, st->batch, st->dtype == QSIM_C128, st->buf, nullptr, st->stream,
+                 out);
   if (rc) return rc;
   if (need_store) st->fresh = false;
   st->queue.gates.clear();
   st->queue.n_params = 0;
   st->qparams.clear();
+  st->qdev = false;
   return QSIM_OK;
 }
 
@@ -78,7 +81,7 @@ const char* qsim_last_error(qsim_ctx* ctx) {
   return ctx->err.c_str();
 }
 
-int qsim_init(const qsim_options* opt, qsim_ctx** out) {
+int qsim_init(qsim_ctx** out, const qsim_options* opt) {
   if (!out) return QSIM_EINVAL;
   *out = nullptr;
   qsim_ctx* ctx = new (std::nothrow) qsim_ctx();
@@ -87,6 +90,8 @@ int qsim_init(const qsim_options* opt, qsim_ctx** out) {
   if (ctx->opt.max_queue <= 0) ctx->opt.max_queue = 4096;
   if (ctx->opt.cone_cap <= 0) ctx->opt.cone_cap = 20;
   if (ctx->opt.hbm_budget_bytes == 0) ctx->opt.hbm_budget_bytes = 64ull << 30;
+  if (ctx->opt.max_inflight <= 0) ctx->opt.max_inflight = 3;
+  if (ctx->opt.max_inflight > 8) ctx->opt.max_inflight = 8;
   ctx->device = ctx->opt.device;
   if (ctx->device < 0) {  // host-only context: planning and a simulated serving loop
     ctx->mock = true;
@@ -164,11 +169,13 @@ int qsim_destroy_state(qsim_state* st) {
     (void)hipStreamSynchronize(st->stream);
   }
   if (st->owned && st->buf) (void)hipFree(st->buf);
+  st->dparams.release();
   delete st;
   return QSIM_OK;
 }
 
-int qsim_apply_layer(qsim_state* st, const qsim_gate* gates, int n_gates, const double* params, int n_params) {
+int qsim_apply_layer(qsim_state* st, const qsim_gate* gates, int n_gates, const double* params, int n_params,
+                     int params_on_device) {
   if (check_state(st)) return QSIM_EINVAL;
   qsim_ctx* ctx = st->ctx;
   if (n_gates < 0 || n_params < 0) return QSIM_EINVAL;
@@ -184,17 +191,42 @@ int qsim_apply_layer(qsim_state* st, const qsim_gate* gates, int n_gates, const 
   }
   std::lock_guard<std::mutex> g(ctx->api_mu);
   const int old = st->queue.n_params;
+  const int total = old + n_params;
+  const size_t B = (size_t)st->batch;
+  if (params_on_device || st->qdev) {
+    // the queue's parameters move to (or stay in) device memory: [batch][total]
+    HIP_TRY(hipSetDevice(ctx->device), "set device");
+    HIP_TRY(hipStreamSynchronize(st->stream), "stream sync");
+    DevBuf nb;
+    HIP_TRY(nb.ensure(std::max<size_t>(1, B * total) * sizeof(double)), "parameter buffer");
+    const size_t w = sizeof(double);
+    hipError_t e = hipSuccess;
+    if (old > 0)
+      e = st->qdev ? hipMemcpy2D(nb.p, total * w, st->dparams.p, old * w, old * w, B, hipMemcpyDeviceToDevice)
+                   : hipMemcpy2D(nb.p, total * w, st->qparams.data(), old * w, old * w, B, hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_params > 0 && params)
+      e = hipMemcpy2D((char*)nb.p + old * w, total * w, params, n_params * w, n_params * w, B,
+                      params_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      nb.release();
+      return hip_fail(ctx, e, "parameter copy");
+    }
+    st->dparams.release();
+    st->dparams = nb;
+    st->qparams.clear();
+    st->qdev = true;
+  } else {
+    std::vector<double> np(B * total);
+    for (size_t b = 0; b < B; ++b) {
+      for (int k = 0; k < old; ++k) np[b * total + k] = st->qparams[b * old + k];
+      for (int k = 0; k < n_params; ++k) np[b * total + old + k] = params[b * n_params + k];
+    }
+    st->qparams.swap(np);
+  }
   for (Gate x : layer.gates) {
     if (x.param >= 0) x.param += old;
     st->queue.gates.push_back(x);
   }
-  const int total = old + n_params;
-  std::vector<double> np((size_t)st->batch * total);
-  for (int b = 0; b < st->batch; ++b) {
-    for (int k = 0; k < old; ++k) np[(size_t)b * total + k] = st->qparams[(size_t)b * old + k];
-    for (int k = 0; k < n_params; ++k) np[(size_t)b * total + old + k] = params[(size_t)b * n_params + k];
-  }
-  st->qparams.swap(np);
   st->queue.n_params = total;
   return QSIM_OK;
 }
@@ -318,7 +350,7 @@ int qsim_state_device_ptr(qsim_state* st, void** ptr) {
   return QSIM_OK;
 }
 
-int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
+int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch, int params_on_device,
                         const qsim_hamiltonian* H, int mode, int dtype, void* stream, double* out, qsim_state** keep) {
   if (!ctx || !out || batch < 1 || !valid_dtype(dtype)) return QSIM_EINVAL;
   if (keep) *keep = nullptr;
@@ -345,8 +377,9 @@ int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* para
     auto dp = mode == QSIM_MODE_LIGHTCONE ? get_cone_plan(ctx, cd, terms, c128, rc)
                                           : get_factor_plan(ctx, cd, terms, c128, rc);
     if (!dp) return rc;
+    const ParamSrc ps(params, params_on_device != 0);
     for (int b = 0; b < batch; ++b) {
-      rc = run_cones(ctx, ctx->ws, *dp, cd, params ? params + (size_t)b * cd.n_params : nullptr, c128, st, out + b);
+      rc = run_cones(ctx, ctx->ws, *dp, cd, ps.row(b, cd.n_params), c128, st, out + b);
       if (rc) return rc;
     }
     return QSIM_OK;
@@ -366,7 +399,7 @@ int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* para
     HIP_TRY(ctx->psi.ensure(bytes), "state workspace");
     A = ctx->psi.p;
   }
-  rc = run_dense(ctx, ctx->ws, *dp, cd, params, batch, c128, A, nullptr, st, out);
+  rc = run_dense(ctx, ctx->ws, *dp, cd, ParamSrc(params, params_on_device != 0), batch, c128, A, nullptr, st, out);
   if (rc) {
     if (keep) (void)hipFree(A);
     return rc;
@@ -391,8 +424,75 @@ int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* para
   return QSIM_OK;
 }
 
+int qsim_expect_terms(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch, int params_on_device,
+                      const qsim_hamiltonian* H, int mode, int dtype, void* stream, double* out) {
+  if (!ctx || !out || batch < 1 || !valid_dtype(dtype)) return QSIM_EINVAL;
+  if (ctx->mock) return no_device(ctx);
+  CircuitDesc cd;
+  int rc = to_circuit(ctx, c, cd);
+  if (rc) return rc;
+  std::vector<Term> terms;
+  if ((rc = to_terms(ctx, H, cd.n, terms))) return rc;
+  if (cd.n_params > 0 && !params) {
+    set_error(ctx, "expect_terms: params missing");
+    return QSIM_EINVAL;
+  }
+  if (mode == QSIM_MODE_AUTO) mode = cd.n > 30 ? QSIM_MODE_LIGHTCONE_FACTORED : QSIM_MODE_DENSE;
+  if (mode < QSIM_MODE_DENSE || mode > QSIM_MODE_LIGHTCONE_FACTORED) return QSIM_EINVAL;
+  const int T = (int)terms.size();
+  if (T == 0) return QSIM_OK;
+  // every term with coefficient 1: the values are <P_t> themselves
+  std::vector<Term> unit = terms;
+  std::vector<int> live;  // non-identity terms, in order
+  for (int t = 0; t < T; ++t) {
+    unit[t].c = 1.0;
+    if (!terms[t].ops.empty()) live.push_back(t);
+  }
+  for (int b = 0; b < batch; ++b)
+    for (int t = 0; t < T; ++t) out[(size_t)b * T + t] = 1.0;  // identity terms
+  if (live.empty()) return QSIM_OK;
+  const int c128 = dtype == QSIM_C128;
+  const ParamSrc ps(params, params_on_device != 0);
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  hipStream_t st = pick_stream(ctx, stream);
+  if (mode == QSIM_MODE_LIGHTCONE || mode == QSIM_MODE_LIGHTCONE_FACTORED) {
+    // one factor product per term: the canonical cone (LIGHTCONE) or disjoint pruned factors
+    auto dp = get_factor_plan(ctx, cd, unit, c128, rc, false, mode == QSIM_MODE_LIGHTCONE_FACTORED);
+    if (!dp) return rc;
+    std::vector<double> vals(live.size());
+    for (int b = 0; b < batch; ++b) {
+      if ((rc = run_cones(ctx, ctx->ws, *dp, cd, ps.row(b, cd.n_params), c128, st, nullptr, vals.data()))) return rc;
+      for (size_t k = 0; k < live.size(); ++k) out[(size_t)b * T + live[k]] = vals[k];
+    }
+    return QSIM_OK;
+  }
+  if (cd.n > kMaxQubits) {
+    set_error(ctx, "dense mode supports at most 40 qubits");
+    return QSIM_ETOOBIG;
+  }
+  // the final states once, then one read-only measurement per term
+  auto fp = get_dense_plan(ctx, cd, {}, c128, true, true, false, rc);
+  if (!fp) return rc;
+  const size_t bytes = (size_t)batch * ((size_t)1 << cd.n) * amp_bytes(dtype);
+  HIP_TRY(ctx->psi.ensure(bytes), "state workspace");
+  void* A = ctx->psi.p;
+  if ((rc = run_dense(ctx, ctx->ws, *fp, cd, ps, batch, c128, A, nullptr, st, nullptr))) return rc;
+  CircuitDesc empty;
+  empty.n = cd.n;
+  std::vector<double> vals(batch);
+  for (int t : live) {
+    auto mp = get_dense_plan(ctx, empty, {unit[t]}, c128, false, false, true, rc);
+    if (!mp) return rc;
+    if ((rc = run_dense(ctx, ctx->ws, *mp, empty, ParamSrc(), batch, c128, A, nullptr, st, vals.data()))) return rc;
+    for (int b = 0; b < batch; ++b) out[(size_t)b * T + t] = vals[b];
+  }
+  return QSIM_OK;
+}
+
 int qsim_expect_grad_cones(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
-                           const qsim_hamiltonian* H, int mode, int dtype, void* stream, double* E, double* grad) {
+                           int params_on_device, const qsim_hamiltonian* H, int mode, int dtype, void* stream,
+                           double* E, double* grad) {
   if (!ctx || !grad || batch < 1 || !valid_dtype(dtype)) return QSIM_EINVAL;
   if (mode == QSIM_MODE_AUTO) mode = QSIM_MODE_LIGHTCONE_FACTORED;
   if (mode != QSIM_MODE_LIGHTCONE && mode != QSIM_MODE_LIGHTCONE_FACTORED) {
@@ -415,18 +515,18 @@ int qsim_expect_grad_cones(qsim_ctx* ctx, const qsim_circuit* c, const double* p
   hipStream_t st = pick_stream(ctx, stream);
   auto dp = get_factor_plan(ctx, cd, terms, c128, rc, true, mode == QSIM_MODE_LIGHTCONE_FACTORED);
   if (!dp) return rc;
+  const ParamSrc ps(params, params_on_device != 0);
   for (int b = 0; b < batch; ++b) {
     double e = 0;
-    rc = run_cone_grad(ctx, ctx->ws, *dp, cd, params ? params + (size_t)b * cd.n_params : nullptr, c128, st, &e,
-                       grad + (size_t)b * cd.n_params);
+    rc = run_cone_grad(ctx, ctx->ws, *dp, cd, ps.row(b, cd.n_params), c128, st, &e, grad + (size_t)b * cd.n_params);
     if (rc) return rc;
     if (E) E[b] = e;
   }
   return QSIM_OK;
 }
 
-int qsim_expect_grad(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch, const qsim_hamiltonian* H,
-                     int dtype, void* stream, qsim_state* saved, double* E, double* grad) {
+int qsim_expect_grad(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch, int params_on_device,
+                     const qsim_hamiltonian* H, int dtype, void* stream, qsim_state* saved, double* E, double* grad) {
   if (!ctx || batch < 1 || !valid_dtype(dtype) || !grad) return QSIM_EINVAL;
   if (ctx->mock) return no_device(ctx);
   CircuitDesc cd;
@@ -459,7 +559,7 @@ int qsim_expect_grad(qsim_ctx* ctx, const qsim_circuit* c, const double* params,
       empty.n = cd.n;
       auto mp = get_dense_plan(ctx, empty, terms, c128, false, false, true, rc);
       if (!mp) return rc;
-      if ((rc = run_dense(ctx, ctx->ws, *mp, empty, nullptr, batch, c128, A, nullptr, st, E))) return rc;
+      if ((rc = run_dense(ctx, ctx->ws, *mp, empty, ParamSrc(), batch, c128, A, nullptr, st, E))) return rc;
     }
   } else {
     auto fp = get_dense_plan(ctx, cd, terms, c128, true, true, true, rc);
@@ -467,13 +567,16 @@ int qsim_expect_grad(qsim_ctx* ctx, const qsim_circuit* c, const double* params,
     HIP_TRY(ctx->psi.ensure(bytes), "state workspace");
     A = ctx->psi.p;
     std::vector<double> e_tmp(batch);
-    if ((rc = run_dense(ctx, ctx->ws, *fp, cd, params, batch, c128, A, nullptr, st, E ? E : e_tmp.data()))) return rc;
+    if ((rc = run_dense(ctx, ctx->ws, *fp, cd, ParamSrc(params, params_on_device != 0), batch, c128, A, nullptr, st,
+                        E ? E : e_tmp.data())))
+      return rc;
   }
   std::shared_ptr<DevPlan> hp;
   auto ap = get_grad_plans(ctx, cd, terms, c128, hp, rc);
   if (!ap) return rc;
   HIP_TRY(ctx->ws.lambda.ensure(bytes), "lambda workspace");
-  return run_grad(ctx, ctx->ws, *hp, *ap, cd, params, batch, c128, A, ctx->ws.lambda.p, st, grad);
+  return run_grad(ctx, ctx->ws, *hp, *ap, cd, ParamSrc(params, params_on_device != 0), batch, c128, A,
+                  ctx->ws.lambda.p, st, grad);
 }
 
 int qsim_timing_enable(qsim_ctx* ctx, int on) {
@@ -566,7 +669,8 @@ int qsim_plan_dense(const qsim_circuit* c, const qsim_hamiltonian* H, int dtype,
   forward_pgates(cd, true, pg, plan.slots);
   double cst = 0;
   term_pgates(terms, false, meas, cst);
-  PlanOptions o = fwd_options(dtype == QSIM_C128);
+  const qsim_options defaults{};
+  PlanOptions o = fwd_options(defaults, dtype == QSIM_C128);
   std::string err;
   if (plan_forward(cd.n, pg, meas, o, plan, err)) return QSIM_EINVAL;
   info[0] = (int64_t)plan.passes.size();
@@ -577,6 +681,42 @@ int qsim_plan_dense(const qsim_circuit* c, const qsim_hamiltonian* H, int dtype,
     if ((int)plan.order.size() / 4 > cap_entries) return QSIM_ETOOBIG;
     std::memcpy(order, plan.order.data(), plan.order.size() * sizeof(int32_t));
   }
+  return QSIM_OK;
+}
+
+int qsim_plan_passes(qsim_ctx* ctx, const qsim_circuit* c, const qsim_hamiltonian* H, int dtype, int keep,
+                     int32_t* rec, int cap, int* count) {
+  if (!ctx || !H || !count || !valid_dtype(dtype) || (cap > 0 && !rec)) return QSIM_EINVAL;
+  *count = 0;
+  CircuitDesc cd;
+  int rc = to_circuit(ctx, c, cd);
+  if (rc) return rc;
+  std::vector<Term> terms;
+  if ((rc = to_terms(ctx, H, cd.n, terms))) return rc;
+  if (cd.n > kMaxQubits) return QSIM_ETOOBIG;
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  if (!ctx->mock) HIP_TRY(hipSetDevice(ctx->device), "set device");
+  auto dp = get_dense_plan(ctx, cd, terms, dtype == QSIM_C128, true, keep != 0, true, rc);
+  if (!dp) return rc;
+  const Plan& P = dp->plan;
+  const int np = (int)P.passes.size();
+  if (np > cap) {
+    *count = np;
+    return QSIM_ETOOBIG;
+  }
+  for (int p = 0; p < np; ++p) {
+    const PassDesc& pd = P.passes[p];
+    int32_t* o = rec + 8 * p;
+    o[0] = pd.flags;
+    o[1] = pd.stage_end - pd.stage_begin;
+    o[2] = pd.store_stage >= 0 ? pd.store_stage - pd.stage_begin : -1;
+    o[3] = pd.entry_perm;
+    o[4] = pd.exit_perm;
+    o[5] = pd.meas_index;
+    o[6] = pd.grad_count;
+    o[7] = pd.m;
+  }
+  *count = np;
   return QSIM_OK;
 }
 

@@ -107,26 +107,35 @@ static double pass_flops_per_amp(const Plan& P, const PassDesc& pd) {
   return f;
 }
 
-PlanOptions fwd_options(int c128) {
+// Option value: the context's field when set (non-zero), else the environment
+// variable of the same meaning (measurement sweeps), else the default.
+static int opt_int(int field, const char* env, int dflt) { return field != 0 ? field : env_int(env, dflt); }
+
+static bool opt_off(const qsim_options& co, int bit, const char* env, bool env_default_on) {
+  if (co.disable & bit) return true;
+  return env_int(env, env_default_on ? 1 : 0) == 0;
+}
+
+PlanOptions fwd_options(const qsim_options& co, int c128) {
   // 2^13-amplitude tiles with 16 per thread: two 512-thread workgroups per CU
   // (64 KiB of LDS each), so one workgroup's exchanges and barriers overlap the
   // other's arithmetic (measured faster than one 2^14 tile with 32 per thread).
-  static const int r64 = std::min(5, std::max(3, env_int("QSIM_FWD_R", 4)));
-  static const int m64 = std::min(14, std::max(12, env_int("QSIM_FWD_M", 13)));
+  const int r64 = std::min(5, std::max(3, opt_int(co.register_bits, "QSIM_FWD_R", 4)));
+  const int m64 = std::min(14, std::max(12, opt_int(co.tile_qubits, "QSIM_FWD_M", 13)));
   // four always-local low bits: 128-byte contiguous segments per access (a full
   // cache line) while leaving more local positions for gates (23 passes instead
   // of 33 at six for the n=30 workload; measured faster)
-  static const int clow = std::min(6, std::max(3, env_int("QSIM_FWD_CLOW", 4)));
-  static const bool absorb = env_int("QSIM_ABSORB", 1) != 0;
+  const int clow = std::min(6, std::max(3, opt_int(co.coalesce_bits, "QSIM_FWD_CLOW", 4)));
+  const bool absorb = !opt_off(co, QSIM_OFF_ABSORB, "QSIM_ABSORB", true);
   // uncontrolled rotations on a stage's register bits as one factored op (two
   // multiply-adds per amplitude and bit plus one diagonal table) in float plans
-  static const bool factored = env_int("QSIM_FACTORED", 1) != 0;
+  const bool factored = !opt_off(co, QSIM_OFF_FACTORED, "QSIM_FACTORED", true);
   // lowest local bit that load/store stages may hold in registers (-1: the
   // always-local low bits stay lane bits, so every access covers whole segments;
   // default 0: a load/store stage may hold them too, which saves the extra stage
   // a pass would otherwise need to store, at the price of accesses that cover
   // each segment over several instructions; measured slightly faster)
-  static const int io_lo = std::min(6, std::max(-1, env_int("QSIM_IO_LO", 0)));
+  const int io_lo = (co.disable & QSIM_OFF_IO_REGS) ? -1 : std::min(6, std::max(-1, env_int("QSIM_IO_LO", 0)));
   PlanOptions o;
   o.m_max = c128 ? 13 : m64;
   o.r = c128 ? 4 : std::max(r64, o.m_max - 10);  // at most 1024 threads per workgroup
@@ -135,32 +144,32 @@ PlanOptions fwd_options(int c128) {
   o.factored = factored && !c128 && o.r <= 4;
   o.io_lo = io_lo;
   // permutation folds and the product-state start (with factored; default on)
-  static const int folds = env_int("QSIM_FOLDS", 7);
-  o.entry_perm = (folds & 1) != 0;
-  o.exit_perm = (folds & 2) != 0;
-  o.init_factors = (folds & 4) != 0;
+  const int folds = env_int("QSIM_FOLDS", 7);
+  o.entry_perm = (folds & 1) != 0 && !(co.disable & QSIM_OFF_ENTRY);
+  o.exit_perm = (folds & 2) != 0 && !(co.disable & QSIM_OFF_EXIT);
+  o.init_factors = (folds & 4) != 0 && !(co.disable & QSIM_OFF_PRODUCT);
   return o;
 }
 
-PlanOptions cone_options(int c128) {
-  PlanOptions o = fwd_options(c128);
+PlanOptions cone_options(const qsim_options& co, int c128) {
+  PlanOptions o = fwd_options(co, c128);
   o.r = 4;  // the cone kernel keeps 16 amplitudes per thread
   o.factored = false;
   o.io_lo = -1;
   return o;
 }
 
-PlanOptions dual_options(int c128) {
-  static const bool absorb = env_int("QSIM_ABSORB", 1) != 0;
+PlanOptions dual_options(const qsim_options& co, int c128) {
   PlanOptions o;
-  o.absorb = absorb;
+  o.absorb = !opt_off(co, QSIM_OFF_ABSORB, "QSIM_ABSORB", true);
   o.m_max = c128 ? 12 : 13;
   o.r = c128 ? 3 : 4;
-  static const int clow = std::min(6, std::max(3, env_int("QSIM_DUAL_CLOW", 6)));
-  o.c_low = clow;
+  o.c_low = std::min(6, std::max(3, opt_int(co.dual_coalesce_bits, "QSIM_DUAL_CLOW", 6)));
   o.fuse = false;
   return o;
 }
+
+bool prefetch_on(const qsim_options& co) { return !opt_off(co, QSIM_OFF_PREFETCH, "QSIM_FWD_PF", true); }
 
 DevPlan::~DevPlan() {
   (void)hipFree(d_passes);
@@ -170,6 +179,8 @@ DevPlan::~DevPlan() {
   (void)hipFree(d_order);
   (void)hipFree(d_poff);
   (void)hipFree(d_pslots);
+  (void)hipFree(d_cslots);
+  (void)hipFree(d_csrcs);
   (void)hipFree(d_toff);
   (void)hipFree(d_tfac);
   (void)hipFree(d_tcoef);
@@ -193,6 +204,13 @@ hipError_t DevPlan::upload(bool mock) {
   if ((e = upload_vec(plan.passes, &d_passes)) != hipSuccess) return e;
   if ((e = upload_vec(plan.stages, &d_stages)) != hipSuccess) return e;
   if ((e = upload_vec(plan.ops, &d_ops)) != hipSuccess) return e;
+  {
+    std::vector<CoefSlot> cs;
+    std::vector<int32_t> srcs;
+    coef_slot_table(plan.slots, cs, srcs);
+    if ((e = upload_vec(cs, &d_cslots)) != hipSuccess) return e;
+    if ((e = upload_vec(srcs, &d_csrcs)) != hipSuccess) return e;
+  }
   if (!cones.empty()) {
     if ((e = upload_vec(cones, &d_cones)) != hipSuccess) return e;
     if ((e = upload_vec(order, &d_order)) != hipSuccess) return e;
@@ -313,7 +331,7 @@ static std::shared_ptr<DevPlan> gate_plan(qsim_ctx* ctx, const CircuitDesc& c, i
   auto dp = std::make_shared<DevPlan>();
   std::vector<PGate> pg;
   forward_pgates(c, true, pg, dp->plan.slots);
-  PlanOptions o = fwd_options(c128);
+  PlanOptions o = fwd_options(ctx->opt, c128);
   o.init = init;
   o.store_final = store_final;
   std::string err;
@@ -350,7 +368,7 @@ int host_forward_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Ter
   out = Plan();
   std::vector<PGate> pg;
   forward_pgates(c, true, pg, out.slots);
-  PlanOptions o = fwd_options(0);
+  PlanOptions o = fwd_options(ctx->opt, 0);
   o.store_final = store_final;
   std::string err;
   if (plan_forward(c.n, pg, meas, o, out, err)) {
@@ -373,7 +391,7 @@ int host_happly_plan(qsim_ctx* ctx, int n, const std::vector<Term>& terms, Plan&
   }
   out = Plan();
   std::string err;
-  if (plan_happly(n, ht, dual_options(0), out, err)) {
+  if (plan_happly(n, ht, dual_options(ctx->opt, 0), out, err)) {
     set_error(ctx, err);
     return QSIM_EINVAL;
   }
@@ -410,7 +428,7 @@ std::shared_ptr<DevPlan> get_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, con
   auto dp = std::make_shared<DevPlan>();
   std::vector<PGate> pg;
   forward_pgates(c, true, pg, dp->plan.slots);
-  PlanOptions o = fwd_options(c128);
+  PlanOptions o = fwd_options(ctx->opt, c128);
   o.init = init;
   o.store_final = store_final;
   std::string err;
@@ -432,7 +450,7 @@ std::shared_ptr<DevPlan> get_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, con
 std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
                                         int c128, std::shared_ptr<DevPlan>& happly, int& rc) {
   rc = QSIM_OK;
-  const PlanOptions o = dual_options(c128);
+  const PlanOptions o = dual_options(ctx->opt, c128);
   // lambda = H psi
   {
     CircuitDesc shape;
@@ -471,7 +489,7 @@ std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, con
 
 std::shared_ptr<DevPlan> get_adjoint_plan(qsim_ctx* ctx, const CircuitDesc& c, int c128, int& rc) {
   rc = QSIM_OK;
-  const PlanOptions o = dual_options(c128);
+  const PlanOptions o = dual_options(ctx->opt, c128);
   const uint64_t key = structure_hash(c, {}, 0x200 | c128);
   if (auto p = cache_get(ctx, key)) return p;
   auto dp = std::make_shared<DevPlan>();
@@ -493,8 +511,8 @@ std::shared_ptr<DevPlan> get_adjoint_plan(qsim_ctx* ctx, const CircuitDesc& c, i
   return dp;
 }
 
-PlanOptions cone_grad_options(int c128) {
-  PlanOptions o = dual_options(c128);
+PlanOptions cone_grad_options(const qsim_options& co, int c128) {
+  PlanOptions o = dual_options(co, c128);
   o.r = 4;  // the cone kernel keeps 16 amplitudes per thread and state
   return o;
 }
@@ -511,8 +529,8 @@ struct ConePacker {
   std::vector<int> relabel;
   // shared coefficient table: (kind, inverse, source gates) -> slot
   std::map<std::tuple<int, bool, std::vector<int>>, int> slot_id;
-  ConePacker(DevPlan& d, const CircuitDesc& cc, int c128, int cap_, bool grad_ = false)
-      : dp(d), c(cc), base(grad_ ? cone_grad_options(c128) : cone_options(c128)), cap(cap_), grad(grad_),
+  ConePacker(DevPlan& d, const CircuitDesc& cc, const qsim_options& co, int c128, int cap_, bool grad_ = false)
+      : dp(d), c(cc), base(grad_ ? cone_grad_options(co, c128) : cone_options(co, c128)), cap(cap_), grad(grad_),
         relabel(cc.n, -1) {}
 
   // Appends a sub-plan's passes, stages and ops to the packed plan; its
@@ -652,7 +670,7 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
   const uint64_t key = structure_hash(c, terms, 0x400 | c128);
   if (auto p = cache_get(ctx, key)) return p;
   auto dp = std::make_shared<DevPlan>();
-  ConePacker pk(*dp, c, c128, ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20);
+  ConePacker pk(*dp, c, ctx->opt, c128, ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20);
   for (const Term& t : terms) {
     if (t.ops.empty()) {
       dp->plan.const_term += t.c;
@@ -682,7 +700,7 @@ std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, co
   auto dp = std::make_shared<DevPlan>();
   dp->factored = true;
   dp->cone_grad = grad;
-  ConePacker pk(*dp, c, c128, ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20, grad);
+  ConePacker pk(*dp, c, ctx->opt, c128, ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20, grad);
   const std::vector<char> drop = trailing_diagonal(c);
   std::map<std::vector<int>, int> factor_id;  // (pruned flag, qubit*4 + letter ...) -> cone
   auto factor = [&](const Term& obs, bool pruned, std::string& err, int& id) {
@@ -773,15 +791,41 @@ std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, co
 // runs
 // ---------------------------------------------------------------------------
 
-static int stage_coefficients(qsim_ctx* ctx, Workspace& ws, const CircuitDesc& c, const std::vector<PGate>& slots,
-                              const double* params, int rows, int c128, hipStream_t st, int64_t& crs) {
+// Coefficient rows of a plan's slots: built on the host from host parameters and
+// uploaded, or built on the device from device parameters (the circuit's gate
+// table is uploaded when it differs from the last one).
+static int stage_coefficients(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c,
+                              const ParamSrc& params, int rows, int c128, hipStream_t st, int64_t& crs) {
+  const std::vector<PGate>& slots = dp.plan.slots;
   const size_t scal = c128 ? 8 : 4;
   crs = (int64_t)std::max<size_t>(1, slots.size()) * 8;
   const size_t bytes = (size_t)rows * crs * scal;
-  HIP_TRY(ws.h_coef.ensure(bytes), "pinned coefficient buffer");
   HIP_TRY(ws.coef.ensure(bytes), "coefficient buffer");
-  if (c128) build_coefficients<double>(c, slots, params, rows, crs, (double*)ws.h_coef.p);
-  else build_coefficients<float>(c, slots, params, rows, crs, (float*)ws.h_coef.p);
+  if (params.dev) {
+    if (slots.empty()) return QSIM_OK;
+    std::vector<CoefGate> gt;
+    coef_gate_table(c, gt);
+    const size_t gbytes = std::max<size_t>(1, gt.size()) * sizeof(CoefGate);
+    const bool same = ws.gates.p && ws.last_gates.size() == gt.size() &&
+                      (gt.empty() || std::memcmp(ws.last_gates.data(), gt.data(), gt.size() * sizeof(CoefGate)) == 0);
+    if (!same) {
+      HIP_TRY(ws.gates.ensure(gbytes), "gate table");
+      HIP_TRY(ws.h_gates.ensure(gbytes), "pinned gate table");
+      if (!gt.empty()) {
+        std::memcpy(ws.h_gates.p, gt.data(), gt.size() * sizeof(CoefGate));
+        HIP_TRY(hipMemcpyAsync(ws.gates.p, ws.h_gates.p, gt.size() * sizeof(CoefGate), hipMemcpyHostToDevice, st),
+                "gate table upload");
+      }
+      ws.last_gates.swap(gt);
+    }
+    HIP_TRY(launch_build_coef(dp.d_cslots, (int)slots.size(), dp.d_csrcs, (const CoefGate*)ws.gates.p, params.p,
+                              c.n_params, rows, ws.coef.p, crs, c128, st),
+            "coefficient build");
+    return QSIM_OK;
+  }
+  HIP_TRY(ws.h_coef.ensure(bytes), "pinned coefficient buffer");
+  if (c128) build_coefficients<double>(c, slots, params.p, rows, crs, (double*)ws.h_coef.p);
+  else build_coefficients<float>(c, slots, params.p, rows, crs, (float*)ws.h_coef.p);
   HIP_TRY(hipMemcpyAsync(ws.coef.p, ws.h_coef.p, bytes, hipMemcpyHostToDevice, st), "coefficient upload");
   return QSIM_OK;
 }
@@ -795,11 +839,11 @@ static int fetch_out(qsim_ctx* ctx, Workspace& ws, size_t count, hipStream_t st,
   return QSIM_OK;
 }
 
-int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params, int rows,
+int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params, int rows,
               int c128, void* A, void* B, hipStream_t st, double* out_host) {
   const Plan& P = dp.plan;
   int64_t crs = 8;
-  int rc = stage_coefficients(ctx, ws, c, P.slots, params, rows, c128, st, crs);
+  int rc = stage_coefficients(ctx, ws, dp, c, params, rows, c128, st, crs);
   if (rc) return rc;
   const int64_t tiles = 1ll << (P.n - P.m);
   if (P.n_meas > 0) HIP_TRY(ws.meas.ensure((size_t)rows * P.n_meas * tiles * sizeof(double)), "partials buffer");
@@ -821,6 +865,7 @@ int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
     L.rows = rows;
     L.c128 = c128;
     L.dual = 0;
+    L.prefetch = prefetch_on(ctx->opt);
     const int ti = timing_begin(ctx, st, pass_bytes(P.passes[p], rows, c128), P.passes[p].flags, 0,
                                 pass_flops_per_amp(P, P.passes[p]) * (double)rows * (double)(1ull << P.n));
     HIP_TRY(launch_pass(L, st), "pass launch");
@@ -845,11 +890,11 @@ int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
 }
 
 int run_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& hp, const DevPlan& ap, const CircuitDesc& c,
-             const double* params, int rows, int c128, void* A, void* B, hipStream_t st, double* grad_host) {
+             const ParamSrc& params, int rows, int c128, void* A, void* B, hipStream_t st, double* grad_host) {
   const Plan& H = hp.plan;
   const Plan& P = ap.plan;
   int64_t crs = 8;
-  int rc = stage_coefficients(ctx, ws, c, P.slots, params, rows, c128, st, crs);
+  int rc = stage_coefficients(ctx, ws, ap, c, params, rows, c128, st, crs);
   if (rc) return rc;
   auto mk = [&](const DevPlan& d, size_t p) {
     PassLaunch L;
@@ -869,6 +914,7 @@ int run_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& hp, const DevPlan& ap,
     L.rows = rows;
     L.c128 = c128;
     L.dual = 1;
+    L.prefetch = 0;
     return L;
   };
   const int64_t tiles = 1ll << (P.n - P.m);
@@ -923,15 +969,15 @@ int run_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& hp, const DevPlan& ap,
   return QSIM_OK;
 }
 
-int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params, int c128,
-              hipStream_t st, double* out_host) {
+int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params, int c128,
+              hipStream_t st, double* out_host, double* terms_host) {
   const Plan& P = dp.plan;
   if (dp.cones.empty()) {
-    *out_host = P.const_term;
+    if (out_host) *out_host = P.const_term;
     return QSIM_OK;
   }
   int64_t crs = 8;
-  int rc = stage_coefficients(ctx, ws, c, P.slots, params, 1, c128, st, crs);
+  int rc = stage_coefficients(ctx, ws, dp, c, params, 1, c128, st, crs);
   if (rc) return rc;
   const size_t amp = c128 ? 16 : 8;
   if (dp.scratch_amps > 0) HIP_TRY(ws.scratch.ensure((size_t)dp.scratch_amps * amp), "cone scratch");
@@ -965,6 +1011,12 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
     HIP_TRY(launch_term_products((const double*)ws.meas.p, dp.d_toff, dp.d_tfac, dp.d_tcoef, T,
                                  (double*)ws.slot_total.p, st),
             "term products");
+    if (terms_host) {
+      HIP_TRY(ws.out.ensure(std::max(1, T) * sizeof(double)), "result buffer");
+      HIP_TRY(hipMemcpyAsync(ws.out.p, ws.slot_total.p, T * sizeof(double), hipMemcpyDeviceToDevice, st),
+              "term values copy");
+      return fetch_out(ctx, ws, T, st, terms_host);
+    }
     HIP_TRY(launch_reduce_rows((const double*)ws.slot_total.p, 1, T, P.const_term, (double*)ws.out.p, st),
             "term reduce");
   } else {
@@ -974,7 +1026,7 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
   return fetch_out(ctx, ws, 1, st, out_host);
 }
 
-int run_cone_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params,
+int run_cone_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params,
                   int c128, hipStream_t st, double* E_host, double* grad_host) {
   const Plan& P = dp.plan;
   const int np = c.n_params, ns = P.n_gslots;
@@ -985,7 +1037,7 @@ int run_cone_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const Circuit
     return QSIM_OK;
   }
   int64_t crs = 8;
-  int rc = stage_coefficients(ctx, ws, c, P.slots, params, 1, c128, st, crs);
+  int rc = stage_coefficients(ctx, ws, dp, c, params, 1, c128, st, crs);
   if (rc) return rc;
   const size_t amp = c128 ? 16 : 8;
   HIP_TRY(ws.scratch.ensure((size_t)dp.scratch_amps * amp), "cone scratch");

@@ -77,6 +77,9 @@ struct DevPlan {
   // gradient scatter (CSR parameter -> gradient slots)
   int32_t* d_poff = nullptr;
   int32_t* d_pslots = nullptr;
+  // coefficient slots for rows built on the device (parameters in device memory)
+  CoefSlot* d_cslots = nullptr;
+  int32_t* d_csrcs = nullptr;
   // factored light cones: term t = t_coef[t] * prod of cone values t_fac[t_off[t] .. t_off[t+1])
   bool factored = false;
   std::vector<int32_t> t_off, t_fac;
@@ -95,9 +98,13 @@ struct DevPlan {
 };
 
 struct Workspace {
-  DevBuf coef, meas, grad, slot_total, out, scratch, lambda, weights, table, dens;
-  HostBuf h_coef, h_out;
+  DevBuf coef, meas, grad, slot_total, out, scratch, lambda, weights, table, dens, gates;
+  HostBuf h_coef, h_out, h_gates;
+  std::vector<CoefGate> last_gates;  // content of 'gates' (device gate table)
   void release() {
+    gates.release();
+    h_gates.release();
+    last_gates.clear();
     coef.release();
     meas.release();
     grad.release();
@@ -150,7 +157,9 @@ struct qsim_state {
   bool fresh = true;      // content is |0...0> but not yet written
   hipStream_t stream = nullptr;
   qsim::CircuitDesc queue;          // gates not yet applied
-  std::vector<double> qparams;      // [batch][queue.n_params]
+  std::vector<double> qparams;      // [batch][queue.n_params] (host parameters)
+  bool qdev = false;                // parameters of the queue are in dparams (device) instead
+  qsim::DevBuf dparams;             // [batch][queue.n_params] float64 in device memory
 };
 
 namespace qsim {
@@ -182,15 +191,27 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
 std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
                                          int c128, int& rc, bool grad = false, bool split = true);
 
+// Where a call's parameters are: float64 rows [rows][n_params] in host memory,
+// or in device memory (coefficient rows are then built on the device).
+struct ParamSrc {
+  const double* p = nullptr;
+  bool dev = false;
+  ParamSrc() = default;
+  ParamSrc(const double* p_, bool dev_) : p(p_), dev(dev_) {}
+  ParamSrc row(int b, int n_params) const { return ParamSrc(p ? p + (size_t)b * n_params : nullptr, dev); }
+};
+
 // Run a dense plan on states A (and B) with 'rows' rows; coefficients from params.
-int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params, int rows,
+int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params, int rows,
               int c128, void* A, void* B, hipStream_t st, double* out_host);
 int run_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& hp, const DevPlan& ap, const CircuitDesc& c,
-             const double* params, int rows, int c128, void* A, void* B, hipStream_t st, double* grad_host);
-int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params, int c128,
-              hipStream_t st, double* out_host);
+             const ParamSrc& params, int rows, int c128, void* A, void* B, hipStream_t st, double* grad_host);
+// One cone launch; out_host receives <H> (terms_host == nullptr) or, for a
+// factored plan, the value of every non-identity term (terms_host[T']).
+int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params, int c128,
+              hipStream_t st, double* out_host, double* terms_host = nullptr);
 // <H> and its gradient from a gradient cone plan (one parameter row).
-int run_cone_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const double* params,
+int run_cone_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params,
                   int c128, hipStream_t st, double* E_host, double* grad_host);
 
 // Launch bracketing for qsim_timing_*: returns the record index or -1.
@@ -198,9 +219,10 @@ int timing_begin(qsim_ctx* ctx, hipStream_t st, double bytes, int flags, int kin
 void timing_end(qsim_ctx* ctx, int idx, hipStream_t st);
 void timing_collect(qsim_ctx* ctx);  // after a stream sync
 
-// Tile options per state precision and kernel kind.
-PlanOptions fwd_options(int c128);
-PlanOptions dual_options(int c128);
-PlanOptions cone_options(int c128);
+// Tile options per state precision and kernel kind, from a context's options.
+PlanOptions fwd_options(const qsim_options& co, int c128);
+PlanOptions dual_options(const qsim_options& co, int c128);
+PlanOptions cone_options(const qsim_options& co, int c128);
+bool prefetch_on(const qsim_options& co);
 
 }  // namespace qsim

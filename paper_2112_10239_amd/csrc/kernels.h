@@ -26,6 +26,7 @@ struct PassLaunch {
   int rows;
   int c128;                 // 0: complex64, 1: complex128
   int dual;                 // 0: psi only, 1: psi and lambda
+  int prefetch = 1;         // next-tile register prefetch where the variant has one
 };
 
 hipError_t launch_pass(const PassLaunch& L, hipStream_t stream);
@@ -90,6 +91,14 @@ struct DensityLaunch {
   int c128;
 };
 hipError_t launch_density(const DensityLaunch& L, hipStream_t stream);
+
+// Coefficient rows [rows][row_stride] (scalars of the state's precision) built on
+// the device: slot s of row b from the slot table and the gates, with parameters
+// theta[b * theta_stride + param] (device float64; may be null without
+// parameterised gates).
+hipError_t launch_build_coef(const CoefSlot* slots, int nslots, const int32_t* srcs, const CoefGate* gates,
+                             const double* theta, int64_t theta_stride, int rows, void* out, int64_t row_stride,
+                             int c128, hipStream_t stream);
 
 // Plain copy of n16 16-byte words (reference HBM stream).
 hipError_t launch_copy(const void* src, void* dst, uint64_t n16, hipStream_t stream);

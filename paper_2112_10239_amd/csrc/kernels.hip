@@ -923,11 +923,13 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
       }
     }
     if (last_utab) utab(OPS + o_end);
-    // A one-stage pass whose loads or stores go through a permutation stores to
-    // addresses other waves load from, with no exchange barrier in between: every
-    // wave's loads must be complete before any wave stores.
-    const bool cross = s0 + 1 == s1 && (P->entry_perm || P->exit_perm);
-    if (cross && (TAIL || s == sst)) {
+    // A pass that stores in its first stage (no exchange barrier between the
+    // loads and the stores) and whose loads or stores go through a permutation
+    // stores to addresses that other waves load from: every wave's loads must be
+    // complete before any wave stores.  Later stages (measurements) may follow.
+    // The TAIL variant stores after the last stage, which is then the first.
+    const bool cross = sst == s0 && (P->entry_perm || P->exit_perm);
+    if (cross && s == s0) {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       lds_sync();
     }
@@ -1335,16 +1337,6 @@ int device_cus() {
   return cus;
 }
 
-// QSIM_FWD_PF=0 turns off the next-tile prefetch of the 32-register forward
-// kernel (a tuning knob for A/B measurements; default on).
-bool fwd_prefetch() {
-  static const bool on = [] {
-    const char* v = std::getenv("QSIM_FWD_PF");
-    return !v || std::atoi(v) != 0;
-  }();
-  return on;
-}
-
 // Workgroups of a kernel resident on one CU at once (occupancy query; at least 1).
 template <class K>
 int resident_per_cu(K kernel, int threads, size_t lds) {
@@ -1388,7 +1380,7 @@ hipError_t launch_pass_r(const PassLaunch& L, hipStream_t stream) {
       if constexpr (!DUAL && sizeof(T) == 4) {
         // 8 amplitudes per thread leave room for a register prefetch of the next tile
         const PassDesc& p = *L.h_pass;
-        if (fwd_prefetch() && p.m - 3 >= 6 && (p.flags & PF_STORE_A) && p.store_stage == p.stage_end - 1)
+        if (L.prefetch && p.m - 3 >= 6 && (p.flags & PF_STORE_A) && p.store_stage == p.stage_end - 1)
           return launch_pass_t<T, 3, false, true, true>(L, stream);
       }
       return launch_pass_t<T, 3, DUAL, false>(L, stream);
@@ -1398,7 +1390,7 @@ hipError_t launch_pass_r(const PassLaunch& L, hipStream_t stream) {
     case 5:
       if constexpr (DUAL || sizeof(T) == 8) return hipErrorInvalidValue;
       else {
-        if (!fwd_prefetch()) return launch_pass_t<T, 5, false, false>(L, stream);
+        if (!L.prefetch) return launch_pass_t<T, 5, false, false>(L, stream);
         // psi stored after the last stage by every lane: the store-at-the-end variant
         const PassDesc& p = *L.h_pass;
         const bool tail = (p.flags & PF_STORE_A) && p.store_stage == p.stage_end - 1 && p.m - 5 >= 6;

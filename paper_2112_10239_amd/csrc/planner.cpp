@@ -16,16 +16,15 @@
 // Stage selection does the same at the register level inside a tile.
 #include "planner.h"
 
+#include "coefmath.h"
+
 #include <algorithm>
 #include <cmath>
-#include <complex>
 #include <cstring>
 #include <numeric>
 #include <thread>
 
 namespace qsim {
-
-using cd = std::complex<double>;
 
 // ---------------------------------------------------------------------------
 // validation
@@ -1291,127 +1290,22 @@ std::vector<char> trailing_diagonal(const CircuitDesc& c) {
 // ---------------------------------------------------------------------------
 // coefficients
 // ---------------------------------------------------------------------------
+// The matrices and blocks themselves are defined once (coefmath.h) for the
+// host rows built here and the rows a device kernel builds from parameters
+// resident in device memory.
 
 namespace {
 
-struct M2 {
-  cd a[2][2];
-};
-
-M2 mul(const M2& x, const M2& y) {
-  M2 z;
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) z.a[i][j] = x.a[i][0] * y.a[0][j] + x.a[i][1] * y.a[1][j];
-  return z;
-}
-
-M2 gate_m2(const Gate& g, const double* th) {
-  M2 u;
-  if (g.kind == G_U1) {
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) u.a[i][j] = cd(g.mat[(i * 2 + j) * 2], g.mat[(i * 2 + j) * 2 + 1]);
-    return u;
-  }
+cm::M2 gate_matrix(const Gate& g, const double* th) {
   const double t = g.param >= 0 ? th[g.param] : g.angle;
-  const double c = std::cos(0.5 * t), s = std::sin(0.5 * t);
-  switch (g.kind) {
-    case G_RX:  // cos(t/2) I - i sin(t/2) X
-      u.a[0][0] = c; u.a[0][1] = cd(0, -s); u.a[1][0] = cd(0, -s); u.a[1][1] = c;
-      break;
-    case G_RY:  // cos(t/2) I - i sin(t/2) Y
-      u.a[0][0] = c; u.a[0][1] = -s; u.a[1][0] = s; u.a[1][1] = c;
-      break;
-    default:    // RZ: cos(t/2) I - i sin(t/2) Z
-      u.a[0][0] = cd(c, -s); u.a[0][1] = 0; u.a[1][0] = 0; u.a[1][1] = cd(c, s);
-      break;
-  }
-  return u;
+  return cm::gate_m2(g.kind, t, g.mat);
 }
 
 // Matrix of a coefficient slot: product of its source gates, adjoint if flagged.
-M2 slot_m2(const CircuitDesc& c, const PGate& p, const double* th) {
-  M2 M;
-  M.a[0][0] = 1; M.a[0][1] = 0; M.a[1][0] = 0; M.a[1][1] = 1;
-  for (int g : p.srcs) M = mul(gate_m2(c.gates[g], th), M);
-  if (p.inverse) {
-    M2 h;
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) h.a[i][j] = std::conj(M.a[j][i]);
-    M = h;
-  }
-  return M;
-}
-
-// Factored form of a unitary 2x2: U = diag(p0, p1) K diag(1, e) with
-// K = [[1, -k], [k, 1]] when |u00| >= |u01| (cot = false), else [[k, -1], [1, k]];
-// |k| <= 1 either way.  Unitarity (orthogonal rows) makes the remaining entries
-// agree: tan form k e = -u01/u00, p0 = u00, p1 = u11/e; cot form k e = u11/u10,
-// p1 = u10, p0 = -u01/e.  The sign of k is chosen so that Re e >= 0, which makes
-// e = 1 (snapped) whenever k e is real, as for any RZ-after-RY product.  The cot
-// form is rewritten for the kernel as diag(p0, p1) [[k, -1], [1, k]] =
-// X diag(p1, -p0) [[1, k], [-k, 1]].
-struct KForm {
-  bool cot = false;
-  double k = 0;
-  cd p0 = 1, p1 = 1, e = 1;
-};
-
-KForm kform(const M2& M) {
-  KForm f;
-  const cd m00 = M.a[0][0], m01 = M.a[0][1], m10 = M.a[1][0], m11 = M.a[1][1];
-  f.cot = std::abs(m01) > std::abs(m00);
-  const cd z = f.cot ? m11 / m10 : -m01 / m00;
-  const double az = std::abs(z);
-  if (az > 0) {
-    f.k = z.real() >= 0 ? az : -az;
-    f.e = z / f.k;
-    if (std::abs(f.e - 1.0) <= 1e-13) f.e = 1;
-  }
-  if (f.cot) {
-    f.p1 = m10;
-    f.p0 = -m01 / f.e;
-  } else {
-    f.p0 = m00;
-    f.p1 = m11 / f.e;
-  }
-  return f;
-}
-
-// The whole coefficient block of a PG_TAB group (layout in planner.h), from
-// the matrices of the member slots.
-void tab_block(const std::vector<M2>& ms, const PGate& p, double* blk) {
-  for (int k = 0; k < 8 * kTabSlots; ++k) blk[k] = 0;
-  KForm f[4];
-  uint32_t form = 0, pre = 0;
-  const int r = (int)p.srcs.size();
-  for (int j = 0; j < r && j < 4; ++j) {
-    if (p.srcs[j] < 0) continue;
-    f[j] = kform(ms[p.srcs[j]]);
-    if (f[j].cot) {  // X diag(p1, -p0) T(-k)
-      form |= 1u << j;
-      const cd p0 = f[j].p0;
-      f[j].p0 = f[j].p1;
-      f[j].p1 = -p0;
-      f[j].k = -f[j].k;
-    }
-    if (f[j].e != 1.0) pre = 1;
-    blk[64 + j] = f[j].k;
-  }
-  for (int i = 0; i < 16; ++i) {
-    cd post = 1, pe = 1;
-    for (int j = 0; j < r && j < 4; ++j) {
-      if (p.srcs[j] < 0) continue;
-      const bool one = (i >> j) & 1;
-      post *= one ? f[j].p1 : f[j].p0;
-      if (one) pe *= f[j].e;
-    }
-    blk[2 * i] = post.real();
-    blk[2 * i + 1] = post.imag();
-    blk[32 + 2 * i] = pe.real();
-    blk[32 + 2 * i + 1] = pe.imag();
-  }
-  blk[68] = form;
-  blk[69] = pre;
+cm::M2 slot_m2(const CircuitDesc& c, const PGate& p, const double* th) {
+  cm::M2 M = cm::eye();
+  for (int g : p.srcs) M = cm::mul(gate_matrix(c.gates[g], th), M);
+  return p.inverse ? cm::adjoint(M) : M;
 }
 
 }  // namespace
@@ -1419,7 +1313,7 @@ void tab_block(const std::vector<M2>& ms, const PGate& p, double* blk) {
 template <class T>
 static void build_rows(const CircuitDesc& c, const std::vector<PGate>& slots, const double* params, int b0, int b1,
                        int64_t row_stride, T* out) {
-  std::vector<M2> ms(slots.size());
+  std::vector<cm::M2> ms(slots.size());
   for (int b = b0; b < b1; ++b) {
     const double* th = params ? params + (size_t)b * c.n_params : nullptr;
     T* row = out + (size_t)b * row_stride;
@@ -1428,18 +1322,18 @@ static void build_rows(const CircuitDesc& c, const std::vector<PGate>& slots, co
       if (p.kind == PG_TAB || p.kind == PG_INITF) continue;
       T* o = row + s * 8;
       for (int k = 0; k < 8; ++k) o[k] = 0;
-      const M2 M = ms[s] = slot_m2(c, p, th);
+      const cm::M2 M = ms[s] = slot_m2(c, p, th);
       if (p.kind == PG_RY) {
-        o[0] = (T)M.a[0][0].real();
-        o[1] = (T)M.a[1][0].real();
+        o[0] = (T)M.a[0][0].re;
+        o[1] = (T)M.a[1][0].re;
       } else if (p.kind == PG_PHASE) {
-        o[0] = (T)M.a[0][0].real(); o[1] = (T)M.a[0][0].imag();
-        o[2] = (T)M.a[1][1].real(); o[3] = (T)M.a[1][1].imag();
+        o[0] = (T)M.a[0][0].re; o[1] = (T)M.a[0][0].im;
+        o[2] = (T)M.a[1][1].re; o[3] = (T)M.a[1][1].im;
       } else {
-        o[0] = (T)M.a[0][0].real(); o[1] = (T)M.a[0][0].imag();
-        o[2] = (T)M.a[0][1].real(); o[3] = (T)M.a[0][1].imag();
-        o[4] = (T)M.a[1][0].real(); o[5] = (T)M.a[1][0].imag();
-        o[6] = (T)M.a[1][1].real(); o[7] = (T)M.a[1][1].imag();
+        o[0] = (T)M.a[0][0].re; o[1] = (T)M.a[0][0].im;
+        o[2] = (T)M.a[0][1].re; o[3] = (T)M.a[0][1].im;
+        o[4] = (T)M.a[1][0].re; o[5] = (T)M.a[1][0].im;
+        o[6] = (T)M.a[1][1].re; o[7] = (T)M.a[1][1].im;
       }
     }
     // product-state start: (U_q|0>)_0, (U_q|0>)_1 per qubit over init_slots(n) slots
@@ -1449,32 +1343,35 @@ static void build_rows(const CircuitDesc& c, const std::vector<PGate>& slots, co
       T* o = row + s * 8;
       for (int e = 0; e < 8 * init_slots(p.q); ++e) o[e] = 0;
       for (int q = 0; q < p.q; ++q) {
-        cd f0 = 1, f1 = 0;
+        cm::C f0 = cm::mk(1), f1 = cm::mk(0);
         if (p.srcs[q] >= 0) {
           f0 = ms[p.srcs[q]].a[0][0];
           f1 = ms[p.srcs[q]].a[1][0];
         }
-        o[4 * q] = (T)f0.real();
-        o[4 * q + 1] = (T)f0.imag();
-        o[4 * q + 2] = (T)f1.real();
-        o[4 * q + 3] = (T)f1.imag();
+        o[4 * q] = (T)f0.re;
+        o[4 * q + 1] = (T)f0.im;
+        o[4 * q + 2] = (T)f1.re;
+        o[4 * q + 3] = (T)f1.im;
       }
     }
     // factored groups: one block over kTabSlots consecutive slots, from the member matrices
     for (size_t s = 0; s < slots.size(); ++s) {
       const PGate& p = slots[s];
       if (p.kind != PG_TAB || p.gen != 0) continue;
-      double blk[8 * kTabSlots];
-      tab_block(ms, p, blk);
+      double blk[cm::kTabScalars];
+      cm::M2 mm[4];
+      int has[4] = {0, 0, 0, 0};
+      const int r = std::min<int>(4, (int)p.srcs.size());
+      for (int j = 0; j < r; ++j)
+        if (p.srcs[j] >= 0) {
+          mm[j] = ms[p.srcs[j]];
+          has[j] = 1;
+        }
+      cm::tab_block(mm, has, r, blk);
       T* o = row + s * 8;
       for (int e = 0; e < 8 * kTabSlots; ++e) {
-        if (e == 68 || e == 69) {  // raw 32-bit words in the scalar's low bytes
-          const uint32_t w = (uint32_t)blk[e];
-          o[e] = 0;
-          std::memcpy(&o[e], &w, sizeof(w));
-        } else {
-          o[e] = (T)blk[e];
-        }
+        if (e == 68 || e == 69) cm::put_raw(&o[e], (uint32_t)blk[e]);
+        else o[e] = (T)blk[e];
       }
     }
   }
@@ -1503,6 +1400,35 @@ template void build_coefficients<float>(const CircuitDesc&, const std::vector<PG
                                         float*);
 template void build_coefficients<double>(const CircuitDesc&, const std::vector<PGate>&, const double*, int, int64_t,
                                          double*);
+
+void coef_slot_table(const std::vector<PGate>& slots, std::vector<CoefSlot>& out, std::vector<int32_t>& srcs) {
+  out.clear();
+  srcs.clear();
+  for (const PGate& p : slots) {
+    CoefSlot s;
+    s.kind = p.kind == PG_RY ? CK_RY : p.kind == PG_PHASE ? CK_PHASE : p.kind == PG_TAB ? CK_TAB
+             : p.kind == PG_INITF ? CK_INITF : CK_U;
+    s.inverse = p.inverse ? 1 : 0;
+    s.gen = p.gen;
+    s.q = p.q;
+    s.src_off = (int32_t)srcs.size();
+    s.src_cnt = (int32_t)p.srcs.size();
+    for (int g : p.srcs) srcs.push_back(g);
+    out.push_back(s);
+  }
+}
+
+void coef_gate_table(const CircuitDesc& c, std::vector<CoefGate>& out) {
+  out.resize(c.gates.size());
+  for (size_t g = 0; g < c.gates.size(); ++g) {
+    const Gate& x = c.gates[g];
+    CoefGate& y = out[g];
+    y.kind = x.kind;
+    y.param = x.param;
+    y.angle = x.angle;
+    for (int k = 0; k < 8; ++k) y.mat[k] = x.mat[k];
+  }
+}
 
 uint64_t structure_hash(const CircuitDesc& c, const std::vector<Term>& terms, int extra) {
   uint64_t h = 1469598103934665603ull;

@@ -146,6 +146,10 @@ template <class T>
 void build_coefficients(const CircuitDesc& c, const std::vector<PGate>& slots, const double* params, int batch,
                         int64_t row_stride, T* out);
 
+// Flat slot and gate tables for building coefficient rows on the device.
+void coef_slot_table(const std::vector<PGate>& slots, std::vector<CoefSlot>& out, std::vector<int32_t>& srcs);
+void coef_gate_table(const CircuitDesc& c, std::vector<CoefGate>& out);
+
 uint64_t structure_hash(const CircuitDesc& c, const std::vector<Term>& terms, int extra);
 
 }  // namespace qsim

@@ -157,4 +157,32 @@ struct PassItem {
   int64_t tile_begin;
 };
 
+// Coefficient rows built on the device (parameters resident in device memory):
+// one record per coefficient slot of a plan, and one per gate of the circuit.
+enum CoefKind : int32_t {
+  CK_U = 0,      // general 2x2: u00, u01, u10, u11 (complex)
+  CK_RY = 1,     // real rotation: c, s
+  CK_PHASE = 2,  // diagonal: d0, d1 (complex)
+  CK_TAB = 3,    // factored group block over kTabSlots slots (written by its gen 0 slot)
+  CK_INITF = 4,  // product-start block: (U_q|0>)_0, (U_q|0>)_1 per qubit (written by gen 0)
+};
+
+struct CoefSlot {
+  int32_t kind;     // CoefKind
+  int32_t inverse;  // the adjoint of the product of the source gates
+  int32_t gen;      // chunk of a block (CK_TAB, CK_INITF)
+  int32_t q;        // CK_TAB: register bits; CK_INITF: qubits
+  int32_t src_off;  // sources: gate indices (CK_U/RY/PHASE, application order) or
+  int32_t src_cnt;  // member slots (CK_TAB per register bit, CK_INITF per qubit; -1 = none)
+};
+static_assert(sizeof(CoefSlot) == 24, "CoefSlot layout");
+
+struct CoefGate {
+  int32_t kind;   // gate kind of the C-ABI (RX 0, RY 1, RZ 2, U1 5)
+  int32_t param;  // parameter index, -1 = fixed angle
+  double angle;
+  double mat[8];  // U1: row-major (re, im)
+};
+static_assert(sizeof(CoefGate) == 80, "CoefGate layout");
+
 }  // namespace qsim

@@ -11,7 +11,7 @@ namespace qsim {
 namespace {
 
 constexpr size_t kMaxRunning = 512;          // requests launching passes at once
-constexpr size_t kMaxSteps = 3;              // steps in flight on the device
+constexpr size_t kDefaultSteps = 3;          // steps in flight on the device (default)
 constexpr size_t kRingBytes = 64ull << 20;   // pinned staging for plan/coefficient uploads
 
 enum Phase { PH_FWD = 0, PH_HAPPLY = 1, PH_ADJ = 2, PH_DONE = 3 };
@@ -140,6 +140,7 @@ void* PinnedRing::alloc(size_t bytes) {
 // ---------------------------------------------------------------------------
 
 Server::Server(qsim_ctx* ctx, bool mock) : ctx_(ctx), mock_(mock), pool_(mock) {
+  max_steps_ = ctx_->opt.max_inflight > 0 ? (size_t)ctx_->opt.max_inflight : kDefaultSteps;
   if (!mock_) {
     (void)hipSetDevice(ctx_->device);
     (void)hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking);
@@ -596,7 +597,7 @@ void Server::loop() {
       steps_.push_back(std::move(st));
     }
     // bound the steps in flight; with nothing left to launch, wait for the oldest
-    if (!steps_.empty() && (mock_ || steps_.size() >= kMaxSteps || run.empty())) retire_front();
+    if (!steps_.empty() && (mock_ || steps_.size() >= max_steps_ || run.empty())) retire_front();
   }
   // shutdown: launched work finishes normally, everything else ends with ESHUTDOWN
   while (!steps_.empty()) retire_front();

@@ -106,6 +106,7 @@ class Server {
   std::vector<hipEvent_t> free_events_;
   DevBuf d_items_;                  // pass items of the step being launched
   bool ok_ = true;
+  size_t max_steps_ = 3;            // steps in flight (context option max_inflight)
 };
 
 }  // namespace qsim

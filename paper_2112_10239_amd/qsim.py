@@ -47,7 +47,13 @@ class Hamiltonian(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_queue", ctypes.c_int32), ("cone_cap", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64)]
+                ("max_inflight", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("tile_qubits", ctypes.c_int32), ("register_bits", ctypes.c_int32), ("coalesce_bits", ctypes.c_int32),
+                ("dual_coalesce_bits", ctypes.c_int32), ("disable", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+OFF_FACTORED, OFF_ABSORB, OFF_ENTRY, OFF_EXIT, OFF_PRODUCT, OFF_PREFETCH, OFF_IO_REGS = 1, 2, 4, 8, 16, 32, 64
 
 
 class Request(ctypes.Structure):
@@ -62,13 +68,14 @@ class ServerStats(ctypes.Structure):
 
 
 assert ctypes.sizeof(Gate) == 32 and ctypes.sizeof(Circuit) == 24 and ctypes.sizeof(Hamiltonian) == 40
+assert ctypes.sizeof(Options) == 56
 
 EXPORTS = [
     "qsim_init", "qsim_finalize", "qsim_strerror", "qsim_last_error", "qsim_create_state", "qsim_destroy_state",
     "qsim_apply_layer", "qsim_expect", "qsim_state_to_host", "qsim_state_device_ptr", "qsim_expect_circuit",
     "qsim_expect_grad", "qsim_lightcone_sets", "qsim_plan_dense", "qsim_submit", "qsim_poll", "qsim_cancel",
     "qsim_server_stats_get", "qsim_timing_enable", "qsim_timing_get", "qsim_poll_timed", "qsim_clock",
-    "qsim_copy_probe", "qsim_expect_grad_cones", "qsim_reduced_density",
+    "qsim_copy_probe", "qsim_expect_grad_cones", "qsim_reduced_density", "qsim_plan_passes", "qsim_expect_terms",
 ]
 
 
@@ -86,22 +93,24 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     P, I, D, V = ctypes.POINTER, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
     sig = {
-        "qsim_init": (I, [P(Options), P(V)]),
+        "qsim_init": (I, [P(V), P(Options)]),
         "qsim_finalize": (None, [V]),
         "qsim_strerror": (ctypes.c_char_p, [I]),
         "qsim_last_error": (ctypes.c_char_p, [V]),
         "qsim_create_state": (I, [V, I, I, I, V, V, P(V)]),
         "qsim_destroy_state": (I, [V]),
-        "qsim_apply_layer": (I, [V, P(Gate), I, P(D), I]),
+        "qsim_apply_layer": (I, [V, P(Gate), I, V, I, I]),
         "qsim_expect": (I, [V, P(Hamiltonian), P(D)]),
         "qsim_state_to_host": (I, [V, V]),
         "qsim_state_device_ptr": (I, [V, P(V)]),
-        "qsim_expect_circuit": (I, [V, P(Circuit), P(D), I, P(Hamiltonian), I, I, V, P(D), P(V)]),
-        "qsim_expect_grad": (I, [V, P(Circuit), P(D), I, P(Hamiltonian), I, V, V, P(D), P(D)]),
-        "qsim_expect_grad_cones": (I, [V, P(Circuit), P(D), I, P(Hamiltonian), I, I, V, P(D), P(D)]),
+        "qsim_expect_circuit": (I, [V, P(Circuit), V, I, I, P(Hamiltonian), I, I, V, P(D), P(V)]),
+        "qsim_expect_terms": (I, [V, P(Circuit), V, I, I, P(Hamiltonian), I, I, V, P(D)]),
+        "qsim_expect_grad": (I, [V, P(Circuit), V, I, I, P(Hamiltonian), I, V, V, P(D), P(D)]),
+        "qsim_expect_grad_cones": (I, [V, P(Circuit), V, I, I, P(Hamiltonian), I, I, V, P(D), P(D)]),
         "qsim_reduced_density": (I, [V, P(ctypes.c_int32), I, V, I]),
         "qsim_lightcone_sets": (I, [P(Circuit), P(Hamiltonian), P(ctypes.c_int32), P(ctypes.c_int32), I]),
         "qsim_plan_dense": (I, [P(Circuit), P(Hamiltonian), I, P(ctypes.c_int64), P(ctypes.c_int32), I]),
+        "qsim_plan_passes": (I, [V, P(Circuit), P(Hamiltonian), I, I, P(ctypes.c_int32), I, P(I)]),
         "qsim_submit": (I, [V, P(Request), P(ctypes.c_uint64)]),
         "qsim_poll": (I, [V, ctypes.c_uint64, P(D), P(D)]),
         "qsim_cancel": (I, [V, ctypes.c_uint64]),
@@ -207,6 +216,39 @@ def _params(theta, rows: int, n_params: int) -> np.ndarray:
     return th
 
 
+def _is_device_tensor(theta) -> bool:
+    return hasattr(theta, "is_cuda") and bool(theta.is_cuda)
+
+
+def _torch_stream(t):
+    """torch's current stream on t's device (a hipStream_t), which produced t's values."""
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _param_args(theta, n_params: int):
+    """(pointer, rows, on_device, keepalive, single) for theta [P] or [B, P]: a host array,
+    or a float64 contiguous device tensor (passed by pointer; its values stay on the GPU)."""
+    if _is_device_tensor(theta):
+        import torch
+
+        t = theta.detach()
+        if t.dtype != torch.float64:
+            t = t.to(torch.float64)
+        t = t.contiguous()
+        single = t.dim() <= 1
+        rows = 1 if single else int(t.shape[0])
+        if t.numel() != rows * n_params:
+            raise ValueError(f"theta has {t.numel()} values, expected {rows} x {n_params}")
+        return ctypes.c_void_p(t.data_ptr() if t.numel() else 0), rows, 1, t, single
+    th = np.asarray(theta, dtype=np.float64)
+    single = th.ndim <= 1
+    rows = 1 if single else th.shape[0]
+    th = _params(th, rows, n_params)
+    return th.ctypes.data_as(ctypes.c_void_p), rows, 0, th, single
+
+
 # ---------------------------------------------------------------------------
 # host-only calls
 # ---------------------------------------------------------------------------
@@ -248,12 +290,16 @@ def plan_dense(circ, H=None, dtype: int = C64):
 class Context:
     """A libqsim context on one HIP device (device=-1: host-only, simulated serving)."""
 
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_queue: int = 0, cone_cap: int = 0):
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_queue: int = 0, cone_cap: int = 0,
+                 max_inflight: int = 0, tile_qubits: int = 0, register_bits: int = 0, coalesce_bits: int = 0,
+                 dual_coalesce_bits: int = 0, disable: int = 0):
         self._lib = lib
-        opt = Options(device, max_queue, cone_cap, 0, hbm_budget_bytes)
+        opt = Options(device=device, max_queue=max_queue, cone_cap=cone_cap, max_inflight=max_inflight,
+                      hbm_budget_bytes=hbm_budget_bytes, tile_qubits=tile_qubits, register_bits=register_bits,
+                      coalesce_bits=coalesce_bits, dual_coalesce_bits=dual_coalesce_bits, disable=disable)
         self._ticket_params = {}  # ticket -> n_params of its request (size of the gradient buffer)
         p = ctypes.c_void_p()
-        rc = lib.qsim_init(ctypes.byref(opt), ctypes.byref(p))
+        rc = lib.qsim_init(ctypes.byref(p), ctypes.byref(opt))
         if rc != OK:
             raise QsimError(rc, "qsim_init: " + strerror(rc))
         self.ptr = p
@@ -284,15 +330,15 @@ class Context:
 
     # -- one-call evaluation ----------------------------------------------------
     def expect_circuit(self, circ, H, theta, mode: int = MODE_AUTO, dtype: int = C64, stream=None, keep=False):
-        """<H> for theta [P] (float) or [B, P] ([B]); keep=True also returns a State."""
-        th = np.asarray(theta, dtype=np.float64)
-        single = th.ndim <= 1
-        rows = 1 if single else th.shape[0]
-        th = _params(th, rows, circ.n_params)
+        """<H> for theta [P] (float) or [B, P] ([B]); keep=True also returns a State.
+        theta may be a device tensor: its values are then read on the GPU only."""
+        tp, rows, dev, _hold, single = _param_args(theta, circ.n_params)
+        if dev and stream is None:  # read the parameters in order after the work that wrote them
+            stream = _torch_stream(_hold)
         cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
         out = np.zeros(rows)
         kp = ctypes.c_void_p()
-        rc = lib.qsim_expect_circuit(self.ptr, ctypes.byref(cc.c), _dptr(th), rows, ctypes.byref(ch.h), mode, dtype,
+        rc = lib.qsim_expect_circuit(self.ptr, ctypes.byref(cc.c), tp, rows, dev, ctypes.byref(ch.h), mode, dtype,
                                      stream, _dptr(out), ctypes.byref(kp) if keep else None)
         self._check(rc, "qsim_expect_circuit")
         val = float(out[0]) if single else out
@@ -300,32 +346,59 @@ class Context:
             return val, State._wrap(self, kp, circ.n, rows, dtype)
         return val
 
+    def expect_terms(self, circ, H, theta, mode: int = MODE_AUTO, dtype: int = C64, stream=None):
+        """<P_t> per term (coefficients not applied): [T] for theta [P], [B, T] for [B, P]."""
+        tp, rows, dev, _hold, single = _param_args(theta, circ.n_params)
+        if dev and stream is None:  # read the parameters in order after the work that wrote them
+            stream = _torch_stream(_hold)
+        cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
+        T = ch.h.n_terms
+        out = np.zeros((rows, max(T, 1)))
+        rc = lib.qsim_expect_terms(self.ptr, ctypes.byref(cc.c), tp, rows, dev, ctypes.byref(ch.h), mode, dtype,
+                                   stream, _dptr(out))
+        self._check(rc, "qsim_expect_terms")
+        out = out[:, :T]
+        return out[0] if single else out
+
     def expect_grad(self, circ, H, theta, dtype: int = C64, stream=None, saved=None, want_E=True,
                     mode: int = MODE_DENSE):
-        """(E [B], grad [B, P]) by the adjoint method; theta [P] or [B, P].  mode: MODE_DENSE
-        (full state), MODE_LIGHTCONE or MODE_LIGHTCONE_FACTORED (adjoint inside light cones)."""
-        th = np.asarray(theta, dtype=np.float64)
-        single = th.ndim <= 1
-        rows = 1 if single else th.shape[0]
-        th = _params(th, rows, circ.n_params)
+        """(E [B], grad [B, P]) by the adjoint method; theta [P] or [B, P] (host, or a device
+        tensor read on the GPU only).  mode: MODE_DENSE (full state), MODE_LIGHTCONE or
+        MODE_LIGHTCONE_FACTORED (adjoint inside light cones)."""
+        tp, rows, dev, _hold, single = _param_args(theta, circ.n_params)
+        if dev and stream is None:  # read the parameters in order after the work that wrote them
+            stream = _torch_stream(_hold)
         cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
         E = np.zeros(rows)
         g = np.zeros((rows, max(1, circ.n_params)))
         if mode == MODE_DENSE:
-            rc = lib.qsim_expect_grad(self.ptr, ctypes.byref(cc.c), _dptr(th), rows, ctypes.byref(ch.h), dtype,
+            rc = lib.qsim_expect_grad(self.ptr, ctypes.byref(cc.c), tp, rows, dev, ctypes.byref(ch.h), dtype,
                                       stream, saved.ptr if saved is not None else None,
                                       _dptr(E) if want_E else None, _dptr(g))
             self._check(rc, "qsim_expect_grad")
         else:
             if saved is not None:
                 raise ValueError("saved states are only used by the dense mode")
-            rc = lib.qsim_expect_grad_cones(self.ptr, ctypes.byref(cc.c), _dptr(th), rows, ctypes.byref(ch.h), mode,
+            rc = lib.qsim_expect_grad_cones(self.ptr, ctypes.byref(cc.c), tp, rows, dev, ctypes.byref(ch.h), mode,
                                             dtype, stream, _dptr(E) if want_E else None, _dptr(g))
             self._check(rc, "qsim_expect_grad_cones")
         g = g[:, : circ.n_params]
         if single:
             return float(E[0]), g[0]
         return E, g
+
+    def plan_passes(self, circ, H, dtype: int = C64, keep: bool = False):
+        """Per-pass records of the dense plan qsim_expect_circuit would launch: a list of
+        dicts (flags, stages, store_stage, entry_perm, exit_perm, meas_index, grad_count, m)."""
+        cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
+        cap = 4096
+        rec = np.zeros(8 * cap, dtype=np.int32)
+        cnt = ctypes.c_int()
+        rc = lib.qsim_plan_passes(self.ptr, ctypes.byref(cc.c), ctypes.byref(ch.h), dtype, int(keep),
+                                  rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cap, ctypes.byref(cnt))
+        self._check(rc, "qsim_plan_passes")
+        keys = ("flags", "stages", "store_stage", "entry_perm", "exit_perm", "meas_index", "grad_count", "m")
+        return [dict(zip(keys, (int(v) for v in rec[8 * p:8 * p + 8]))) for p in range(cnt.value)]
 
     # -- states -------------------------------------------------------------------
     def create_state(self, n: int, batch: int = 1, dtype: int = C64, dev_buf=None, stream=None) -> "State":
@@ -429,11 +502,20 @@ class State:
             pass
 
     def apply_layer(self, gates: np.ndarray, params=None, n_params: int = 0, mats=None):
+        """Queue gates; params [batch, n_params] on the host, or a device tensor."""
         cc = CCircuit(self.n, gates, n_params, mats)
-        th = None
+        tp, dev, hold = None, 0, None
         if n_params:
-            th = np.ascontiguousarray(params, dtype=np.float64).reshape(self.batch, n_params)
-        rc = lib.qsim_apply_layer(self.ptr, cc._arr, len(gates), _dptr(th) if th is not None else None, n_params)
+            if _is_device_tensor(params):
+                tp, rows, dev, hold, _ = _param_args(params.reshape(self.batch, n_params), n_params)
+                import torch
+
+                torch.cuda.current_stream(hold.device).synchronize()  # the values are complete
+            else:
+                hold = np.ascontiguousarray(params, dtype=np.float64).reshape(self.batch, n_params)
+                tp = hold.ctypes.data_as(ctypes.c_void_p)
+        rc = lib.qsim_apply_layer(self.ptr, cc._arr, len(gates), tp, n_params, dev)
+        del hold
         self.ctx._check(rc, "qsim_apply_layer")
 
     def expect(self, H) -> np.ndarray:

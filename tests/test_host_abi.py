@@ -196,3 +196,29 @@ def test_serving_poll_sizes_gradient_buffer(Q):
     st, E, g = wait(ctx, t)
     assert st == 0 and g is not None and g.shape == (r.circuit.n_params,)
     ctx.close()
+
+
+def test_plan_passes_store_first_stage_shapes(Q):
+    """Plans with a pass that stores in its first stage through a permutation and
+    measures in later stages (the loads of every wave must finish before any wave
+    stores): the dense n=30 workload, and the shapes the GPU parity tests run."""
+    ctx = Q.Context(-1)
+    try:
+        def hazards(c, H, keep=False):
+            ps = ctx.plan_passes(c, H, keep=keep)
+            return [p for p in ps if p["store_stage"] == 0 and (p["entry_perm"] or p["exit_perm"])
+                    and p["stages"] > 1]
+
+        w = W.dense_tfim()
+        assert hazards(w.circuit, w.H)
+        assert hazards(W.brickwork_ry_rz_cnot(15, 9), W.tfim(15, 1.0))
+        assert hazards(W.brickwork_ry_rz_cnot(23, 20), W.tfim(23, 1.0))
+        zz = W.Hamiltonian.from_terms([(1.0, [(i, "Z"), ((i + 1) % 14, "Z")]) for i in range(14)])
+        assert hazards(W.brickwork_ry_rz_cnot(14, 2), zz, keep=True)
+        # every pass record is consistent with its flags
+        for p in ctx.plan_passes(w.circuit, w.H):
+            assert p["stages"] >= 1 and p["m"] == 13
+            assert (p["store_stage"] >= 0) == bool(p["flags"] & 4)
+            assert (p["meas_index"] >= 0) == bool(p["flags"] & 64)
+    finally:
+        ctx.close()
