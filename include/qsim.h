@@ -252,6 +252,17 @@ int qsim_plan_dense(const qsim_circuit* c, const qsim_hamiltonian* H, int dtype,
 int qsim_plan_passes(qsim_ctx* ctx, const qsim_circuit* c, const qsim_hamiltonian* H, int dtype, int keep,
                      int32_t* rec, int cap, int* count);
 
+/* Coefficient rows (diagnostic for tests): the scalars that the dense passes of
+ * the gate plan of c read, for batch parameter rows, built on the host
+ * (params_on_device = 0) or by the device kernel from a device parameter buffer
+ * (1), copied raw into out (host memory, rows of 8 scalars per coefficient slot;
+ * float for QSIM_C64, double for QSIM_C128; entries 68 and 69 of a factored
+ * block are 32-bit words).  Both builders follow one fp64 definition, so the two
+ * results are expected to agree bit for bit.  *bytes = size of the rows;
+ * QSIM_ETOOBIG when cap is smaller. */
+int qsim_coef_rows(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch, int params_on_device,
+                   int dtype, void* out, uint64_t cap, uint64_t* bytes);
+
 /* ---- measurement ------------------------------------------------------------------ */
 
 /* Per-launch timing of the synchronous calls' pass kernels on ctx: with on != 0,

@@ -720,4 +720,22 @@ int qsim_plan_passes(qsim_ctx* ctx, const qsim_circuit* c, const qsim_hamiltonia
   return QSIM_OK;
 }
 
+int qsim_coef_rows(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch, int params_on_device,
+                   int dtype, void* out, uint64_t cap, uint64_t* bytes) {
+  if (!ctx || !bytes || batch < 1 || !valid_dtype(dtype) || (cap > 0 && !out)) return QSIM_EINVAL;
+  *bytes = 0;
+  if (ctx->mock) return no_device(ctx);
+  CircuitDesc cd;
+  int rc = to_circuit(ctx, c, cd);
+  if (rc) return rc;
+  if (cd.n_params > 0 && !params) return QSIM_EINVAL;
+  if (cd.n > kMaxQubits) return QSIM_ETOOBIG;
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  auto dp = get_dense_plan(ctx, cd, {}, dtype == QSIM_C128, true, true, false, rc);
+  if (!dp) return rc;
+  return coef_rows(ctx, ctx->ws, *dp, cd, ParamSrc(params, params_on_device != 0), batch, dtype == QSIM_C128,
+                   ctx->stream, out, cap, bytes);
+}
+
 }  // extern "C"

@@ -310,36 +310,42 @@ int to_terms(qsim_ctx* ctx, const qsim_hamiltonian* H, int n, std::vector<Term>&
 // plans
 // ---------------------------------------------------------------------------
 
-static std::shared_ptr<DevPlan> cache_get(qsim_ctx* ctx, uint64_t key) {
+static std::shared_ptr<DevPlan> cache_get(qsim_ctx* ctx, const std::string& key) {
   std::lock_guard<std::mutex> g(ctx->plan_mu);
   auto it = ctx->plans.find(key);
   return it == ctx->plans.end() ? nullptr : it->second;
 }
 
-static void cache_put(qsim_ctx* ctx, uint64_t key, std::shared_ptr<DevPlan> p) {
+static void cache_put(qsim_ctx* ctx, const std::string& key, std::shared_ptr<DevPlan> p) {
   std::lock_guard<std::mutex> g(ctx->plan_mu);
   if (ctx->plans.size() >= 256) ctx->plans.clear();
   ctx->plans[key] = std::move(p);
+}
+
+// Plan of the gates alone (no measurement), on the host.
+static int plan_gates_host(qsim_ctx* ctx, const CircuitDesc& c, int c128, bool init, bool store_final, Plan& out) {
+  out = Plan();
+  std::vector<PGate> pg;
+  forward_pgates(c, true, pg, out.slots);
+  PlanOptions o = fwd_options(ctx->opt, c128);
+  o.init = init;
+  o.store_final = store_final;
+  std::string err;
+  if (plan_forward(c.n, pg, {}, o, out, err)) {
+    set_error(ctx, err);
+    return QSIM_EINVAL;
+  }
+  return QSIM_OK;
 }
 
 // Plan of the gates alone, cached by circuit structure.
 static std::shared_ptr<DevPlan> gate_plan(qsim_ctx* ctx, const CircuitDesc& c, int c128, bool init, bool store_final,
                                           int& rc) {
   const int extra = 0x500 | c128 | (init << 1) | (store_final << 2);
-  const uint64_t key = structure_hash(c, {}, extra);
+  const std::string key = structure_key(c, {}, extra);
   if (auto p = cache_get(ctx, key)) return p;
   auto dp = std::make_shared<DevPlan>();
-  std::vector<PGate> pg;
-  forward_pgates(c, true, pg, dp->plan.slots);
-  PlanOptions o = fwd_options(ctx->opt, c128);
-  o.init = init;
-  o.store_final = store_final;
-  std::string err;
-  if (plan_forward(c.n, pg, {}, o, dp->plan, err)) {
-    set_error(ctx, err);
-    rc = QSIM_EINVAL;
-    return nullptr;
-  }
+  if ((rc = plan_gates_host(ctx, c, c128, init, store_final, dp->plan))) return nullptr;
   hipError_t e = dp->upload(ctx->mock);
   if (e != hipSuccess) {
     rc = hip_fail(ctx, e, "plan upload");
@@ -347,6 +353,37 @@ static std::shared_ptr<DevPlan> gate_plan(qsim_ctx* ctx, const CircuitDesc& c, i
   }
   cache_put(ctx, key, dp);
   return dp;
+}
+
+int host_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, int c128, bool init,
+                    bool store_final, Plan& out) {
+  // the same plan get_dense_plan(..., measure = true) builds, without its device copy
+  std::vector<PGate> meas;
+  double cst = 0;
+  term_pgates(terms, false, meas, cst);
+  bool diag = true;
+  for (const PGate& t : meas) diag &= t.fmask == 0;
+  if (meas.empty() || diag) {
+    int rc = plan_gates_host(ctx, c, c128, init, store_final, out);
+    if (rc) return rc;
+    if (meas.empty() && cst == 0.0) return QSIM_OK;
+    append_diag_measure(out, meas);
+    out.const_term = cst;
+    return QSIM_OK;
+  }
+  out = Plan();
+  std::vector<PGate> pg;
+  forward_pgates(c, true, pg, out.slots);
+  PlanOptions o = fwd_options(ctx->opt, c128);
+  o.init = init;
+  o.store_final = store_final;
+  std::string err;
+  if (plan_forward(c.n, pg, meas, o, out, err)) {
+    set_error(ctx, err);
+    return QSIM_EINVAL;
+  }
+  out.const_term = cst;
+  return QSIM_OK;
 }
 
 int host_forward_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, bool store_final,
@@ -423,7 +460,7 @@ std::shared_ptr<DevPlan> get_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, con
     return dp;
   }
   const int extra = 0x100 | c128 | (init << 1) | (store_final << 2) | (measure << 3);
-  const uint64_t key = structure_hash(c, terms, extra);
+  const std::string key = structure_key(c, terms, extra);
   if (auto p = cache_get(ctx, key)) return p;
   auto dp = std::make_shared<DevPlan>();
   std::vector<PGate> pg;
@@ -455,7 +492,7 @@ std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, con
   {
     CircuitDesc shape;
     shape.n = c.n;
-    const uint64_t key = structure_hash(shape, terms, 0x300 | c128);
+    const std::string key = structure_key(shape, terms, 0x300 | c128);
     happly = cache_get(ctx, key);
     if (!happly) {
       auto dp = std::make_shared<DevPlan>();
@@ -490,7 +527,7 @@ std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, con
 std::shared_ptr<DevPlan> get_adjoint_plan(qsim_ctx* ctx, const CircuitDesc& c, int c128, int& rc) {
   rc = QSIM_OK;
   const PlanOptions o = dual_options(ctx->opt, c128);
-  const uint64_t key = structure_hash(c, {}, 0x200 | c128);
+  const std::string key = structure_key(c, {}, 0x200 | c128);
   if (auto p = cache_get(ctx, key)) return p;
   auto dp = std::make_shared<DevPlan>();
   std::vector<PGate> pg;
@@ -667,7 +704,7 @@ struct ConePacker {
 std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, int c128,
                                        int& rc) {
   rc = QSIM_OK;
-  const uint64_t key = structure_hash(c, terms, 0x400 | c128);
+  const std::string key = structure_key(c, terms, 0x400 | c128);
   if (auto p = cache_get(ctx, key)) return p;
   auto dp = std::make_shared<DevPlan>();
   ConePacker pk(*dp, c, ctx->opt, c128, ctx->opt.cone_cap > 0 ? ctx->opt.cone_cap : 20);
@@ -695,7 +732,7 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
 std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
                                          int c128, int& rc, bool grad, bool split) {
   rc = QSIM_OK;
-  const uint64_t key = structure_hash(c, terms, 0x600 | c128 | (grad ? 2 : 0) | (split ? 0 : 4));
+  const std::string key = structure_key(c, terms, 0x600 | c128 | (grad ? 2 : 0) | (split ? 0 : 4));
   if (auto p = cache_get(ctx, key)) return p;
   auto dp = std::make_shared<DevPlan>();
   dp->factored = true;
@@ -836,6 +873,19 @@ static int fetch_out(qsim_ctx* ctx, Workspace& ws, size_t count, hipStream_t st,
   HIP_TRY(hipStreamSynchronize(st), "stream sync");
   timing_collect(ctx);
   std::memcpy(out_host, ws.h_out.p, count * sizeof(double));
+  return QSIM_OK;
+}
+
+int coef_rows(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params, int rows,
+              int c128, hipStream_t st, void* out_host, uint64_t cap, uint64_t* bytes) {
+  int64_t crs = 8;
+  const uint64_t need = (uint64_t)rows * (uint64_t)std::max<size_t>(1, dp.plan.slots.size()) * 8 * (c128 ? 8 : 4);
+  *bytes = need;
+  if (need > cap) return QSIM_ETOOBIG;
+  int rc = stage_coefficients(ctx, ws, dp, c, params, rows, c128, st, crs);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(out_host, ws.coef.p, need, hipMemcpyDeviceToHost, st), "coefficient copy");
+  HIP_TRY(hipStreamSynchronize(st), "stream sync");
   return QSIM_OK;
 }
 

@@ -141,7 +141,7 @@ struct qsim_ctx {
   qsim_options opt{};
   std::mutex api_mu;     // synchronous calls
   std::mutex plan_mu;    // plan cache
-  std::unordered_map<uint64_t, std::shared_ptr<qsim::DevPlan>> plans;
+  std::unordered_map<std::string, std::shared_ptr<qsim::DevPlan>> plans;  // by structure key
   qsim::Workspace ws;
   qsim::DevBuf psi;      // state workspace of qsim_expect_circuit
   std::mutex err_mu;
@@ -177,6 +177,10 @@ std::shared_ptr<DevPlan> get_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, con
 std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms,
                                         int c128, std::shared_ptr<DevPlan>& happly, int& rc);
 std::shared_ptr<DevPlan> get_adjoint_plan(qsim_ctx* ctx, const CircuitDesc& c, int c128, int& rc);
+// The plan get_dense_plan(..., measure = true) returns, built on the host only
+// (no device copy, not cached).
+int host_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, int c128, bool init,
+                    bool store_final, Plan& out);
 // Host-only plans for the serving loop (complex64): the forward plan reuses
 // the structure-cached gate plan and appends this H's measurement.
 int host_forward_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, bool store_final,
@@ -204,6 +208,9 @@ struct ParamSrc {
 // Run a dense plan on states A (and B) with 'rows' rows; coefficients from params.
 int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params, int rows,
               int c128, void* A, void* B, hipStream_t st, double* out_host);
+// The coefficient rows a dense plan's passes read (host- or device-built), copied to host memory.
+int coef_rows(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params, int rows,
+              int c128, hipStream_t st, void* out_host, uint64_t cap, uint64_t* bytes);
 int run_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& hp, const DevPlan& ap, const CircuitDesc& c,
              const ParamSrc& params, int rows, int c128, void* A, void* B, hipStream_t st, double* grad_host);
 // One cone launch; out_host receives <H> (terms_host == nullptr) or, for a

@@ -1430,28 +1430,28 @@ void coef_gate_table(const CircuitDesc& c, std::vector<CoefGate>& out) {
   }
 }
 
-uint64_t structure_hash(const CircuitDesc& c, const std::vector<Term>& terms, int extra) {
-  uint64_t h = 1469598103934665603ull;
-  auto mix = [&](uint64_t v) {
-    h ^= v;
-    h *= 1099511628211ull;
-  };
-  mix((uint64_t)c.n);
-  mix((uint64_t)c.n_params);
-  mix((uint64_t)extra);
+std::string structure_key(const CircuitDesc& c, const std::vector<Term>& terms, int extra) {
+  // every field a plan depends on, in a fixed byte layout: equal keys mean equal structure
+  std::string k;
+  k.reserve(24 + 16 * c.gates.size() + 24 * terms.size());
+  auto put = [&](uint64_t v) { k.append(reinterpret_cast<const char*>(&v), sizeof v); };
+  put((uint64_t)c.n);
+  put((uint64_t)c.n_params);
+  put((uint64_t)(uint32_t)extra);
+  put((uint64_t)c.gates.size());
   for (const Gate& g : c.gates) {
-    mix((uint64_t)g.kind | ((uint64_t)(uint32_t)g.q0 << 8));
-    mix((uint64_t)(uint32_t)g.q1 | ((uint64_t)(uint32_t)g.param << 32));
+    put((uint64_t)(uint32_t)g.kind | ((uint64_t)(uint32_t)g.q0 << 32));
+    put((uint64_t)(uint32_t)g.q1 | ((uint64_t)(uint32_t)g.param << 32));
   }
-  mix(0xabcdefull);
+  put((uint64_t)terms.size());
   for (const Term& t : terms) {
     uint64_t cb;
     std::memcpy(&cb, &t.c, 8);
-    mix(cb);
-    for (auto [q, L] : t.ops) mix(((uint64_t)(uint32_t)q << 8) | (uint8_t)L);
-    mix(0x55ull);
+    put(cb);
+    put((uint64_t)t.ops.size());
+    for (auto [q, L] : t.ops) put(((uint64_t)(uint32_t)q << 8) | (uint8_t)L);
   }
-  return h;
+  return k;
 }
 
 }  // namespace qsim

@@ -150,6 +150,8 @@ void build_coefficients(const CircuitDesc& c, const std::vector<PGate>& slots, c
 void coef_slot_table(const std::vector<PGate>& slots, std::vector<CoefSlot>& out, std::vector<int32_t>& srcs);
 void coef_gate_table(const CircuitDesc& c, std::vector<CoefGate>& out);
 
-uint64_t structure_hash(const CircuitDesc& c, const std::vector<Term>& terms, int extra);
+// Cache key of a plan: the circuit's structure (gate kinds, qubits, parameter
+// indices), the terms and the plan variant, serialised; keys compare by value.
+std::string structure_key(const CircuitDesc& c, const std::vector<Term>& terms, int extra);
 
 }  // namespace qsim

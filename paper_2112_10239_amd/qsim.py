@@ -76,6 +76,7 @@ EXPORTS = [
     "qsim_expect_grad", "qsim_lightcone_sets", "qsim_plan_dense", "qsim_submit", "qsim_poll", "qsim_cancel",
     "qsim_server_stats_get", "qsim_timing_enable", "qsim_timing_get", "qsim_poll_timed", "qsim_clock",
     "qsim_copy_probe", "qsim_expect_grad_cones", "qsim_reduced_density", "qsim_plan_passes", "qsim_expect_terms",
+    "qsim_coef_rows",
 ]
 
 
@@ -111,6 +112,7 @@ def _load():
         "qsim_lightcone_sets": (I, [P(Circuit), P(Hamiltonian), P(ctypes.c_int32), P(ctypes.c_int32), I]),
         "qsim_plan_dense": (I, [P(Circuit), P(Hamiltonian), I, P(ctypes.c_int64), P(ctypes.c_int32), I]),
         "qsim_plan_passes": (I, [V, P(Circuit), P(Hamiltonian), I, I, P(ctypes.c_int32), I, P(I)]),
+        "qsim_coef_rows": (I, [V, P(Circuit), V, I, I, I, V, ctypes.c_uint64, P(ctypes.c_uint64)]),
         "qsim_submit": (I, [V, P(Request), P(ctypes.c_uint64)]),
         "qsim_poll": (I, [V, ctypes.c_uint64, P(D), P(D)]),
         "qsim_cancel": (I, [V, ctypes.c_uint64]),
@@ -399,6 +401,21 @@ class Context:
         self._check(rc, "qsim_plan_passes")
         keys = ("flags", "stages", "store_stage", "entry_perm", "exit_perm", "meas_index", "grad_count", "m")
         return [dict(zip(keys, (int(v) for v in rec[8 * p:8 * p + 8]))) for p in range(cnt.value)]
+
+    def coef_rows(self, circ, theta, dtype: int = C64) -> np.ndarray:
+        """Raw coefficient rows of the dense gate plan (uint8 [rows, row_bytes]), built on the
+        host for a host theta or by the device kernel for a device tensor."""
+        tp, rows, dev, _hold, _ = _param_args(theta, circ.n_params)
+        cc = CCircuit.of(circ)
+        need = ctypes.c_uint64()
+        rc = lib.qsim_coef_rows(self.ptr, ctypes.byref(cc.c), tp, rows, dev, dtype, None, 0, ctypes.byref(need))
+        if rc != ETOOBIG:
+            self._check(rc, "qsim_coef_rows")
+        out = np.zeros(need.value, dtype=np.uint8)
+        rc = lib.qsim_coef_rows(self.ptr, ctypes.byref(cc.c), tp, rows, dev, dtype, out.ctypes.data_as(ctypes.c_void_p),
+                                need.value, ctypes.byref(need))
+        self._check(rc, "qsim_coef_rows")
+        return out.reshape(rows, -1)
 
     # -- states -------------------------------------------------------------------
     def create_state(self, n: int, batch: int = 1, dtype: int = C64, dev_buf=None, stream=None) -> "State":

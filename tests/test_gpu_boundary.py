@@ -101,6 +101,30 @@ def test_terms_batched_rows(Q, eng, oracle_mod):
 
 # --- parameters in device memory --------------------------------------------------------
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_device_coef_rows_equal_host_rows(Q, eng, dtype):
+    """The coefficient rows built by the device kernel from device parameters equal,
+    bit for bit, the rows the host builds (one fp64 definition serves both)."""
+    import torch
+
+    from tests.test_gpu_parity import _rotation_mix
+
+    dt = Q.C64 if dtype == "c64" else Q.C128
+    cases = [W.batched_grad_tfim(batch=3, n=14, depth=4), None]
+    for k, w in enumerate(cases):
+        if w is None:
+            c, th = _rotation_mix(13, 5, 7)
+            th = th[None, :]
+        else:
+            c, th = w.circuit, w.theta
+        say("coef rows", dtype, k)
+        host = eng.coef_rows(c, th, dtype=dt)
+        dev = eng.coef_rows(c, torch.tensor(th, dtype=torch.float64, device="cuda:0"), dtype=dt)
+        assert host.shape == dev.shape
+        bad = np.nonzero(host != dev)
+        assert bad[0].size == 0, f"case {k}: {bad[0].size} bytes differ, first at row/byte {bad[0][0]}/{bad[1][0]}"
+
+
 def test_device_params_dense_and_grad(Q, eng, oracle_mod):
     import torch
 
