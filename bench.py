@@ -107,21 +107,37 @@ def bench_dense(Q, W, steps, warmup):
     return dict(value=steps / (t1 - t0), ms_per_step=(t1 - t0) / steps * 1e3, E=E, plan=info, roofline=roof)
 
 
-def cpu_baseline(W, n_sample=23):
+def cpu_baseline(W, sizes_1=(20,), sizes_all=(20, 22, 24)):
+    """The oracle on the host cores: one complex128 <H> of the same depth-20 RY+RZ+CNOT
+    TFIM family at n = 20 on one thread (with --cpu-full also 22 and 24) and at n = 20,
+    22 and 24 on every thread (n = 30 itself would take hours and 16 GiB); the value is the n = 24
+    all-thread time scaled to n = 30 (2^6 more amplitudes, 1780/1404 more gates),
+    labelled as an extrapolation."""
     import oracle
 
     oracle.build(force=False)
-    w = W.dense_tfim(n=n_sample)
     full = W.dense_tfim()
-    log(f"[cpu] oracle n={n_sample}")
-    t0 = time.perf_counter()
-    oracle.expect(w.circuit, w.H, w.theta)
-    dt = time.perf_counter() - t0
-    # scale to n=30: work per gate grows as 2^n, and the n=30 circuit has more gates
-    scale = 2.0 ** (30 - n_sample) * full.circuit.n_gates / w.circuit.n_gates
-    return dict(value=1.0 / (dt * scale), unit="evals/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"one complex128 <H> of the same RY+RZ+CNOT depth-20 TFIM family at n={n_sample} "
-                       f"({dt:.2f} s), scaled by 2^{30 - n_sample} x gate-count ratio to n=30")
+    all_threads = oracle.num_threads()
+    times = {}
+    for threads, sizes in ((1, sizes_1), (all_threads, sizes_all)):
+        oracle.set_num_threads(threads)
+        for n in sizes:
+            w = W.dense_tfim(n=n)
+            log(f"[cpu] oracle n={n} threads={threads}")
+            t0 = time.perf_counter()
+            oracle.expect(w.circuit, w.H, w.theta)
+            times[f"n{n}_threads{threads}"] = time.perf_counter() - t0
+    oracle.set_num_threads(all_threads)
+    n_top = sizes_all[-1]
+    dt = times[f"n{n_top}_threads{all_threads}"]
+    top = W.dense_tfim(n=n_top)
+    scale = 2.0 ** (30 - n_top) * full.circuit.n_gates / top.circuit.n_gates
+    return dict(value=1.0 / (dt * scale), unit="evals/s", cores=all_threads, kind="oracle",
+                sample=f"one complex128 <H> of the same RY+RZ+CNOT depth-20 TFIM family, measured at "
+                       f"n={', '.join(str(n) for n in sizes_1)} on 1 thread and n={', '.join(str(n) for n in sizes_all)} "
+                       f"on {all_threads} threads; value = the n={n_top} {all_threads}-thread time ({dt:.2f} s) "
+                       f"extrapolated by 2^{30 - n_top} x gate-count ratio to n=30",
+                seconds=times)
 
 
 def bench_lightcone(Q, W, reps=20):
@@ -370,6 +386,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true", help="oracle also at n = 22 and 24 on one thread (minutes)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--serving", type=float, default=1.0, help="seconds of Poisson arrivals (0 = skip serving)")
     ap.add_argument("--counter-run", action="store_true",
@@ -410,7 +427,7 @@ def main():
         "roofline": d["roofline"],
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(W)
+        line["cpu_baseline"] = cpu_baseline(W, sizes_1=(20, 22, 24) if args.cpu_full else (20,))
     if not args.no_extras:
         line["extras"] = {"lightcone": bench_lightcone(Q, W), "gradient": bench_grad(Q, W),
                           "lightcone_gradient": bench_lightcone_grad(Q, W), "density": bench_density(Q, W),

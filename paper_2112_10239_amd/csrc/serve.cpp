@@ -2,6 +2,7 @@
 #include "serve.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -141,6 +142,10 @@ void* PinnedRing::alloc(size_t bytes) {
 
 Server::Server(qsim_ctx* ctx, bool mock) : ctx_(ctx), mock_(mock), pool_(mock) {
   max_steps_ = ctx_->opt.max_inflight > 0 ? (size_t)ctx_->opt.max_inflight : kDefaultSteps;
+  if (mock_) {  // test hook: simulated steps take this long, so tests can act on queued requests
+    const char* s = std::getenv("QSIM_TEST_MOCK_STEP_MS");
+    mock_step_ms_ = s ? std::max(0, std::atoi(s)) : 0;
+  }
   if (!mock_) {
     (void)hipSetDevice(ctx_->device);
     (void)hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking);
@@ -595,6 +600,7 @@ void Server::loop() {
         for (SReq* r : st.finishing) running_.erase(std::find(running_.begin(), running_.end(), r));
       }
       steps_.push_back(std::move(st));
+      if (mock_ && mock_step_ms_ > 0) std::this_thread::sleep_for(std::chrono::milliseconds(mock_step_ms_));
     }
     // bound the steps in flight; with nothing left to launch, wait for the oldest
     if (!steps_.empty() && (mock_ || steps_.size() >= max_steps_ || run.empty())) retire_front();

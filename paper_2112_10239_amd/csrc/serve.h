@@ -88,6 +88,7 @@ class Server {
   void* stage_upload(const void* src, size_t bytes, void* dst);
 
   qsim_ctx* ctx_;
+  int mock_step_ms_ = 0;  // simulated step time (test hook)
   bool mock_;
   hipStream_t stream_ = nullptr;
   std::thread thread_;

@@ -150,7 +150,9 @@ def test_serving_mock_budget_and_queue(Q):
     ctx.close()
 
 
-def test_serving_mock_cancel_and_shutdown(Q):
+def test_serving_mock_cancel_and_shutdown(Q, monkeypatch):
+    # simulated steps of 20 ms: the last of ten requests is still queued when it is cancelled
+    monkeypatch.setenv("QSIM_TEST_MOCK_STEP_MS", "20")
     ctx = Q.Context(-1, hbm_budget_bytes=(1 << 24) + (1 << 22), max_queue=100)
     reqs = [W.serving_request(r, n_range=(20, 20), depth_range=(16, 16)) for r in range(10)]
     ts = [ctx.submit(r.circuit, r.H, r.theta, True) for r in reqs]
@@ -222,3 +224,4 @@ def test_plan_passes_store_first_stage_shapes(Q):
             assert (p["meas_index"] >= 0) == bool(p["flags"] & 64)
     finally:
         ctx.close()
+
