@@ -6,6 +6,11 @@
 // Conventions: RX/RY/RZ(t) = exp(-i t P / 2); a slot's matrix is the product of
 // its source gates in application order (later gates on the left), adjoint
 // when the slot is flagged inverse.
+//
+// Every value here is computed from correctly rounded IEEE operations only (+,
+// -, *, /, sqrt, rint, comparisons), with multiply-add contraction switched off
+// and no math-library call (the sine and cosine are the series below), so the
+// host and the device produce the same bits.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -14,8 +19,56 @@
 
 #include "qsim_types.h"
 
+#pragma float_control(push)
+#pragma clang fp contract(off)
+
 namespace qsim {
 namespace cm {
+
+// pi/2 split in three parts of at most 33 significant bits (the first two), so
+// k * part is exact for |k| < 2^20; and 2/pi.
+constexpr double kPio2a = 0x1.921fb544p+0;
+constexpr double kPio2b = 0x1.0b4611a6p-34;
+constexpr double kPio2c = 0x1.3198a2e037073p-69;
+constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+
+// sin x and cos x: x = k pi/2 + r with |r| <= pi/4 (three-part reduction,
+// accurate for |x| < 1.6e6), then the Taylor series of sin r and cos r to
+// degree 21 and 20 (truncation below 1e-24 on |r| <= pi/4) in Horner form, and
+// the quadrant from k mod 4.
+__host__ __device__ inline void sincos_ieee(double x, double* s_out, double* c_out) {
+  const double k = ::rint(x * kTwoOverPi);
+  double r = x - k * kPio2a;
+  r = r - k * kPio2b;
+  r = r - k * kPio2c;
+  const double u = r * r;
+  // sin r = r (1 - u/3! + u^2/5! - ...), cos r = 1 - u/2! + u^2/4! - ...
+  double ps = -1.0 / 51090942171709440000.0;  // -1/21!
+  ps = ps * u + 1.0 / 121645100408832000.0;    // 1/19!
+  ps = ps * u - 1.0 / 355687428096000.0;       // 1/17!
+  ps = ps * u + 1.0 / 1307674368000.0;         // 1/15!
+  ps = ps * u - 1.0 / 6227020800.0;            // 1/13!
+  ps = ps * u + 1.0 / 39916800.0;              // 1/11!
+  ps = ps * u - 1.0 / 362880.0;                // 1/9!
+  ps = ps * u + 1.0 / 5040.0;                  // 1/7!
+  ps = ps * u - 1.0 / 120.0;                   // 1/5!
+  ps = ps * u + 1.0 / 6.0;                     // 1/3!
+  const double sr = r - (r * u) * ps;
+  double pc = 1.0 / 2432902008176640000.0;     // 1/20!
+  pc = pc * u - 1.0 / 6402373705728000.0;      // 1/18!
+  pc = pc * u + 1.0 / 20922789888000.0;        // 1/16!
+  pc = pc * u - 1.0 / 87178291200.0;           // 1/14!
+  pc = pc * u + 1.0 / 479001600.0;             // 1/12!
+  pc = pc * u - 1.0 / 3628800.0;               // 1/10!
+  pc = pc * u + 1.0 / 40320.0;                 // 1/8!
+  pc = pc * u - 1.0 / 720.0;                   // 1/6!
+  pc = pc * u + 1.0 / 24.0;                    // 1/4!
+  pc = pc * u - 1.0 / 2.0;                     // 1/2!
+  const double cr = 1.0 + u * pc;
+  const int q = (int)((int64_t)k & 3);
+  *s_out = q == 0 ? sr : q == 1 ? cr : q == 2 ? -sr : -cr;
+  *c_out = q == 0 ? cr : q == 1 ? -sr : q == 2 ? -cr : sr;
+}
 
 struct C {
   double re, im;
@@ -26,7 +79,8 @@ __host__ __device__ inline C add(C a, C b) { return C{a.re + b.re, a.im + b.im};
 __host__ __device__ inline C mul(C a, C b) { return C{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __host__ __device__ inline C neg(C a) { return C{-a.re, -a.im}; }
 __host__ __device__ inline C conj(C a) { return C{a.re, -a.im}; }
-__host__ __device__ inline double cabs(C a) { return ::hypot(a.re, a.im); }
+__host__ __device__ inline double norm2(C a) { return a.re * a.re + a.im * a.im; }
+__host__ __device__ inline double cabs(C a) { return ::sqrt(norm2(a)); }
 __host__ __device__ inline C scale(C a, double s) { return C{a.re * s, a.im * s}; }
 // a / b (Smith's method: no overflow for entries of a unitary)
 __host__ __device__ inline C cdiv(C a, C b) {
@@ -73,7 +127,8 @@ __host__ __device__ inline M2 gate_m2(int kind, double t, const double* mat) {
       for (int j = 0; j < 2; ++j) u.a[i][j] = mk(mat[(i * 2 + j) * 2], mat[(i * 2 + j) * 2 + 1]);
     return u;
   }
-  const double c = ::cos(0.5 * t), s = ::sin(0.5 * t);
+  double s, c;
+  sincos_ieee(0.5 * t, &s, &c);
   if (kind == 0) {  // cos(t/2) I - i sin(t/2) X
     u.a[0][0] = mk(c); u.a[0][1] = mk(0, -s); u.a[1][0] = mk(0, -s); u.a[1][1] = mk(c);
   } else if (kind == 1) {  // cos(t/2) I - i sin(t/2) Y
@@ -103,7 +158,7 @@ __host__ __device__ inline KForm kform(const M2& M) {
   f.p1 = mk(1);
   f.e = mk(1);
   const C m00 = M.a[0][0], m01 = M.a[0][1], m10 = M.a[1][0], m11 = M.a[1][1];
-  f.cot = cabs(m01) > cabs(m00);
+  f.cot = norm2(m01) > norm2(m00);
   const C z = f.cot ? cdiv(m11, m10) : neg(cdiv(m01, m00));
   const double az = cabs(z);
   if (az > 0) {
@@ -172,3 +227,5 @@ __host__ __device__ inline void put_raw(T* o, uint32_t w) {
 
 }  // namespace cm
 }  // namespace qsim
+
+#pragma float_control(pop)
