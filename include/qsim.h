@@ -187,6 +187,30 @@ int qsim_expect_circuit(qsim_ctx* ctx, const qsim_circuit* c, const double* para
                         int params_on_device, const qsim_hamiltonian* H, int mode, int dtype, void* stream,
                         double* out, qsim_state** keep);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): qsim_expect_circuit in
+ * dense mode, with the final states kept, that calls no hipMalloc, hipFree or
+ * other allocating routine.  out[b] = <psi(theta_b)|H|psi(theta_b)> (float64,
+ * host, [batch]); params and params_on_device as in qsim_expect_circuit.  state:
+ * caller device buffer of state_bytes >= batch * 2^n * (8 or 16) bytes (layout as
+ * in qsim_create_state); the passes work in it and it holds the final states
+ * psi(theta_b) on return (the same values, bit for bit, as the state that
+ * qsim_expect_circuit returns in *keep).  Plan descriptors, coefficient rows,
+ * partial sums and the results live in a fixed 64 MiB device array that the
+ * library holds on each GPU it runs on until the process ends; a call needs
+ * about batch * (measurement passes) * 2^(n - 13) * 8 bytes of it for partial
+ * sums (n = 30, batch 1: 2 MiB) and returns QSIM_ETOOBIG, allocating nothing,
+ * when the whole need exceeds 64 MiB.  Plans are built on the host and kept per
+ * circuit structure in the context's host memory.  Every call on one GPU (any
+ * context, any thread) uses that GPU's single array and overwrites what the
+ * last call left there: calls that overlap in time on one GPU race and give
+ * wrong results (calls on one context are serialised).  Returns when out is
+ * written.  QSIM_EINVAL for a short or NULL state buffer and for the errors of
+ * qsim_expect_circuit. */
+int qsim_expect_circuit_noalloc(qsim_ctx* ctx, const qsim_circuit* c, const double* params, int batch,
+                                int params_on_device, const qsim_hamiltonian* H, int dtype, void* state,
+                                uint64_t state_bytes, void* stream, double* out);
+
 /* Per-term values (Sec. 1 and Sec. 3: <H> = sum_t coeff[t] <P_t>):
  * out[b * n_terms + t] = <psi(theta_b)|P_t|psi(theta_b)> without the coefficient (1
  * for identity terms), float64, host, [batch][n_terms].  params and params_on_device

@@ -108,6 +108,9 @@ int qsim_init(qsim_ctx** out, const qsim_options* opt) {
     delete ctx;
     return QSIM_EDEVICE;
   }
+  // address of the allocation-free entry point's working memory on this device;
+  // a failure is reported by that entry point, the rest of the library works
+  (void)noalloc_setup(ctx->device);
   *out = ctx;
   return QSIM_OK;
 }

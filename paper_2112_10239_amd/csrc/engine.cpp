@@ -889,6 +889,36 @@ int coef_rows(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
   return QSIM_OK;
 }
 
+int enqueue_dense_passes(qsim_ctx* ctx, const Plan& P, const DenseBufs& b, int rows, int c128, void* A, void* B,
+                         hipStream_t st, bool timed) {
+  for (size_t p = 0; p < P.passes.size(); ++p) {
+    PassLaunch L;
+    L.d_pass = b.passes + p;
+    L.h_pass = &P.passes[p];
+    L.d_stages = b.stages;
+    L.d_ops = b.ops;
+    L.A = A;
+    L.B = B;
+    L.row_stride = 1ll << P.n;
+    L.coef = b.coef;
+    L.coef_row_stride = b.coef_row_stride;
+    L.meas = b.meas;
+    L.n_meas = P.n_meas;
+    L.grad = nullptr;
+    L.n_gslots = 0;
+    L.rows = rows;
+    L.c128 = c128;
+    L.dual = 0;
+    L.prefetch = prefetch_on(ctx->opt);
+    const int ti = timed ? timing_begin(ctx, st, pass_bytes(P.passes[p], rows, c128), P.passes[p].flags, 0,
+                                        pass_flops_per_amp(P, P.passes[p]) * (double)rows * (double)(1ull << P.n))
+                         : -1;
+    HIP_TRY(launch_pass(L, st), "pass launch");
+    if (timed) timing_end(ctx, ti, st);
+  }
+  return QSIM_OK;
+}
+
 int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params, int rows,
               int c128, void* A, void* B, hipStream_t st, double* out_host) {
   const Plan& P = dp.plan;
@@ -897,30 +927,8 @@ int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
   if (rc) return rc;
   const int64_t tiles = 1ll << (P.n - P.m);
   if (P.n_meas > 0) HIP_TRY(ws.meas.ensure((size_t)rows * P.n_meas * tiles * sizeof(double)), "partials buffer");
-  for (size_t p = 0; p < P.passes.size(); ++p) {
-    PassLaunch L;
-    L.d_pass = dp.d_passes + p;
-    L.h_pass = &P.passes[p];
-    L.d_stages = dp.d_stages;
-    L.d_ops = dp.d_ops;
-    L.A = A;
-    L.B = B;
-    L.row_stride = 1ll << P.n;
-    L.coef = ws.coef.p;
-    L.coef_row_stride = crs;
-    L.meas = (double*)ws.meas.p;
-    L.n_meas = P.n_meas;
-    L.grad = nullptr;
-    L.n_gslots = 0;
-    L.rows = rows;
-    L.c128 = c128;
-    L.dual = 0;
-    L.prefetch = prefetch_on(ctx->opt);
-    const int ti = timing_begin(ctx, st, pass_bytes(P.passes[p], rows, c128), P.passes[p].flags, 0,
-                                pass_flops_per_amp(P, P.passes[p]) * (double)rows * (double)(1ull << P.n));
-    HIP_TRY(launch_pass(L, st), "pass launch");
-    timing_end(ctx, ti, st);
-  }
+  const DenseBufs bufs{dp.d_passes, dp.d_stages, dp.d_ops, ws.coef.p, crs, (double*)ws.meas.p};
+  if ((rc = enqueue_dense_passes(ctx, P, bufs, rows, c128, A, B, st, true))) return rc;
   if (out_host) {
     if (P.n_meas == 0) {
       HIP_TRY(hipStreamSynchronize(st), "stream sync");

@@ -142,6 +142,7 @@ struct qsim_ctx {
   std::mutex api_mu;     // synchronous calls
   std::mutex plan_mu;    // plan cache
   std::unordered_map<std::string, std::shared_ptr<qsim::DevPlan>> plans;  // by structure key
+  std::unordered_map<std::string, std::shared_ptr<qsim::Plan>> host_plans;  // host-only plans (no device copy)
   qsim::Workspace ws;
   qsim::DevBuf psi;      // state workspace of qsim_expect_circuit
   std::mutex err_mu;
@@ -205,6 +206,19 @@ struct ParamSrc {
   ParamSrc row(int b, int n_params) const { return ParamSrc(p ? p + (size_t)b * n_params : nullptr, dev); }
 };
 
+// Device copies of a dense plan's descriptors and the buffers its passes use.
+struct DenseBufs {
+  const PassDesc* passes;
+  const StageDesc* stages;
+  const DevOp* ops;
+  const void* coef;         // [rows][coef_row_stride] scalars
+  int64_t coef_row_stride;
+  double* meas;             // [rows][n_meas][tiles] partial sums
+};
+// Launch every pass of P on states A (and B) on stream st, without synchronising
+// (timed: each launch is recorded for qsim_timing_get when timing is on).
+int enqueue_dense_passes(qsim_ctx* ctx, const Plan& P, const DenseBufs& b, int rows, int c128, void* A, void* B,
+                         hipStream_t st, bool timed);
 // Run a dense plan on states A (and B) with 'rows' rows; coefficients from params.
 int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params, int rows,
               int c128, void* A, void* B, hipStream_t st, double* out_host);
@@ -220,6 +234,10 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
 // <H> and its gradient from a gradient cone plan (one parameter row).
 int run_cone_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params,
                   int c128, hipStream_t st, double* E_host, double* grad_host);
+
+// Device address of the fixed working memory of qsim_expect_circuit_noalloc on
+// 'device' (current), taken once per device; the stored status on later calls.
+hipError_t noalloc_setup(int device);
 
 // Launch bracketing for qsim_timing_*: returns the record index or -1.
 int timing_begin(qsim_ctx* ctx, hipStream_t st, double bytes, int flags, int kind, double flops = 0);

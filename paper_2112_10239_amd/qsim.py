@@ -77,6 +77,7 @@ EXPORTS = [
     "qsim_server_stats_get", "qsim_timing_enable", "qsim_timing_get", "qsim_poll_timed", "qsim_clock",
     "qsim_copy_probe", "qsim_expect_grad_cones", "qsim_reduced_density", "qsim_plan_passes", "qsim_expect_terms",
     "qsim_coef_rows",
+    "qsim_expect_circuit_noalloc",
 ]
 
 
@@ -113,6 +114,7 @@ def _load():
         "qsim_plan_dense": (I, [P(Circuit), P(Hamiltonian), I, P(ctypes.c_int64), P(ctypes.c_int32), I]),
         "qsim_plan_passes": (I, [V, P(Circuit), P(Hamiltonian), I, I, P(ctypes.c_int32), I, P(I)]),
         "qsim_coef_rows": (I, [V, P(Circuit), V, I, I, I, V, ctypes.c_uint64, P(ctypes.c_uint64)]),
+        "qsim_expect_circuit_noalloc": (I, [V, P(Circuit), V, I, I, P(Hamiltonian), I, V, ctypes.c_uint64, V, P(D)]),
         "qsim_submit": (I, [V, P(Request), P(ctypes.c_uint64)]),
         "qsim_poll": (I, [V, ctypes.c_uint64, P(D), P(D)]),
         "qsim_cancel": (I, [V, ctypes.c_uint64]),
@@ -347,6 +349,24 @@ class Context:
         if keep:
             return val, State._wrap(self, kp, circ.n, rows, dtype)
         return val
+
+    def expect_circuit_noalloc(self, circ, H, theta, state, dtype: int = C64, stream=None):
+        """Dense <H> through the allocation-free entry point: state is a caller device
+        buffer (a contiguous torch tensor on the context's GPU, batch * 2^n complex of
+        dtype) that holds the final states on return.  theta [P] or [B, P] as in
+        expect_circuit.  Returns a float for theta [P], else an array [B]."""
+        tp, rows, dev, _hold, single = _param_args(theta, circ.n_params)
+        if dev and stream is None:  # read the parameters in order after the work that wrote them
+            stream = _torch_stream(_hold)
+        if not (_is_device_tensor(state) and state.is_contiguous()):
+            raise ValueError("state must be a contiguous device tensor")
+        nbytes = state.numel() * state.element_size()
+        cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
+        out = np.zeros(rows)
+        rc = lib.qsim_expect_circuit_noalloc(self.ptr, ctypes.byref(cc.c), tp, rows, dev, ctypes.byref(ch.h), dtype,
+                                             ctypes.c_void_p(state.data_ptr()), nbytes, stream, _dptr(out))
+        self._check(rc, "qsim_expect_circuit_noalloc")
+        return float(out[0]) if single else out
 
     def expect_terms(self, circ, H, theta, mode: int = MODE_AUTO, dtype: int = C64, stream=None):
         """<P_t> per term (coefficients not applied): [T] for theta [P], [B, T] for [B, P]."""
