@@ -391,6 +391,8 @@ def main():
     ap.add_argument("--serving", type=float, default=1.0, help="seconds of Poisson arrivals (0 = skip serving)")
     ap.add_argument("--counter-run", action="store_true",
                     help="short run for HBM byte counters: one 8 GiB reference copy, then one dense evaluation")
+    ap.add_argument("--only", choices=["lightcone", "gradient", "lightcone_gradient", "density", "small_c128"],
+                    help="run one secondary workload alone (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported by this build "
@@ -399,6 +401,11 @@ def main():
     import paper_2112_10239_amd as Q
     import workloads as W
 
+    if args.only:
+        fn = {"lightcone": bench_lightcone, "gradient": bench_grad, "lightcone_gradient": bench_lightcone_grad,
+              "density": bench_density, "small_c128": bench_small}[args.only]
+        print(json.dumps({args.only: fn(Q, W)}), flush=True)
+        return
     if args.counter_run:
         ctx = Q.Context(0)
         ms = ctx.copy_probe(8 << 30, reps=1)
