@@ -123,6 +123,7 @@ typedef struct {
 #define QSIM_OFF_PRODUCT 16   /* leading single-qubit gates folded into a product start state */
 #define QSIM_OFF_PREFETCH 32  /* register prefetch of the next tile */
 #define QSIM_OFF_IO_REGS 64   /* load/store stages may hold the always-local low bits in registers */
+#define QSIM_OFF_BATCH_PROBES 128  /* adjoint: inverse phases as one table, gradient probes in groups */
 
 typedef struct qsim_ctx qsim_ctx;
 typedef struct qsim_state qsim_state;

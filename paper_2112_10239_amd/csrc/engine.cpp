@@ -99,6 +99,8 @@ static double pass_flops_per_amp(const Plan& P, const PassDesc& pd) {
         case OP_MEAS_ZS: f += 3 + 2.0 * op.slot; o += op.slot; break;
         case OP_MEAS_F: f += 4; break;
         case OP_GRAD_X: case OP_GRAD_Y: case OP_GRAD_Z: f += 4; break;
+        case OP_PTAB: f += 6; break;
+        case OP_GZS: case OP_GXYS: f += 4.0 * op.slot; o += op.slot; break;
         case OP_H_Z: case OP_H_F: f += 4; break;
         default: break;
       }
@@ -166,6 +168,7 @@ PlanOptions dual_options(const qsim_options& co, int c128) {
   o.r = c128 ? 3 : 4;
   o.c_low = std::min(6, std::max(3, opt_int(co.dual_coalesce_bits, "QSIM_DUAL_CLOW", 6)));
   o.fuse = false;
+  o.batch_probes = !opt_off(co, QSIM_OFF_BATCH_PROBES, "QSIM_BATCH_PROBES", true);
   return o;
 }
 
@@ -588,8 +591,28 @@ struct ConePacker {
       st.op_end += ob;
       all.stages.push_back(st);
     }
-    std::vector<int> remap(slots.size());
+    std::vector<int> remap(slots.size(), -1);
     for (size_t k = 0; k < slots.size(); ++k) {
+      if (remap[k] >= 0) continue;
+      if (slots[k].kind == PG_TAB) {
+        // a table block: kTabSlots consecutive chunks whose sources are member
+        // slots (listed earlier); kept consecutive, shared by member slots
+        std::vector<int> mem;
+        for (int m : slots[k].srcs) mem.push_back(m >= 0 ? remap[m] : -1);
+        auto key = std::make_tuple((int)PG_TAB, false, mem);
+        auto it = slot_id.find(key);
+        if (it == slot_id.end()) {
+          it = slot_id.emplace(key, (int)all.slots.size()).first;
+          for (int chunk = 0; chunk < kTabSlots; ++chunk) {
+            PGate t = slots[k + chunk];
+            t.srcs = mem;
+            t.slot = (int)all.slots.size();
+            all.slots.push_back(t);
+          }
+        }
+        for (int chunk = 0; chunk < kTabSlots; ++chunk) remap[k + chunk] = it->second + chunk;
+        continue;
+      }
       auto key = std::make_tuple(slots[k].kind, slots[k].inverse, slots[k].srcs);
       auto it = slot_id.find(key);
       if (it == slot_id.end()) {
@@ -598,10 +621,17 @@ struct ConePacker {
       }
       remap[k] = it->second;
     }
-    for (DevOp op : cp.ops) {
-      if (op.type == OP_U || op.type == OP_RY || op.type == OP_PHASE) op.slot = remap[op.slot];
+    for (size_t k = 0; k < cp.ops.size(); ++k) {
+      DevOp op = cp.ops[k];
+      if (op.type == OP_U || op.type == OP_RY || op.type == OP_PHASE || op.type == OP_PTAB) op.slot = remap[op.slot];
       if (op.type == OP_GRAD_X || op.type == OP_GRAD_Y || op.type == OP_GRAD_Z) op.slot += gb;
       all.ops.push_back(op);
+      if (op.type == OP_GZS || op.type == OP_GXYS)  // probe records: gradient slots
+        for (int t = 0; t < op.slot; ++t) {
+          DevOp rec = cp.ops[++k];
+          rec.slot += gb;
+          all.ops.push_back(rec);
+        }
     }
     for (int g = 0; g < cp.n_gslots; ++g) {
       all.gslot_param.push_back(cp.gslot_param[g]);
@@ -674,8 +704,9 @@ struct ConePacker {
       adjoint_pgates(sub, apg, aslots, gsp);
       to_circuit_gates(apg);
       to_circuit_gates(aslots);
+      ap.slots = aslots;  // table blocks of the adjoint plan are appended after these
       if (plan_adjoint(s_eff, apg, base, ap, err)) return QSIM_EINVAL;
-      append(ap, aslots, cone);
+      append(ap, ap.slots, cone);
     }
     cd.pass_end = (int)all.passes.size();
     dp.cones.push_back(cd);

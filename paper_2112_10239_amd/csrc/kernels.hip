@@ -876,6 +876,10 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         o += R;
       } else if (!DUAL && R <= 4 && std::is_same<T, float>::value && type == OP_DTAB) {
         ap_table<T, R>(a, coef + (int64_t)op->slot * 8 + 32);
+      } else if (R <= 4 && type == OP_PTAB) {
+        const kptr<T> d = coef + (int64_t)op->slot * 8;
+        ap_table<T, R>(a, d);
+        if constexpr (DUAL) ap_table<T, R>(b, d);
       } else if (type == OP_PHASE) {
         kptr<T> d = coef + (int64_t)op->slot * 8;
         const BitSel c = mkbit(ck, cb, tl, base);
@@ -955,6 +959,72 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
           }
           const T w = wave_sum(v);
           if (lane == 0) gacc[wave * gcount + (op->slot - gbegin)] += (double)w;
+        } else if (type == OP_GZS) {
+          // Z probes of up to 4 qubits on the same states: with w_i = Im(conj(b_i) a_i),
+          // a register-bit probe is the Walsh coefficient W[1 << j] of w over the
+          // register index, a thread- or tile-bit probe is +-W[0]
+          T wt[NR];
+#pragma unroll
+          for (int i = 0; i < NR; ++i) wt[i] = b[i].x * a[i].y - b[i].y * a[i].x;
+#pragma unroll
+          for (int bb = 0; bb < R; ++bb) {
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+              if (i & (1 << bb)) continue;
+              const T x = wt[i], y = wt[i | (1 << bb)];
+              wt[i] = x + y;
+              wt[i | (1 << bb)] = x - y;
+            }
+          }
+          const int nt = op->slot;
+          T v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            v[k] = 0;
+            if (k < nt) {
+              const uint32_t wr = *(kptr<uint32_t>)(OPS + o + 1 + k);
+              const uint32_t rk = (wr >> 16) & 0xffu, rbit = wr >> 24;
+              if (rk == BK_REG) {
+                for_bit<R>((int)rbit, [&](auto JC) __attribute__((always_inline)) {
+                  v[k] = wt[1 << decltype(JC)::value];
+                });
+              } else {
+                v[k] = mkbit(rk, rbit, tl, base).val ? -wt[0] : wt[0];
+              }
+            }
+          }
+          T tot[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) tot[k] = wave_sum(v[k]);
+          if (lane == 0)
+            for (int k = 0; k < nt; ++k)
+              gacc[wave * gcount + ((OPS + o + 1 + k)->slot - gbegin)] += (double)tot[k];
+          o += nt;
+        } else if (type == OP_GXYS) {
+          // X and Y probes on up to 4 register bits on the same states
+          const int nt = op->slot;
+          T v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            v[k] = 0;
+            if (k < nt) {
+              const uint32_t w0 = *(kptr<uint32_t>)(OPS + o + 1 + k), w1 = *((kptr<uint32_t>)(OPS + o + 1 + k) + 1);
+              const int rj = (int)((w0 >> 8) & 0xffu);
+              const bool isy = ((w1 >> 16) & 0xffu) != 0u;
+              for_bit<R>(rj, [&](auto JC) __attribute__((always_inline)) {
+                constexpr int J = decltype(JC)::value;
+                if (isy) v[k] = grad_y<T, R, J>(a, b);
+                else v[k] = grad_x<T, R, J>(a, b);
+              });
+            }
+          }
+          T tot[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) tot[k] = wave_sum(v[k]);
+          if (lane == 0)
+            for (int k = 0; k < nt; ++k)
+              gacc[wave * gcount + ((OPS + o + 1 + k)->slot - gbegin)] += (double)tot[k];
+          o += nt;
         }
       }
     }

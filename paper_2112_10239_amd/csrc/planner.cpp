@@ -364,6 +364,7 @@ struct PassEmitter {
   bool allow_fused_bits = false;  // OP_UALL / OP_RYALL (single-state kernels with r <= 4 only)
   bool allow_factored = false;    // OP_UTAB (single-state float kernels with r <= 4 only)
   int io_lo = -1;                 // see PlanOptions::io_lo
+  bool batch_probes = false;      // adjoint sweeps: diagonals and probes regrouped (see emit)
   bool allow_entry = false;       // fold a permute-only first stage into the loads
   bool allow_exit = false;        // apply the last stage's CNOT run in the store addresses
 
@@ -816,8 +817,123 @@ struct PassEmitter {
       }
       st.op_begin = (int)plan.ops.size();
       const auto& its = sb[si].items;
+      auto record_order = [&](const PGate* h, int at) {
+        for (int src : h->srcs) {
+          plan.order.push_back(pass_no);
+          plan.order.push_back(si);
+          plan.order.push_back(at);
+          plan.order.push_back(src);
+        }
+      };
+      // gradient probes in groups of up to four (OP_GZS / OP_GXYS + records)
+      auto emit_probes = [&](const std::vector<const PGate*>& probes, bool zgen) {
+        for (size_t k0 = 0; k0 < probes.size(); k0 += 4) {
+          const size_t k1 = std::min(probes.size(), k0 + 4);
+          DevOp head;
+          std::memset(&head, 0, sizeof(head));
+          head.type = zgen ? OP_GZS : OP_GXYS;
+          head.slot = (int)(k1 - k0);
+          const int at = (int)plan.ops.size() - st.op_begin;
+          plan.ops.push_back(head);
+          for (size_t k = k0; k < k1; ++k) {
+            const PGate* h = probes[k];
+            DevOp rec = to_devop(*h, rb);
+            rec.type = OP_NONE;
+            rec.ph = h->gen == 'Y' ? 1 : 0;
+            rec.slot = plan.n_gslots++;
+            gmin = std::min(gmin, rec.slot);
+            ++gcount;
+            plan.gslot_param.push_back(h->slot);  // a probe's slot field holds its parameter index
+            plan.ops.push_back(rec);
+            record_order(h, at);
+          }
+        }
+      };
       for (size_t ii = 0; ii < its.size(); ++ii) {
         const PGate* g = its[ii];
+        // Adjoint sweep on two states.  A run of diagonal items (inverse phases,
+        // CZ) and Z-generator probes: the diagonals first, register-bit phases on
+        // distinct bits as one table over the register index, then the probes.
+        // Both states receive the same diagonal unitary D, and D commutes with Z,
+        // so <D lambda|Z|D psi> = <lambda|Z|psi> wherever a probe is taken.
+        auto zrun = [&](const PGate* h) {
+          return (h->kind == PG_GRAD && h->gen == 'Z') || (h->kind == PG_PHASE && h->q2 < 0) || h->kind == PG_CZ;
+        };
+        if (batch_probes && r <= 4 && zrun(g)) {
+          size_t jj = ii;
+          while (jj < its.size() && zrun(its[jj])) ++jj;
+          std::vector<const PGate*> reg_ph(r, nullptr), others, probes;
+          for (size_t k = ii; k < jj; ++k) {
+            const PGate* h = its[k];
+            if (h->kind == PG_GRAD) {
+              probes.push_back(h);
+            } else if (h->kind == PG_PHASE) {
+              const BitRef b = bitref(h->q, rb);
+              if (b.kind == BK_REG && !reg_ph[b.idx]) reg_ph[b.idx] = h;
+              else others.push_back(h);
+            } else {
+              others.push_back(h);
+            }
+          }
+          bool any_reg = false;
+          for (const PGate* h : reg_ph) any_reg |= h != nullptr;
+          if (any_reg) {
+            DevOp head;
+            std::memset(&head, 0, sizeof(head));
+            head.type = OP_PTAB;
+            head.slot = (int)plan.slots.size();
+            PGate tab;
+            tab.kind = PG_TAB;
+            tab.q = r;
+            for (int j = 0; j < r; ++j) tab.srcs.push_back(reg_ph[j] ? reg_ph[j]->slot : -1);
+            for (int chunk = 0; chunk < kTabSlots; ++chunk) {
+              tab.gen = chunk;
+              tab.slot = (int)plan.slots.size();
+              plan.slots.push_back(tab);
+            }
+            const int at = (int)plan.ops.size() - st.op_begin;
+            plan.ops.push_back(head);
+            for (const PGate* h : reg_ph)
+              if (h) record_order(h, at);
+          }
+          for (const PGate* h : others) {
+            record_order(h, (int)plan.ops.size() - st.op_begin);
+            plan.ops.push_back(to_devop(*h, rb));
+          }
+          emit_probes(probes, true);
+          ii = jj - 1;
+          continue;
+        }
+        // A run of X/Y-generator probes and uncontrolled rotations on register
+        // bits, where no probe follows a rotation on its own qubit: the probes
+        // first, then the rotations in their order.  A rotation on another qubit
+        // commutes with the probe's Pauli.
+        auto xyrun = [&](const PGate* h) {
+          if (h->q < 0 || h->q2 >= 0 || bitref(h->q, rb).kind != BK_REG) return false;
+          return (h->kind == PG_GRAD && h->gen != 'Z') || h->kind == PG_RY || h->kind == PG_U;
+        };
+        if (batch_probes && xyrun(g) && g->kind == PG_GRAD) {
+          size_t jj = ii;
+          std::vector<int> rotated;  // qubits rotated so far in the run
+          while (jj < its.size() && xyrun(its[jj])) {
+            const PGate* h = its[jj];
+            if (h->kind == PG_GRAD) {
+              if (std::find(rotated.begin(), rotated.end(), h->q) != rotated.end()) break;
+            } else {
+              rotated.push_back(h->q);
+            }
+            ++jj;
+          }
+          std::vector<const PGate*> probes, rots;
+          for (size_t k = ii; k < jj; ++k) (its[k]->kind == PG_GRAD ? probes : rots).push_back(its[k]);
+          emit_probes(probes, false);
+          for (const PGate* h : rots) {
+            record_order(h, (int)plan.ops.size() - st.op_begin);
+            plan.ops.push_back(to_devop(*h, rb));
+          }
+          ii = jj - 1;
+          continue;
+        }
         // a run of uncontrolled rotations on distinct register bits that ends the
         // stage's ops (they commute): one factored op, U_j = X^f P_j T_j E_j with
         // diagonal P_j, E_j, a real T_j of two multiply-adds per amplitude and a
@@ -1205,6 +1321,7 @@ int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, P
     if (p != np - 1) flags |= PF_STORE_A | PF_STORE_B;
     PassEmitter em(plan, n, m, r, Ls[p]);
     em.allow_absorb = o.absorb;
+    em.batch_probes = o.batch_probes;
     std::vector<const PGate*> mod;
     for (int idx : lists[p]) mod.push_back(&gates[idx]);
     em.emit(mod, {}, flags, c_low, p);

@@ -100,6 +100,8 @@ struct PlanOptions {
   bool entry_perm = true;  // with factored: a permute-only first stage folded into the loads
   bool exit_perm = true;   // with factored: the last stage's CNOT run folded into the stores
   bool init_factors = true;  // with factored and init: leading single-qubit gates folded into the start state
+  bool batch_probes = false;  // adjoint plans: diagonals as tables and probes in groups (OP_PTAB,
+                              // OP_GZS, OP_GXYS)
   bool factored = false;  // runs of uncontrolled rotations on register bits as one OP_UTAB
                           // (single-state float kernels with r <= 4; needs plan.slots)
 };

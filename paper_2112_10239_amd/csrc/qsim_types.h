@@ -40,6 +40,12 @@ enum OpType : uint8_t {
                   // in planner.h); slot = first of the block's coefficient slots; no records follow;
                   // always the last op of its stage (its register swaps go to the stage's exit)
   OP_DTAB = 17,   // the pre table of the OP_UTAB that follows (same slot)
+  OP_PTAB = 18,   // diagonal over the register index, a_i *= d_i (and b_i in dual kernels): the post table
+                  // of a PG_TAB block whose members are diagonal gates (slot = the block's first slot)
+  OP_GZS = 19,    // Z-generator probes on the same states: the next 'slot' ops (at most 4) are records
+                  // (ck, cb: the qubit's bit; slot: gradient slot); g += Im sum_i conj(b_i) (-1)^{bit(i)} a_i
+  OP_GXYS = 20,   // X/Y-generator probes on register bits: the next 'slot' ops (at most 4) are records
+                  // (j: register bit; ph: 0 for X, 1 for Y; slot: gradient slot), as OP_GRAD_X / OP_GRAD_Y
 };
 
 // Bit reference kinds for controls, diagonal bits and z-masks.
