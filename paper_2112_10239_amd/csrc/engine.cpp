@@ -99,7 +99,7 @@ static double pass_flops_per_amp(const Plan& P, const PassDesc& pd) {
         case OP_MEAS_ZS: f += 3 + 2.0 * op.slot; o += op.slot; break;
         case OP_MEAS_F: f += 4; break;
         case OP_GRAD_X: case OP_GRAD_Y: case OP_GRAD_Z: f += 4; break;
-        case OP_PTAB: f += 6; break;
+        case OP_PTAB: f += 6; o += op.j; break;
         case OP_GZS: case OP_GXYS: f += 4.0 * op.slot; o += op.slot; break;
         case OP_H_Z: case OP_H_F: f += 4; break;
         default: break;
@@ -164,8 +164,8 @@ PlanOptions cone_options(const qsim_options& co, int c128) {
 PlanOptions dual_options(const qsim_options& co, int c128) {
   PlanOptions o;
   o.absorb = !opt_off(co, QSIM_OFF_ABSORB, "QSIM_ABSORB", true);
-  o.m_max = c128 ? 12 : 13;
-  o.r = c128 ? 3 : 4;
+  o.m_max = c128 ? 12 : std::min(13, std::max(12, env_int("QSIM_DUAL_M", 13)));
+  o.r = c128 ? 3 : std::min(4, std::max(3, env_int("QSIM_DUAL_R", 4)));
   o.c_low = std::min(6, std::max(3, opt_int(co.dual_coalesce_bits, "QSIM_DUAL_CLOW", 6)));
   o.fuse = false;
   o.batch_probes = !opt_off(co, QSIM_OFF_BATCH_PROBES, "QSIM_BATCH_PROBES", true);
@@ -623,13 +623,20 @@ struct ConePacker {
     }
     for (size_t k = 0; k < cp.ops.size(); ++k) {
       DevOp op = cp.ops[k];
-      if (op.type == OP_U || op.type == OP_RY || op.type == OP_PHASE || op.type == OP_PTAB) op.slot = remap[op.slot];
+      if (op.type == OP_U || op.type == OP_RY || op.type == OP_PHASE || (op.type == OP_PTAB && op.slot >= 0))
+        op.slot = remap[op.slot];
       if (op.type == OP_GRAD_X || op.type == OP_GRAD_Y || op.type == OP_GRAD_Z) op.slot += gb;
       all.ops.push_back(op);
       if (op.type == OP_GZS || op.type == OP_GXYS)  // probe records: gradient slots
         for (int t = 0; t < op.slot; ++t) {
           DevOp rec = cp.ops[++k];
           rec.slot += gb;
+          all.ops.push_back(rec);
+        }
+      if (op.type == OP_PTAB)  // phase records: coefficient slots
+        for (int t = 0; t < (int)op.j; ++t) {
+          DevOp rec = cp.ops[++k];
+          rec.slot = remap[rec.slot];
           all.ops.push_back(rec);
         }
     }
@@ -1003,7 +1010,7 @@ int run_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& hp, const DevPlan& ap,
     L.rows = rows;
     L.c128 = c128;
     L.dual = 1;
-    L.prefetch = 0;
+    L.prefetch = env_int("QSIM_DUAL_PF", 1);
     return L;
   };
   const int64_t tiles = 1ll << (P.n - P.m);

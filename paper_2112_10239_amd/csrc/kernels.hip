@@ -400,13 +400,21 @@ __device__ __forceinline__ void h_f(const cpx<T>* a, cpx<T>* b, T c, uint32_t rz
 }
 
 // Im sum_i conj(b_i) (P a)_i for P = X, Y on register bit J, or Z on a bit.
+// Probes accumulate as chains of multiply-adds (one per real product).
+template <class T>
+__device__ __forceinline__ T fma_t(T x, T y, T z) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(x, y, z);
+  else return __builtin_fma(x, y, z);
+}
+
 template <class T, int R, int J>
 __device__ __forceinline__ T grad_x(const cpx<T>* a, const cpx<T>* b) {
   T s = 0;
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
     const cpx<T> p = a[i ^ (1 << J)];
-    s += b[i].x * p.y - b[i].y * p.x;
+    s = fma_t<T>(b[i].x, p.y, s);
+    s = fma_t<T>(-b[i].y, p.x, s);
   }
   return s;
 }
@@ -418,8 +426,9 @@ __device__ __forceinline__ T grad_y(const cpx<T>* a, const cpx<T>* b) {
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
     const cpx<T> p = a[i ^ (1 << J)];
-    const T re = b[i].x * p.x + b[i].y * p.y;
-    s += ((i >> J) & 1) ? re : -re;
+    const T sg = ((i >> J) & 1) ? T(1) : T(-1);
+    s = fma_t<T>(sg * b[i].x, p.x, s);
+    s = fma_t<T>(sg * b[i].y, p.y, s);
   }
   return s;
 }
@@ -877,9 +886,44 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
       } else if (!DUAL && R <= 4 && std::is_same<T, float>::value && type == OP_DTAB) {
         ap_table<T, R>(a, coef + (int64_t)op->slot * 8 + 32);
       } else if (R <= 4 && type == OP_PTAB) {
-        const kptr<T> d = coef + (int64_t)op->slot * 8;
-        ap_table<T, R>(a, d);
-        if constexpr (DUAL) ap_table<T, R>(b, d);
+        // the per-thread factor of the thread- and tile-bit phases, then one
+        // complex product per amplitude with the register table times that factor
+        T fr = 1, fi = 0;
+        const int nrec = (int)opj;
+        for (int k = 1; k <= nrec; ++k) {
+          const uint32_t wr = *(kptr<uint32_t>)(OPS + o + k);
+          const kptr<T> c = coef + (int64_t)(OPS + o + k)->slot * 8;
+          const bool one = mkbit((wr >> 16) & 0xffu, wr >> 24, tl, base).val != 0u;
+          const T dr = one ? c[2] : c[0], di = one ? c[3] : c[1];
+          const T xr = fr * dr - fi * di;
+          fi = fr * di + fi * dr;
+          fr = xr;
+        }
+        const int tslot = op->slot;
+        const bool lane_f = nrec > 0;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          T tr = fr, ti = fi;
+          if (tslot >= 0) {
+            const kptr<T> d = coef + (int64_t)tslot * 8;
+            if (lane_f) {
+              tr = d[2 * i] * fr - d[2 * i + 1] * fi;
+              ti = d[2 * i] * fi + d[2 * i + 1] * fr;
+            } else {
+              tr = d[2 * i];
+              ti = d[2 * i + 1];
+            }
+          }
+          const cpx<T> x = a[i];
+          a[i].x = tr * x.x - ti * x.y;
+          a[i].y = tr * x.y + ti * x.x;
+          if constexpr (DUAL) {
+            const cpx<T> y = b[i];
+            b[i].x = tr * y.x - ti * y.y;
+            b[i].y = tr * y.y + ti * y.x;
+          }
+        }
+        o += nrec;
       } else if (type == OP_PHASE) {
         kptr<T> d = coef + (int64_t)op->slot * 8;
         const BitSel c = mkbit(ck, cb, tl, base);
@@ -1492,6 +1536,7 @@ hipError_t launch_pass_r(const PassLaunch& L, hipStream_t stream) {
       return launch_pass_t<T, 3, DUAL, false>(L, stream);
     case 4:
       if constexpr (DUAL && sizeof(T) == 8) return hipErrorInvalidValue;
+      else if (DUAL && !L.prefetch) return launch_pass_t<T, 4, DUAL, false>(L, stream);
       else return launch_pass_t<T, 4, DUAL, DUAL && sizeof(T) == 4>(L, stream);
     case 5:
       if constexpr (DUAL || sizeof(T) == 8) return hipErrorInvalidValue;

@@ -862,7 +862,7 @@ struct PassEmitter {
         if (batch_probes && r <= 4 && zrun(g)) {
           size_t jj = ii;
           while (jj < its.size() && zrun(its[jj])) ++jj;
-          std::vector<const PGate*> reg_ph(r, nullptr), others, probes;
+          std::vector<const PGate*> reg_ph(r, nullptr), lane_ph, others, probes;
           for (size_t k = ii; k < jj; ++k) {
             const PGate* h = its[k];
             if (h->kind == PG_GRAD) {
@@ -870,6 +870,7 @@ struct PassEmitter {
             } else if (h->kind == PG_PHASE) {
               const BitRef b = bitref(h->q, rb);
               if (b.kind == BK_REG && !reg_ph[b.idx]) reg_ph[b.idx] = h;
+              else if (b.kind != BK_REG && lane_ph.size() < 255) lane_ph.push_back(h);
               else others.push_back(h);
             } else {
               others.push_back(h);
@@ -877,24 +878,34 @@ struct PassEmitter {
           }
           bool any_reg = false;
           for (const PGate* h : reg_ph) any_reg |= h != nullptr;
-          if (any_reg) {
+          if (any_reg || !lane_ph.empty()) {
             DevOp head;
             std::memset(&head, 0, sizeof(head));
             head.type = OP_PTAB;
-            head.slot = (int)plan.slots.size();
-            PGate tab;
-            tab.kind = PG_TAB;
-            tab.q = r;
-            for (int j = 0; j < r; ++j) tab.srcs.push_back(reg_ph[j] ? reg_ph[j]->slot : -1);
-            for (int chunk = 0; chunk < kTabSlots; ++chunk) {
-              tab.gen = chunk;
-              tab.slot = (int)plan.slots.size();
-              plan.slots.push_back(tab);
+            head.slot = -1;
+            head.j = (uint8_t)lane_ph.size();
+            if (any_reg) {
+              head.slot = (int)plan.slots.size();
+              PGate tab;
+              tab.kind = PG_TAB;
+              tab.q = r;
+              for (int j = 0; j < r; ++j) tab.srcs.push_back(reg_ph[j] ? reg_ph[j]->slot : -1);
+              for (int chunk = 0; chunk < kTabSlots; ++chunk) {
+                tab.gen = chunk;
+                tab.slot = (int)plan.slots.size();
+                plan.slots.push_back(tab);
+              }
             }
             const int at = (int)plan.ops.size() - st.op_begin;
             plan.ops.push_back(head);
             for (const PGate* h : reg_ph)
               if (h) record_order(h, at);
+            for (const PGate* h : lane_ph) {  // records: the phase's bit and coefficient slot
+              DevOp rec = to_devop(*h, rb);
+              rec.type = OP_NONE;
+              plan.ops.push_back(rec);
+              record_order(h, at);
+            }
           }
           for (const PGate* h : others) {
             record_order(h, (int)plan.ops.size() - st.op_begin);

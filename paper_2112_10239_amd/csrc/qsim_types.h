@@ -40,8 +40,10 @@ enum OpType : uint8_t {
                   // in planner.h); slot = first of the block's coefficient slots; no records follow;
                   // always the last op of its stage (its register swaps go to the stage's exit)
   OP_DTAB = 17,   // the pre table of the OP_UTAB that follows (same slot)
-  OP_PTAB = 18,   // diagonal over the register index, a_i *= d_i (and b_i in dual kernels): the post table
-                  // of a PG_TAB block whose members are diagonal gates (slot = the block's first slot)
+  OP_PTAB = 18,   // diagonal phases on both states: a_i *= d_i f (and b_i in dual kernels) with d the post
+                  // table of a PG_TAB block whose members are diagonal gates on register bits (slot = the
+                  // block's first slot; -1: none) and f the per-thread product of the phases of the next
+                  // 'j' ops, records of diagonal gates on thread or tile bits (ck, cb; slot: d0, d1)
   OP_GZS = 19,    // Z-generator probes on the same states: the next 'slot' ops (at most 4) are records
                   // (ck, cb: the qubit's bit; slot: gradient slot); g += Im sum_i conj(b_i) (-1)^{bit(i)} a_i
   OP_GXYS = 20,   // X/Y-generator probes on register bits: the next 'slot' ops (at most 4) are records
