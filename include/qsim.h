@@ -261,10 +261,13 @@ int qsim_lightcone_sets(const qsim_circuit* c, const qsim_hamiltonian* H, int32_
 /* Plan summary for a dense evaluation on the host (no device use): passes,
  * stages and ops that the given options produce.  info[0] = passes, info[1] =
  * stages, info[2] = device ops, info[3] = measurement passes.  If 'order' is not
- * NULL it receives, for every gate of c in execution order, (pass, stage, gate
- * index) triples; cap_triples bounds it. */
+ * NULL it receives, for every gate of c in execution order, (pass, stage, op,
+ * gate index) quadruples of int32 (op: the op's index within its stage; -1 for a
+ * CNOT folded into the loads); cap_entries bounds the number of quadruples (the
+ * buffer holds 4 * cap_entries int32), and QSIM_ETOOBIG is returned, writing
+ * nothing, when the plan has more. */
 int qsim_plan_dense(const qsim_circuit* c, const qsim_hamiltonian* H, int dtype, int64_t* info, int32_t* order,
-                    int cap_triples);
+                    int cap_entries);
 
 /* Passes that qsim_expect_circuit launches for (c, H) in dense mode on ctx (with
  * keep != 0: the variant that stores the final state), as 8 int32 per pass:

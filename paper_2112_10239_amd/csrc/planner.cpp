@@ -1011,8 +1011,12 @@ struct PassEmitter {
           bool full = true;
           for (int k = 0; k < r && full; ++k) {
             const PGate* h = its[ii + k];
+            if (h->kind != g->kind || h->q2 >= 0) {  // (terms have no qubit: check the kind first)
+              full = false;
+              break;
+            }
             const BitRef b = bitref(h->q, rb);
-            if (h->kind != g->kind || h->q2 >= 0 || b.kind != BK_REG || slot_of[b.idx] >= 0) full = false;
+            if (b.kind != BK_REG || slot_of[b.idx] >= 0) full = false;
             else slot_of[b.idx] = (int)(ii + k);
           }
           if (full) {
