@@ -324,9 +324,10 @@ int qsim_copy_probe(qsim_ctx* ctx, uint64_t bytes, int reps, double* ms);
  * work), where many objective evaluations (Sec. 1: expectation values, with
  * their gradients for the classical optimiser) are requested at once.  These
  * calls accept such requests from any thread and share the device between
- * them: requests are admitted in arrival order while their state memory,
- * (1 + want_grad) * 2^n * 8 bytes plus partial sums, fits the context's
- * hbm_budget_bytes; every running request advances one pass per scheduler step
+ * them: requests are admitted in arrival order while their device memory
+ * (states, (1 + want_grad) * 2^n * 8 bytes, plus plan descriptors, coefficients,
+ * partial sums and results) fits the context's hbm_budget_bytes; every running
+ * request advances one pass per scheduler step
  * in multi-request launches; results do not depend on what else is running. */
 
 typedef struct {
@@ -341,6 +342,8 @@ typedef struct {
     uint64_t submitted, completed, rejected, cancelled, failed;
     uint64_t steps, launches, inflight_bytes, peak_inflight_bytes;
     uint64_t queued, running;
+    uint64_t pool_outstanding_bytes;  /* device blocks handed out to admitted requests now */
+    uint64_t accounting_violations;   /* admissions after which those blocks exceeded inflight_bytes (0) */
 } qsim_server_stats;
 
 /* Enqueue a request (deep copy of the circuit, H and parameters; complex64 dense
@@ -362,8 +365,11 @@ double qsim_clock(void);
  * ENOTFOUND for an unknown or consumed ticket.  Thread-safe. */
 int qsim_cancel(qsim_ctx* ctx, uint64_t ticket);
 /* Counters of the serving loop since the context was created (requests by
- * outcome, scheduler steps and launches, state bytes in flight now and at peak,
- * requests queued and running now).  Thread-safe. */
+ * outcome, scheduler steps and launches, device bytes in flight now and at
+ * peak, requests queued and running now).  A request's footprint is every
+ * device block it holds while admitted (states, plan descriptors,
+ * coefficients, partial sums, results), computed from its plans at submit.
+ * Thread-safe. */
 int qsim_server_stats_get(qsim_ctx* ctx, qsim_server_stats* out);
 
 #ifdef __cplusplus

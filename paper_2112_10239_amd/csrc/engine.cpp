@@ -84,22 +84,23 @@ static int env_int(const char* name, int dflt) {
 // for a real rotation, 6 for a diagonal phase, 0 for CNOT and CZ (sign or
 // permutation); measurements 3 for |a|^2 once per group, then 2 per diagonal
 // term and 4 per flip term; gradient probes 4; H-apply terms 4.
-static double pass_flops_per_amp(const Plan& P, const PassDesc& pd) {
+static double pass_flops_per_amp(const Plan& P, const PassDesc& pd, bool dual = false) {
+  const double g = dual ? 2.0 : 1.0;  // gate ops of dual-state passes act on both states
   double f = 0;
   for (int s = pd.stage_begin; s < pd.stage_end; ++s) {
     const StageDesc& st = P.stages[s];
     for (int o = st.op_begin; o < st.op_end; ++o) {
       const DevOp& op = P.ops[o];
       switch (op.type) {
-        case OP_U: f += 16; break;
+        case OP_U: f += 16 * g; break;
         case OP_UTAB: f += 4 * P.r + 6; break;  // a real 2x2 per register bit + the post table
         case OP_DTAB: f += 6; break;
-        case OP_RY: f += 8; break;
-        case OP_PHASE: f += 6; break;
+        case OP_RY: f += 8 * g; break;
+        case OP_PHASE: f += 6 * g; break;
         case OP_MEAS_ZS: f += 3 + 2.0 * op.slot; o += op.slot; break;
         case OP_MEAS_F: f += 4; break;
         case OP_GRAD_X: case OP_GRAD_Y: case OP_GRAD_Z: f += 4; break;
-        case OP_PTAB: f += 6; o += op.j; break;
+        case OP_PTAB: f += 6 * g; o += op.j; break;
         case OP_GZS: case OP_GXYS: f += 4.0 * op.slot; o += op.slot; break;
         case OP_H_Z: case OP_H_F: f += 4; break;
         default: break;
@@ -1016,13 +1017,16 @@ int run_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& hp, const DevPlan& ap,
   const int64_t tiles = 1ll << (P.n - P.m);
   const int ns = P.n_gslots;
   if (ns > 0) HIP_TRY(ws.grad.ensure((size_t)rows * ns * tiles * sizeof(double)), "gradient partials");
+  const double amps = (double)rows * (double)(1ull << P.n);
   for (size_t p = 0; p < H.passes.size(); ++p) {
-    const int ti = timing_begin(ctx, st, pass_bytes(H.passes[p], rows, c128), H.passes[p].flags, 0);
+    const int ti = timing_begin(ctx, st, pass_bytes(H.passes[p], rows, c128), H.passes[p].flags, 0,
+                                pass_flops_per_amp(H, H.passes[p], true) * amps);
     HIP_TRY(launch_pass(mk(hp, p), st), "H-apply launch");
     timing_end(ctx, ti, st);
   }
   for (size_t p = 0; p < P.passes.size(); ++p) {
-    const int ti = timing_begin(ctx, st, pass_bytes(P.passes[p], rows, c128), P.passes[p].flags, 0);
+    const int ti = timing_begin(ctx, st, pass_bytes(P.passes[p], rows, c128), P.passes[p].flags, 0,
+                                pass_flops_per_amp(P, P.passes[p], true) * amps);
     HIP_TRY(launch_pass(mk(ap, p), st), "adjoint launch");
     timing_end(ctx, ti, st);
   }
@@ -1094,10 +1098,12 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
   L.r = 4;
   L.c128 = c128;
   L.dual = 0;
-  double cone_bytes = 0;  // only cones above the tile size touch HBM scratch
-  for (const PassDesc& pd : P.passes)
+  double cone_bytes = 0, cone_flops = 0;  // only cones above the tile size touch HBM scratch
+  for (const PassDesc& pd : P.passes) {
     if (pd.n > pd.m) cone_bytes += pass_bytes(pd, 1, c128);
-  const int ti = timing_begin(ctx, st, cone_bytes, 0, 1);
+    cone_flops += pass_flops_per_amp(P, pd) * (double)(1ull << pd.n);
+  }
+  const int ti = timing_begin(ctx, st, cone_bytes, 0, 1, cone_flops);
   HIP_TRY(launch_cones(L, st), "cone launch");
   timing_end(ctx, ti, st);
   HIP_TRY(ws.out.ensure(sizeof(double)), "result buffer");
@@ -1154,9 +1160,13 @@ int run_cone_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const Circuit
   L.r = 4;
   L.c128 = c128;
   L.dual = 1;
-  double bytes = 0;  // psi and lambda through scratch between a cone's passes
-  for (const PassDesc& pd : P.passes) bytes += pass_bytes(pd, 1, c128);
-  const int ti = timing_begin(ctx, st, bytes, PF_GRAD, 1);
+  double bytes = 0, flops = 0;  // psi and lambda through scratch between a cone's passes
+  for (const PassDesc& pd : P.passes) {
+    bytes += pass_bytes(pd, 1, c128);
+    const bool two = (pd.flags & (PF_LOAD_B | PF_STORE_B | PF_ZERO_B)) != 0;
+    flops += pass_flops_per_amp(P, pd, two) * (double)(1ull << pd.n);
+  }
+  const int ti = timing_begin(ctx, st, bytes, PF_GRAD, 1, flops);
   HIP_TRY(launch_cones(L, st), "gradient cone launch");
   timing_end(ctx, ti, st);
   // E = const + sum_t coef_t prod_f v_f; weights w_f = d<H>/d v_f; grad = sum_slots w g

@@ -76,11 +76,13 @@ void* BlockPool::get(size_t bytes) {
     void* p = it->second;
     free_.erase(it);
     cached_ -= bytes;
+    out_ += bytes;
     return p;
   }
   if (mock_) {
     const uintptr_t p = fake_;
     fake_ += (bytes + 255) & ~(size_t)255;
+    out_ += bytes;
     return reinterpret_cast<void*>(p);
   }
   void* p = nullptr;
@@ -92,6 +94,7 @@ void* BlockPool::get(size_t bytes) {
       return nullptr;
     }
   }
+  out_ += bytes;
   return p;
 }
 
@@ -99,6 +102,7 @@ void BlockPool::put(void* p, size_t bytes) {
   if (!p) return;
   free_.emplace(bytes, p);
   cached_ += bytes;
+  out_ -= bytes;
 }
 
 void BlockPool::trim(size_t keep_bytes) {
@@ -170,24 +174,33 @@ Server::~Server() {
   }
 }
 
-static size_t footprint_of(const CircuitDesc& c, const std::vector<Term>& terms, bool grad) {
-  const size_t amps = (size_t)1 << c.n;
-  size_t rot = 0, flips = 0;
-  for (const Gate& g : c.gates) rot += (g.param >= 0);
-  for (const Term& t : terms)
-    for (auto [q, L] : t.ops)
-      if (L != 'Z') {
-        ++flips;
-        break;
-      }
-  const size_t tiles_f = (size_t)1 << std::max(0, c.n - 14);
-  const size_t tiles_d = (size_t)1 << std::max(0, c.n - 13);
-  size_t bytes = (grad ? 2 : 1) * amps * 8;                // psi (+ lambda)
-  bytes += (1 + flips) * tiles_f * 8;                      // measurement partials
-  bytes += c.gates.size() * 32 * (grad ? 2 : 1);           // coefficients
-  if (grad) bytes += rot * tiles_d * 8 + (2 * rot + c.n_params + 1) * 8;  // gradient partials and results
-  else bytes += 8;
-  return bytes;
+// Device bytes of a request while admitted: exactly the blocks admit() takes
+// from the pool (plan descriptors, states, coefficients, partial sums,
+// results), computed from its plans once they are built.
+static void plan_block_sizes(const Plan& p, ReqPlan& d) {
+  d.bp = std::max<size_t>(1, p.passes.size()) * sizeof(PassDesc);
+  d.bs = std::max<size_t>(1, p.stages.size()) * sizeof(StageDesc);
+  d.bo = std::max<size_t>(1, p.ops.size()) * sizeof(DevOp);
+}
+
+static void request_sizes(SReq* r) {
+  const Plan& F = r->fplan;
+  plan_block_sizes(F, r->df);
+  r->state_bytes = ((size_t)1 << r->c.n) * 8;
+  r->cf_bytes = r->coef_f.size() * sizeof(float);
+  r->meas_bytes = std::max<size_t>(1, (size_t)F.n_meas << (F.n - F.m)) * sizeof(double);
+  size_t ns = 0;
+  size_t bytes = r->df.bp + r->df.bs + r->df.bo + r->state_bytes + r->cf_bytes + r->meas_bytes;
+  if (r->want_grad) {
+    const Plan& P = r->ap->plan;
+    ns = P.n_gslots;
+    plan_block_sizes(r->hplan, r->dh);
+    r->ca_bytes = r->coef_a.size() * sizeof(float);
+    r->gpart_bytes = std::max<size_t>(1, ns << (P.n - P.m)) * sizeof(double);
+    bytes += r->dh.bp + r->dh.bs + r->dh.bo + r->state_bytes + r->ca_bytes + r->gpart_bytes;
+  }
+  r->res_bytes = (1 + ns + (size_t)r->c.n_params) * sizeof(double);
+  r->footprint = bytes + r->res_bytes;
 }
 
 int Server::submit(const qsim_request* rq, uint64_t* ticket) {
@@ -206,7 +219,8 @@ int Server::submit(const qsim_request* rq, uint64_t* ticket) {
   }
   r->params.assign(rq->params, rq->params + r->c.n_params);
   r->want_grad = rq->want_grad != 0;
-  r->footprint = footprint_of(r->c, r->terms, r->want_grad);
+  // the states alone bound the footprint from below: reject before planning
+  r->footprint = (r->want_grad ? 2 : 1) * ((size_t)1 << r->c.n) * 8;
   auto admissible = [&]() -> int {
     if (stop_) return QSIM_ESHUTDOWN;
     if (r->footprint > ctx_->opt.hbm_budget_bytes) {
@@ -240,6 +254,7 @@ int Server::submit(const qsim_request* rq, uint64_t* ticket) {
     build_coefficients<float>(r->c, r->ap->plan.slots, r->params.data(), 1, crs_a, r->coef_a.data());
     for (int p : r->ap->plan.gslot_param) r->np_used = std::max(r->np_used, p + 1);
   }
+  request_sizes(r.get());
   std::lock_guard<std::mutex> g(mu_);
   if ((rc = admissible())) return rc;
   r->ticket = next_ticket_++;
@@ -294,6 +309,7 @@ void Server::stats(qsim_server_stats* out) {
   *out = st_;
   out->inflight_bytes = inflight_;
   out->peak_inflight_bytes = peak_;
+  out->pool_outstanding_bytes = pool_.outstanding();
   out->queued = queue_.size();
   out->running = running_.size();
 }
@@ -322,10 +338,8 @@ void* Server::stage_upload(const void* src, size_t bytes, void* dst) {
 
 int Server::admit(SReq* r) {
   r->admitted = true;  // from here on release() gives back whatever was taken
-  auto plan_blocks = [&](const Plan& p, ReqPlan& d) {
-    d.bp = std::max<size_t>(1, p.passes.size()) * sizeof(PassDesc);
-    d.bs = std::max<size_t>(1, p.stages.size()) * sizeof(StageDesc);
-    d.bo = std::max<size_t>(1, p.ops.size()) * sizeof(DevOp);
+  auto plan_blocks = [&](const Plan& p, ReqPlan& d) {  // sizes from request_sizes()
+    (void)p;
     d.P = static_cast<PassDesc*>(pool_.get(d.bp));
     d.S = static_cast<StageDesc*>(pool_.get(d.bs));
     d.O = static_cast<DevOp*>(pool_.get(d.bo));
@@ -337,27 +351,18 @@ int Server::admit(SReq* r) {
            stage_upload(p.ops.data(), p.ops.size() * sizeof(DevOp), d.O);
   };
   const Plan& F = r->fplan;
-  size_t ns = 0;
-  r->state_bytes = ((size_t)1 << r->c.n) * 8;
-  r->cf_bytes = r->coef_f.size() * sizeof(float);
-  r->meas_bytes = std::max<size_t>(1, (size_t)F.n_meas << (F.n - F.m)) * sizeof(double);
   bool ok = plan_blocks(F, r->df);
   r->A = pool_.get(r->state_bytes);
   r->cf = pool_.get(r->cf_bytes);
   r->meas = static_cast<double*>(pool_.get(r->meas_bytes));
   ok = ok && r->A && r->cf && r->meas;
   if (r->want_grad) {
-    const Plan& P = r->ap->plan;
-    ns = P.n_gslots;
-    r->ca_bytes = r->coef_a.size() * sizeof(float);
-    r->gpart_bytes = std::max<size_t>(1, ns << (P.n - P.m)) * sizeof(double);
     ok = plan_blocks(r->hplan, r->dh) && ok;
     r->B = pool_.get(r->state_bytes);
     r->ca = pool_.get(r->ca_bytes);
     r->gpart = static_cast<double*>(pool_.get(r->gpart_bytes));
     ok = ok && r->B && r->ca && r->gpart;
   }
-  r->res_bytes = (1 + ns + (size_t)r->c.n_params) * sizeof(double);
   r->res = static_cast<double*>(pool_.get(r->res_bytes));
   if (!ok || !r->res) {
     set_error(ctx_, "serving: device allocation failed");
@@ -590,6 +595,10 @@ void Server::loop() {
         r->status = rc;
       }
       run.push_back(r);
+      if (pool_.outstanding() > inflight_) {  // accounting check: the budget covers every block handed out
+        std::lock_guard<std::mutex> g(mu_);
+        st_.accounting_violations++;
+      }
     }
     if (!run.empty()) {
       Step st;

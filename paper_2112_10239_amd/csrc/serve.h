@@ -38,11 +38,14 @@ class BlockPool {
   void put(void* p, size_t bytes);
   void trim(size_t keep_bytes);
   size_t cached() const { return cached_; }
+  // bytes handed out and not yet returned (read by other threads for statistics)
+  size_t outstanding() const { return out_.load(std::memory_order_relaxed); }
 
  private:
   bool mock_;
   std::multimap<size_t, void*> free_;
   size_t cached_ = 0;
+  std::atomic<size_t> out_{0};
   uintptr_t fake_ = 0x1000;
 };
 

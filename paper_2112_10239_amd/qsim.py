@@ -64,7 +64,7 @@ class Request(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "rejected", "cancelled", "failed", "steps",
                                                 "launches", "inflight_bytes", "peak_inflight_bytes", "queued",
-                                                "running")]
+                                                "running", "pool_outstanding_bytes", "accounting_violations")]
 
 
 assert ctypes.sizeof(Gate) == 32 and ctypes.sizeof(Circuit) == 24 and ctypes.sizeof(Hamiltonian) == 40

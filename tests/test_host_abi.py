@@ -189,6 +189,32 @@ ctx.close()
     assert res.count(-2) == 1 and res.count(0) == 5
 
 
+def test_serving_mock_accounting_covers_pool(Q, monkeypatch):
+    """In-flight accounting is at least the device bytes the pool hands out (every block of
+    every admitted request: states, plan descriptors, coefficients, partial sums, results)."""
+    monkeypatch.setenv("QSIM_TEST_MOCK_STEP_MS", "1")
+    budget = 3 << 24
+    ctx = Q.Context(-1, hbm_budget_bytes=budget, max_queue=200)
+    reqs = [W.serving_request(r, n_range=(14, 21), depth_range=(4, 12)) for r in range(40)]
+    ts = [ctx.submit(r.circuit, r.H, r.theta, r.want_grad) for r in reqs]
+    seen_out = 0
+    for t in ts:
+        while True:
+            s = ctx.server_stats()
+            assert s["pool_outstanding_bytes"] <= s["inflight_bytes"] <= budget
+            seen_out = max(seen_out, s["pool_outstanding_bytes"])
+            st = ctx.poll(t)[0]
+            if st != 1:
+                break
+            time.sleep(0.0005)
+        assert st == 0
+    s = ctx.server_stats()
+    assert s["accounting_violations"] == 0 and seen_out > 0
+    assert s["inflight_bytes"] == 0 and s["pool_outstanding_bytes"] == 0
+    assert s["peak_inflight_bytes"] <= budget
+    ctx.close()
+
+
 def test_serving_poll_sizes_gradient_buffer(Q):
     """Polling a gradient request without stating n_params still returns the whole gradient (regression:
     the binding used to hand the library a one-element buffer)."""
