@@ -253,6 +253,30 @@ def bench_density(Q, W, reps=5):
     return out
 
 
+def bench_block5(Q, W, reps=4):
+    """A dense five-qubit block (random 32 x 32 unitary) on qubits 0..4 of the n=30 complex64
+    state: fp32 matrix cores against the vector ALUs, beside the factored pass kernel."""
+    rng = np.random.default_rng(5)
+    U, _ = np.linalg.qr(rng.normal(size=(32, 32)) + 1j * rng.normal(size=(32, 32)))
+    n = 30
+    ctx = Q.Context(0)
+    st = ctx.create_state(n)
+    c = W.brickwork_ry_rz_cnot(n, 1)
+    st.apply_layer(c.gates, W.angles(c.n_params, [5, n])[None, :], c.n_params)
+    out = dict(workload="dense 32x32 complex block on qubits 0..4 of the n=30 complex64 state (8 GiB), in place")
+    amps = 2.0 ** n
+    for method, name in ((0, "mfma"), (1, "valu")):
+        st.apply_block5(U, method)
+        ms = float(np.median([st.apply_block5(U, method) for _ in range(reps)]))
+        tf = 256 * amps / (ms * 1e-3) / 1e12
+        out[name] = dict(ms=ms, TFLOPs=tf, frac=tf / (FP32_PEAK_TFLOPS if method == 0 else FP32_PEAK_TFLOPS / 2),
+                         GBs=16 * amps / (ms * 1e-3) / 1e9)
+    out["peaks"] = "mfma: fp32 matrix peak 157.3 TFLOP/s; valu: plain fp32 FMA issue 78.6 TFLOP/s"
+    st.destroy()
+    ctx.close()
+    return out
+
+
 def bench_small(Q, W, reps=200):
     w = W.small_ring_maxcut()
     ctx = Q.Context(0)
@@ -426,7 +450,8 @@ def main():
     ap.add_argument("--serving", type=float, default=1.0, help="seconds of Poisson arrivals (0 = skip serving)")
     ap.add_argument("--counter-run", action="store_true",
                     help="short run for HBM byte counters: one 8 GiB reference copy, then one dense evaluation")
-    ap.add_argument("--only", choices=["lightcone", "gradient", "lightcone_gradient", "density", "small_c128"],
+    ap.add_argument("--only", choices=["lightcone", "gradient", "lightcone_gradient", "density", "small_c128",
+                                       "block5"],
                     help="run one secondary workload alone (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -438,7 +463,7 @@ def main():
 
     if args.only:
         fn = {"lightcone": bench_lightcone, "gradient": bench_grad, "lightcone_gradient": bench_lightcone_grad,
-              "density": bench_density, "small_c128": bench_small}[args.only]
+              "density": bench_density, "small_c128": bench_small, "block5": bench_block5}[args.only]
         print(json.dumps({args.only: fn(Q, W)}), flush=True)
         return
     if args.counter_run:
@@ -473,7 +498,7 @@ def main():
     if not args.no_extras:
         line["extras"] = {"lightcone": bench_lightcone(Q, W), "gradient": bench_grad(Q, W),
                           "lightcone_gradient": bench_lightcone_grad(Q, W), "density": bench_density(Q, W),
-                          "small_c128": bench_small(Q, W)}
+                          "small_c128": bench_small(Q, W), "block5": bench_block5(Q, W)}
     if args.serving > 0:
         line.setdefault("extras", {})["serving"] = bench_serving(Q, W, args.serving)
     print(json.dumps(line), flush=True)

@@ -176,6 +176,18 @@ int qsim_state_device_ptr(qsim_state* st, void** ptr);
  * rho is complete.  QSIM_EINVAL on bad qubits or m. */
 int qsim_reduced_density(qsim_state* st, const int32_t* qubits, int m, void* rho, int rho_on_device);
 
+/* A dense five-qubit gate (Sec. 2: custom gates acting on states; here a
+ * 32 x 32 unitary such as several layers on five qubits contracted into one
+ * tensor) applied to qubits 0..4 of every state: amplitude x = 32 h + j becomes
+ * sum_i u[j][i] psi[32 h + i], u row-major complex128 (2048 doubles, host; j
+ * and i little-endian over qubits 0..4), rounded once to fp32.  method 0: fp32
+ * matrix cores (the block in real form, 256 flops per amplitude; batch *
+ * 2^(n-5) must be a multiple of 32); method 1: vector ALUs.  Measurement call:
+ * the engine's own passes factor single-qubit rotations instead of forming
+ * dense blocks.  Flushes queued gates; *ms (optional) = kernel time.
+ * QSIM_EINVAL unless the states are complex64 of at least 5 qubits. */
+int qsim_apply_block5(qsim_state* st, const double* u, int method, double* ms);
+
 /* ---- one-call evaluation (Sec. 3: forward value) ----------------------------------- */
 
 /* out[b] = <psi(theta_b)|H|psi(theta_b)> for b < batch, theta_b = params + b*n_params
@@ -306,7 +318,8 @@ int qsim_timing_enable(qsim_ctx* ctx, int on);
  * 16 store lambda, 64 measure, 128 gradient), kind[i] = 0 dense pass, 1
  * light-cone batch, 2 reduced density matrix (bytes = state read once plus rho
  * written once; flops = 4 N (N + 1) K per state for N = 2^m, K = 2^(n-m): the
- * Hermitian product's lower triangle at 8 real flops per complex multiply-add).
+ * Hermitian product's lower triangle at 8 real flops per complex multiply-add),
+ * 3 dense five-qubit block (16 bytes and 256 flops per amplitude).
  * Any output pointer may be NULL.  *count = records copied. */
 int qsim_timing_get(qsim_ctx* ctx, double* ms, double* bytes, double* flops, int32_t* flags, int32_t* kind, int cap,
                     int* count);

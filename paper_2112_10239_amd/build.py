@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libqsim.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "density.hip", "coef.hip", "noalloc.hip", "planner.cpp", "engine.cpp", "api.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "density.hip", "coef.hip", "noalloc.hip", "block.hip", "planner.cpp", "engine.cpp", "api.cpp", "serve.cpp"]
 ARCH = os.environ.get("QSIM_OFFLOAD_ARCH", "gfx950")
 # Packed-FP32 instructions are disabled: plain fp32 VALU code only.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",

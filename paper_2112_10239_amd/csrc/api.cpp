@@ -258,6 +258,78 @@ int qsim_state_to_host(qsim_state* st, void* host) {
   return QSIM_OK;
 }
 
+int qsim_apply_block5(qsim_state* st, const double* u, int method, double* ms) {
+  if (check_state(st) || !u || (method != 0 && method != 1)) return QSIM_EINVAL;
+  qsim_ctx* ctx = st->ctx;
+  if (st->dtype != QSIM_C64 || st->n < 5) {
+    set_error(ctx, "apply_block5: complex64 states of at least 5 qubits");
+    return QSIM_EINVAL;
+  }
+  const int64_t rows = (int64_t)st->batch << (st->n - 5);
+  if (method == 0 && rows % 32) {
+    set_error(ctx, "apply_block5: the matrix-core kernel needs a multiple of 32 rows (batch * 2^(n-5))");
+    return QSIM_EINVAL;
+  }
+  if (ctx->mock) return no_device(ctx);
+  // the block in the form each kernel reads (fp32, rounded once from fp64)
+  std::vector<float> w;
+  if (method == 0) {
+    // W[c][j]: c < 32 real part of input amplitude c, else imaginary part of c - 32;
+    // j < 32 real part of output j, else imaginary part of output j - 32
+    auto W = [&](int c, int j) -> double {
+      const int i = c & 31, o = j & 31;
+      const double ur = u[(o * 32 + i) * 2], ui = u[(o * 32 + i) * 2 + 1];
+      if (c < 32) return j < 32 ? ur : ui;
+      return j < 32 ? -ui : ur;
+    };
+    w.resize(2 * 32 * 64);
+    for (int t = 0; t < 2; ++t)
+      for (int s = 0; s < 32; ++s)
+        for (int l = 0; l < 64; ++l) {
+          const int g = l >> 5;
+          const int krow = s < 16 ? g * 16 + s : 32 + g * 16 + (s - 16);
+          w[(t * 32 + s) * 64 + l] = (float)W(krow, t * 32 + (l & 31));
+        }
+  } else {
+    w.resize(2048);
+    for (int k = 0; k < 2048; ++k) w[k] = (float)u[k];
+  }
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  int rc = flush(st, nullptr, nullptr);
+  if (rc) return rc;
+  Workspace& ws = ctx->ws;
+  hipStream_t s = st->stream;
+  HIP_TRY(hipStreamSynchronize(s), "stream sync");  // the pinned staging buffer may still feed an upload
+  HIP_TRY(ws.block.ensure(w.size() * sizeof(float)), "block buffer");
+  HIP_TRY(ws.h_coef.ensure(w.size() * sizeof(float)), "pinned block staging");
+  std::memcpy(ws.h_coef.p, w.data(), w.size() * sizeof(float));
+  HIP_TRY(hipMemcpyAsync(ws.block.p, ws.h_coef.p, w.size() * sizeof(float), hipMemcpyHostToDevice, s), "block upload");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms) {
+    HIP_TRY(hipEventCreate(&e0), "event");
+    HIP_TRY(hipEventCreate(&e1), "event");
+    HIP_TRY(hipEventRecord(e0, s), "event record");
+  }
+  const double amps = (double)st->batch * (double)(1ull << st->n);
+  const int ti = timing_begin(ctx, s, 16.0 * amps, PF_LOAD_A | PF_STORE_A, 3, 256.0 * amps);
+  hipError_t le = launch_block5(st->buf, rows, (const float*)ws.block.p, method, s);
+  timing_end(ctx, ti, s);
+  if (ms) (void)hipEventRecord(e1, s);
+  hipError_t se = hipStreamSynchronize(s);
+  timing_collect(ctx);
+  if (ms) {
+    float t = 0;
+    if (le == hipSuccess && se == hipSuccess) (void)hipEventElapsedTime(&t, e0, e1);
+    *ms = t;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  HIP_TRY(le, "block launch");
+  HIP_TRY(se, "stream sync");
+  return QSIM_OK;
+}
+
 int qsim_reduced_density(qsim_state* st, const int32_t* qubits, int m, void* rho, int rho_on_device) {
   if (check_state(st) || !qubits || !rho) return QSIM_EINVAL;
   qsim_ctx* ctx = st->ctx;

@@ -98,7 +98,7 @@ struct DevPlan {
 };
 
 struct Workspace {
-  DevBuf coef, meas, grad, slot_total, out, scratch, lambda, weights, table, dens, gates;
+  DevBuf coef, meas, grad, slot_total, out, scratch, lambda, weights, table, dens, gates, block;
   HostBuf h_coef, h_out, h_gates;
   std::vector<CoefGate> last_gates;  // content of 'gates' (device gate table)
   void release() {
@@ -115,6 +115,7 @@ struct Workspace {
     weights.release();
     table.release();
     dens.release();
+    block.release();
     h_coef.release();
     h_out.release();
   }

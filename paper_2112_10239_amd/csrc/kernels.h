@@ -100,6 +100,12 @@ hipError_t launch_build_coef(const CoefSlot* slots, int nslots, const int32_t* s
                              const double* theta, int64_t theta_stride, int rows, void* out, int64_t row_stride,
                              int c128, hipStream_t stream);
 
+// A dense 32 x 32 complex block on qubits 0..4 of complex64 states, rows = states *
+// 2^(n-5) rows of 32 amplitudes, in place.  method 0: fp32 matrix cores, w = the
+// 64 x 64 real form in MFMA operand order (4096 floats; rows a multiple of 32);
+// method 1: vector ALUs, w = the complex matrix row-major (2048 floats).
+hipError_t launch_block5(void* psi, int64_t rows, const float* w, int method, hipStream_t stream);
+
 // Plain copy of n16 16-byte words (reference HBM stream).
 hipError_t launch_copy(const void* src, void* dst, uint64_t n16, hipStream_t stream);
 

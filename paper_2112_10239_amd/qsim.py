@@ -78,6 +78,7 @@ EXPORTS = [
     "qsim_copy_probe", "qsim_expect_grad_cones", "qsim_reduced_density", "qsim_plan_passes", "qsim_expect_terms",
     "qsim_coef_rows",
     "qsim_expect_circuit_noalloc",
+    "qsim_apply_block5",
 ]
 
 
@@ -115,6 +116,7 @@ def _load():
         "qsim_plan_passes": (I, [V, P(Circuit), P(Hamiltonian), I, I, P(ctypes.c_int32), I, P(I)]),
         "qsim_coef_rows": (I, [V, P(Circuit), V, I, I, I, V, ctypes.c_uint64, P(ctypes.c_uint64)]),
         "qsim_expect_circuit_noalloc": (I, [V, P(Circuit), V, I, I, P(Hamiltonian), I, V, ctypes.c_uint64, V, P(D)]),
+        "qsim_apply_block5": (I, [V, P(D), I, P(D)]),
         "qsim_submit": (I, [V, P(Request), P(ctypes.c_uint64)]),
         "qsim_poll": (I, [V, ctypes.c_uint64, P(D), P(D)]),
         "qsim_cancel": (I, [V, ctypes.c_uint64]),
@@ -560,6 +562,15 @@ class State:
         out = np.zeros(self.batch)
         self.ctx._check(lib.qsim_expect(self.ptr, ctypes.byref(ch.h), _dptr(out)), "qsim_expect")
         return out
+
+    def apply_block5(self, u, method: int = 0) -> float:
+        """Dense 32 x 32 unitary u (complex, [out j][in i], little-endian over qubits 0..4)
+        on qubits 0..4: method 0 matrix cores, 1 vector ALUs.  Returns the kernel time in ms."""
+        uu = np.ascontiguousarray(np.asarray(u, dtype=np.complex128).reshape(32, 32))
+        ms = ctypes.c_double()
+        self.ctx._check(lib.qsim_apply_block5(self.ptr, uu.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              method, ctypes.byref(ms)), "qsim_apply_block5")
+        return float(ms.value)
 
     def to_host(self) -> np.ndarray:
         dt = np.complex64 if self.dtype == C64 else np.complex128

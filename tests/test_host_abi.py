@@ -32,14 +32,14 @@ def Q():
 def header_functions():
     with open(os.path.join(ROOT, "include", "qsim.h")) as f:
         src = f.read()
-    return sorted(set(re.findall(r"\b(qsim_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(qsim_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_exports_every_declared_symbol(Q):
     names = header_functions()
     assert len(names) >= 18
     out = subprocess.run(["nm", "-D", "--defined-only", Q.qsim.LIB_PATH], capture_output=True, text=True).stdout
-    exported = set(re.findall(r"\bT (qsim_[a-z_]+)$", out, re.M))
+    exported = set(re.findall(r"\bT (qsim_[a-z0-9_]+)$", out, re.M))
     missing = [n for n in names if n not in exported]
     assert not missing, missing
     assert set(Q.qsim.EXPORTS) == set(names)

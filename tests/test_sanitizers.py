@@ -21,7 +21,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2112_10239_amd", "csrc")
 HOST_SOURCES = ["planner.cpp", "engine.cpp", "api.cpp", "serve.cpp"]
-HIP_OBJECTS = ["kernels.o", "density.o", "coef.o", "noalloc.o"]
+HIP_OBJECTS = ["kernels.o", "density.o", "coef.o", "noalloc.o", "block.o"]
 VARIANTS = {
     "asan": ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"],
     "tsan": ["-fsanitize=thread"],
