@@ -723,22 +723,24 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
   }
   double acc = 0.0;
   const int s0 = P->stage_begin, s1 = P->stage_end, sst = P->store_stage;
+  // a pass that stores in its first stage through a permutation (see below)
+  const bool cross = sst == s0 && (P->entry_perm || P->exit_perm);
+  constexpr uint32_t kSh = sizeof(cpx<T>) == 8 ? 3u : 4u;  // slot -> byte offset
+  const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
   uint32_t pend = 0;  // register i holds the amplitude of register index i ^ pend
   for (int s = s0; s < s1; ++s) {
     kptr<StageDesc> S = SD + s;
     pend = 0;
-    const uint32_t tl = thread_local_index<R>(S, m, tid);
-    const KWords<2> rbw(S->rb);
-    uint32_t rl[R];
+    // LDS addressing precomputed per stage (swizzled slots, linear over XOR):
+    // lane bits per lane, wave bits by the wave's index, register bits uniform
+    const KWords<3> rdl(S->rd_lane);
+    const KWords<4> rdr(S->rd_reg);
+    uint32_t rd = kh(&S->rd_wave[wv]);
 #pragma unroll
-    for (int j = 0; j < R; ++j) rl[j] = 1u << rbw.u8(j);
-    // The swizzle is linear over XOR and the thread and register bits are
-    // disjoint, so an LDS slot is swz(tl) ^ swz(register offset): one lane
-    // value and one uniform value per register, the latter the XOR of the
-    // swizzled byte offsets of the register's bits.
+    for (int k = 0; k < 6; ++k) rd ^= ((uint32_t)(tid >> k) & 1u) ? rdl.u16(k) : 0u;
     uint32_t sb[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) sb[j] = swz(rl[j]) * (uint32_t)sizeof(cpx<T>);
+    for (int j = 0; j < R; ++j) sb[j] = rdr.u16(j) << kSh;
     auto soff = [&](int i) __attribute__((always_inline)) {
       uint32_t o = 0;
 #pragma unroll
@@ -748,8 +750,13 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     };
     // full LDS address of the thread's slot (tile at address 0), opaque to the
     // optimiser so each access is one XOR with a uniform offset
-    uint32_t tl_b = lds0 + swz(tl) * (uint32_t)sizeof(cpx<T>);
+    uint32_t tl_b = lds0 + (rd << kSh);
     asm volatile("" : "+v"(tl_b));
+    // the thread's local index, for ops that read index bits (controls,
+    // diagonals, measurement signs); stages of a factored op alone need none
+    const bool has_ops = S->op_end > S->op_begin + 1 ||
+                         (S->op_end == S->op_begin + 1 && (*(kptr<uint32_t>)(OPS + S->op_begin) & 0xffu) != OP_UTAB);
+    const uint32_t tl = has_ops ? thread_local_index<R>(S, m, tid) : 0u;
 
     const uint32_t bofs = tsize * (uint32_t)sizeof(cpx<T>);  // second state's tile (dual kernels)
     if (s != s0) {
@@ -1078,7 +1085,6 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     // stores to addresses that other waves load from: every wave's loads must be
     // complete before any wave stores.  Later stages (measurements) may follow.
     // The TAIL variant stores after the last stage, which is then the first.
-    const bool cross = sst == s0 && (P->entry_perm || P->exit_perm);
     if (cross && s == s0) {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       lds_sync();
@@ -1109,53 +1115,39 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     if (s + 1 < s1) {
       lds_sync();
       if (active) {
-        if (kh(&S->has_perm)) {
-          // write every amplitude to its image under the stage's exit permutation
-          const KWords<kMaxLocal / 2> tcol(S->tcol);
-          // lane bits per lane; wave bits are uniform (scalar work)
-          const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
-          uint32_t w = 0, wu = 0;
+        // every amplitude to its slot in the next layout: through the stage's
+        // exit permutation when it has one (the precomputed write parts are its
+        // images), else the slots it was read from; register i holds index i ^ pend
+        const KWords<3> wrl(S->wr_lane);
+        const KWords<4> wrr(S->wr_reg);
+        uint32_t wr = kh(&S->wr_wave[wv]);
 #pragma unroll
-          for (int k = 0; k < kMaxLocal - R; ++k)
-            if (k < m - R) {
-              if (k < 6) w ^= ((uint32_t)(tid >> k) & 1u) ? tcol.u16(k) : 0u;
-              else wu ^= ((wv >> (k - 6)) & 1u) ? tcol.u16(k) : 0u;
-            }
-          const int n_aff = (int)kh(&S->n_aff);
-          uint32_t wa = 0;  // affine part: tile bits (uniform)
+        for (int k = 0; k < 6; ++k) wr ^= ((uint32_t)(tid >> k) & 1u) ? wrl.u16(k) : 0u;
+        const int n_aff = (int)kh(&S->n_aff);
+        if (n_aff > 0) {  // affine part: the tile's non-local control bits (uniform)
+          uint32_t wa = 0;
           for (int j = 0; j < n_aff; ++j)
-            if ((base >> kb(&S->aff_pos[j])) & 1) wa ^= kh(&S->aff_mask[j]);
-          // register i holds index i ^ pend; preg is linear, so its image is preg(i) ^ preg(pend)
-          const uint32_t wp = pend ? kh(&S->preg[pend]) : 0u;
-          uint32_t w_b = lds0 + swz(w ^ wu ^ wa ^ wp) * (uint32_t)sizeof(cpx<T>);
-          asm volatile("" : "+v"(w_b));
-          const KWords<(1 << R) / 2> preg(S->preg);
-          uint32_t pb[R];  // swizzled byte offsets of the images of the register bits
+            if ((base >> kb(&S->aff_pos[j])) & 1) wa ^= kh(&S->wr_aff[j]);
+          wr ^= wa;
+        }
+        uint32_t pb[R];  // byte offsets of the images of the register bits
 #pragma unroll
-          for (int j = 0; j < R; ++j) pb[j] = swz(preg.u16(1 << j)) * (uint32_t)sizeof(cpx<T>);
+        for (int j = 0; j < R; ++j) pb[j] = wrr.u16(j) << kSh;
+        uint32_t wp = 0;  // image of register index pend (linear)
 #pragma unroll
-          for (int i = 0; i < NR; ++i) {
-            uint32_t po = 0;
+        for (int j = 0; j < R; ++j)
+          if ((pend >> j) & 1u) wp ^= pb[j];
+        uint32_t w_b = (lds0 + (wr << kSh)) ^ wp;
+        asm volatile("" : "+v"(w_b));
 #pragma unroll
-            for (int j = 0; j < R; ++j)
-              if ((i >> j) & 1) po ^= pb[j];
-            const uint32_t l = w_b ^ po;
-            st_lds<T>(l, a[i]);
-            if constexpr (DUAL) st_lds<T>(l + bofs, b[i]);
-          }
-        } else {
-          uint32_t rp = 0;  // offset of register index pend
+        for (int i = 0; i < NR; ++i) {
+          uint32_t po = 0;
 #pragma unroll
           for (int j = 0; j < R; ++j)
-            if ((pend >> j) & 1u) rp ^= sb[j];
-          uint32_t wl_b = tl_b ^ rp;
-          asm volatile("" : "+v"(wl_b));
-#pragma unroll
-          for (int i = 0; i < NR; ++i) {
-            const uint32_t l = wl_b ^ soff(i);
-            st_lds<T>(l, a[i]);
-            if constexpr (DUAL) st_lds<T>(l + bofs, b[i]);
-          }
+            if ((i >> j) & 1) po ^= pb[j];
+          const uint32_t l = w_b ^ po;
+          st_lds<T>(l, a[i]);
+          if constexpr (DUAL) st_lds<T>(l + bofs, b[i]);
         }
       }
       lds_sync();

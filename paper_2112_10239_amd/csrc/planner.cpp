@@ -1110,6 +1110,46 @@ struct PassEmitter {
   }
 };
 
+// The swizzled LDS slot of a local index: lanes that differ only in bits 5..9
+// land in different banks.  Linear over XOR.
+uint32_t swz_slot(uint32_t l) { return l ^ ((l >> 5) & 31u); }
+
+// Fills the precomputed LDS addressing of every stage of a plan (StageDesc
+// rd_* / wr_* fields) from its register bits, thread bits and exit permutation.
+void stage_addressing(Plan& plan) {
+  for (const PassDesc& pd : plan.passes) {
+    const int m = pd.m, r = pd.r, nt = m - r;
+    for (int s = pd.stage_begin; s < pd.stage_end; ++s) {
+      StageDesc& st = plan.stages[s];
+      uint32_t rd_t[kMaxLocal] = {0}, wr_t[kMaxLocal] = {0};
+      for (int k = 0; k < nt && k < kMaxLocal; ++k) {
+        rd_t[k] = swz_slot(1u << st.tb[k]);
+        wr_t[k] = st.has_perm ? swz_slot(st.tcol[k]) : rd_t[k];
+      }
+      for (int k = 0; k < 6; ++k) {
+        st.rd_lane[k] = (uint16_t)rd_t[k];
+        st.wr_lane[k] = (uint16_t)wr_t[k];
+      }
+      for (int w = 0; w < 16; ++w) {
+        uint32_t a = 0, b = 0;
+        for (int bit = 0; bit < 4; ++bit)
+          if ((w >> bit) & 1) {
+            a ^= rd_t[6 + bit];
+            b ^= wr_t[6 + bit];
+          }
+        st.rd_wave[w] = (uint16_t)a;
+        st.wr_wave[w] = (uint16_t)b;
+      }
+      for (int j = 0; j < 8; ++j) {
+        st.rd_reg[j] = j < r ? (uint16_t)swz_slot(1u << st.rb[j]) : 0;
+        st.wr_reg[j] = j < r ? (uint16_t)(st.has_perm ? swz_slot(st.preg[1u << j]) : st.rd_reg[j]) : 0;
+      }
+      for (int j = 0; j < kMaxAffine; ++j)
+        st.wr_aff[j] = (st.has_perm && j < st.n_aff) ? (uint16_t)swz_slot(st.aff_mask[j]) : 0;
+    }
+  }
+}
+
 // Split gates into passes; returns the local masks and applied gate lists.
 void split_passes(int n, int m, int c_low, const std::vector<PGate>& G, int max_grad, std::vector<uint64_t>& Ls,
                   std::vector<std::vector<int>>& applied_lists) {
@@ -1280,6 +1320,7 @@ int plan_forward(int n, const std::vector<PGate>& gates_in, const std::vector<PG
         plan.order.push_back(src);
       }
   }
+  stage_addressing(plan);
   return 0;
 }
 
@@ -1310,6 +1351,7 @@ int plan_happly(int n, const std::vector<PGate>& hterms, const PlanOptions& o, P
     PassEmitter em(plan, n, m, r, Ls[p]);
     em.emit(mod, {}, flags, c_low, (int)p);
   }
+  stage_addressing(plan);
   return 0;
 }
 
@@ -1341,6 +1383,7 @@ int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, P
     for (int idx : lists[p]) mod.push_back(&gates[idx]);
     em.emit(mod, {}, flags, c_low, p);
   }
+  stage_addressing(plan);
   return 0;
 }
 
@@ -1373,6 +1416,7 @@ void append_diag_measure(Plan& plan, const std::vector<PGate>& meas) {
     pd.flags |= PF_MEASURE;
     pd.meas_index = plan.n_meas++;
   }
+  stage_addressing(plan);
 }
 
 // ---------------------------------------------------------------------------

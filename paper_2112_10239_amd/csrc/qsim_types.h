@@ -92,8 +92,23 @@ struct StageDesc {
   uint8_t tpos[kMaxLocal];  // physical bit of thread bit k (the pass's lpos[tb[k]])
   uint8_t rpos[8];          // physical bit of register bit j (lpos[rb[j]])
   uint8_t rbs[8];           // register bits as local indices, ascending (r used)
+  // LDS addressing, precomputed on the host, in swizzled slots (the swizzle is
+  // linear over XOR, so a slot is the XOR of the parts of its index bits).
+  // Reading the stage's registers: slot of register i of thread t =
+  //   XOR_{k<6} t_k rd_lane[k] ^ rd_wave[t >> 6] ^ XOR_{j in i} rd_reg[j];
+  // writing them at the exchange that ends the stage (through its exit
+  // permutation when it has one, else the same slots):
+  //   XOR_{k<6} t_k wr_lane[k] ^ wr_wave[t >> 6] ^ XOR_{tile bits} wr_aff ^ XOR_{j in i} wr_reg[j].
+  // Entries for thread bits at or above m - r are zero.
+  uint16_t rd_lane[6];
+  uint16_t rd_wave[16];
+  uint16_t rd_reg[8];
+  uint16_t wr_lane[6];
+  uint16_t wr_wave[16];
+  uint16_t wr_reg[8];
+  uint16_t wr_aff[kMaxAffine];
 };
-static_assert(sizeof(StageDesc) == 188, "StageDesc layout");
+static_assert(sizeof(StageDesc) == 324, "StageDesc layout");
 
 enum PassFlags : int32_t {
   PF_INIT = 1,      // first stage generates |0...0> instead of loading a
