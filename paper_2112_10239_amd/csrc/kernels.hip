@@ -731,16 +731,20 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
   for (int s = s0; s < s1; ++s) {
     kptr<StageDesc> S = SD + s;
     pend = 0;
+    // the stage header in one scalar load; the wave parts by the wave's index
+    const KWords<16> hd(S);
+    const uint32_t rdw = kh(&S->rd_wave[wv]), wrw = kh(&S->wr_wave[wv]);
+    const int op_begin = (int)hd.w[0], op_end = (int)hd.w[1];
+    const uint32_t n_aff = hd.w[2] >> 16, sflags = hd.w[3];
     // LDS addressing precomputed per stage (swizzled slots, linear over XOR):
     // lane bits per lane, wave bits by the wave's index, register bits uniform
-    const KWords<3> rdl(S->rd_lane);
-    const KWords<4> rdr(S->rd_reg);
-    uint32_t rd = kh(&S->rd_wave[wv]);
+    // (header words: rd_lane 4..6, wr_lane 7..9, rd_reg 10..12, wr_reg 13..15)
+    uint32_t rd = rdw;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) rd ^= ((uint32_t)(tid >> k) & 1u) ? rdl.u16(k) : 0u;
+    for (int k = 0; k < 6; ++k) rd ^= ((uint32_t)(tid >> k) & 1u) ? hd.u16(8 + k) : 0u;
     uint32_t sb[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) sb[j] = rdr.u16(j) << kSh;
+    for (int j = 0; j < R; ++j) sb[j] = hd.u16(20 + j) << kSh;
     auto soff = [&](int i) __attribute__((always_inline)) {
       uint32_t o = 0;
 #pragma unroll
@@ -754,9 +758,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     asm volatile("" : "+v"(tl_b));
     // the thread's local index, for ops that read index bits (controls,
     // diagonals, measurement signs); stages of a factored op alone need none
-    const bool has_ops = S->op_end > S->op_begin + 1 ||
-                         (S->op_end == S->op_begin + 1 && (*(kptr<uint32_t>)(OPS + S->op_begin) & 0xffu) != OP_UTAB);
-    const uint32_t tl = has_ops ? thread_local_index<R>(S, m, tid) : 0u;
+    const uint32_t tl = (sflags & SF_INDEX_OPS) ? thread_local_index<R>(S, m, tid) : 0u;
 
     const uint32_t bofs = tsize * (uint32_t)sizeof(cpx<T>);  // second state's tile (dual kernels)
     if (s != s0) {
@@ -804,13 +806,13 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     };
     // a factored op ends its stage: it runs after the op loop, outside the
     // op dispatch (the loop is empty for the common stage holding only it)
-    int o_end = S->op_end;
+    int o_end = op_end;
     bool last_utab = false;
     if constexpr (!DUAL && R <= 4 && std::is_same<T, float>::value) {
-      last_utab = o_end > S->op_begin && (*(kptr<uint32_t>)(OPS + (o_end - 1)) & 0xffu) == OP_UTAB;
+      last_utab = (sflags & SF_LAST_UTAB) != 0u;
       if (last_utab) --o_end;
     }
-    for (int o = S->op_begin; o < o_end; ++o) {
+    for (int o = op_begin; o < o_end; ++o) {
       kptr<DevOp> op = OPS + o;
       // type, j, ck, cb | ck2, cb2, ph, pad
       const uint32_t w0 = *(kptr<uint32_t>)op, w1 = *((kptr<uint32_t>)op + 1);
@@ -1118,21 +1120,18 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         // every amplitude to its slot in the next layout: through the stage's
         // exit permutation when it has one (the precomputed write parts are its
         // images), else the slots it was read from; register i holds index i ^ pend
-        const KWords<3> wrl(S->wr_lane);
-        const KWords<4> wrr(S->wr_reg);
-        uint32_t wr = kh(&S->wr_wave[wv]);
+        uint32_t wr = wrw;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) wr ^= ((uint32_t)(tid >> k) & 1u) ? wrl.u16(k) : 0u;
-        const int n_aff = (int)kh(&S->n_aff);
+        for (int k = 0; k < 6; ++k) wr ^= ((uint32_t)(tid >> k) & 1u) ? hd.u16(14 + k) : 0u;
         if (n_aff > 0) {  // affine part: the tile's non-local control bits (uniform)
           uint32_t wa = 0;
-          for (int j = 0; j < n_aff; ++j)
+          for (int j = 0; j < (int)n_aff; ++j)
             if ((base >> kb(&S->aff_pos[j])) & 1) wa ^= kh(&S->wr_aff[j]);
           wr ^= wa;
         }
         uint32_t pb[R];  // byte offsets of the images of the register bits
 #pragma unroll
-        for (int j = 0; j < R; ++j) pb[j] = wrr.u16(j) << kSh;
+        for (int j = 0; j < R; ++j) pb[j] = hd.u16(26 + j) << kSh;
         uint32_t wp = 0;  // image of register index pend (linear)
 #pragma unroll
         for (int j = 0; j < R; ++j)

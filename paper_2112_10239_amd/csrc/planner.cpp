@@ -1140,12 +1140,15 @@ void stage_addressing(Plan& plan) {
         st.rd_wave[w] = (uint16_t)a;
         st.wr_wave[w] = (uint16_t)b;
       }
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < 6; ++j) {
         st.rd_reg[j] = j < r ? (uint16_t)swz_slot(1u << st.rb[j]) : 0;
         st.wr_reg[j] = j < r ? (uint16_t)(st.has_perm ? swz_slot(st.preg[1u << j]) : st.rd_reg[j]) : 0;
       }
       for (int j = 0; j < kMaxAffine; ++j)
         st.wr_aff[j] = (st.has_perm && j < st.n_aff) ? (uint16_t)swz_slot(st.aff_mask[j]) : 0;
+      // the ops before a trailing factored group (that one runs after the op loop)
+      const bool utab = st.op_end > st.op_begin && plan.ops[st.op_end - 1].type == OP_UTAB;
+      st.flags = (utab ? SF_LAST_UTAB : 0u) | ((st.op_end - st.op_begin > (utab ? 1 : 0)) ? SF_INDEX_OPS : 0u);
     }
   }
 }

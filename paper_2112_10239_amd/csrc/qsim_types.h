@@ -14,6 +14,7 @@
 // stages the tile is exchanged through LDS; the first stage reads from HBM
 // (or generates |0...0>) and the last stage writes to HBM.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 namespace qsim {
@@ -81,10 +82,26 @@ constexpr int kMaxAffine = 8;
 // affine map l -> M l + b(tile) on the local index, applied by writing each
 // amplitude to its image in LDS at the exchange that ends the stage.
 struct StageDesc {
+  // Header: everything the pass kernel needs at the start of a stage, read as
+  // one 64-byte block.  LDS addressing is precomputed on the host in swizzled
+  // slots (the swizzle is linear over XOR, so a slot is the XOR of the parts
+  // of its index bits).  Reading the stage's registers: slot of register i of
+  // thread t = XOR_{k<6} t_k rd_lane[k] ^ rd_wave[t >> 6] ^ XOR_{j in i} rd_reg[j];
+  // writing them at the exchange that ends the stage (through its exit
+  // permutation when it has one, else the same slots):
+  //   XOR_{k<6} t_k wr_lane[k] ^ wr_wave[t >> 6] ^ XOR_{tile bits} wr_aff ^ XOR_{j in i} wr_reg[j].
+  // Entries for thread bits at or above m - r, and for register bits at or
+  // above r, are zero.
   int32_t op_begin, op_end;
+  uint16_t has_perm, n_aff; // exit permutation present; affine terms used
+  uint32_t flags;           // SF_* below
+  uint16_t rd_lane[6];
+  uint16_t wr_lane[6];
+  uint16_t rd_reg[6];
+  uint16_t wr_reg[6];
+  // the rest
   uint8_t rb[8];            // register bits as local indices
   uint8_t tb[kMaxLocal];    // thread bits as local indices, ascending (m - r used)
-  uint16_t has_perm, n_aff; // exit permutation present; affine terms used
   uint16_t tcol[kMaxLocal]; // M applied to thread bit k
   uint16_t preg[1 << kMaxRegBits];  // M applied to register offset i
   uint8_t aff_pos[kMaxAffine];      // physical non-local bit of affine term j
@@ -92,23 +109,16 @@ struct StageDesc {
   uint8_t tpos[kMaxLocal];  // physical bit of thread bit k (the pass's lpos[tb[k]])
   uint8_t rpos[8];          // physical bit of register bit j (lpos[rb[j]])
   uint8_t rbs[8];           // register bits as local indices, ascending (r used)
-  // LDS addressing, precomputed on the host, in swizzled slots (the swizzle is
-  // linear over XOR, so a slot is the XOR of the parts of its index bits).
-  // Reading the stage's registers: slot of register i of thread t =
-  //   XOR_{k<6} t_k rd_lane[k] ^ rd_wave[t >> 6] ^ XOR_{j in i} rd_reg[j];
-  // writing them at the exchange that ends the stage (through its exit
-  // permutation when it has one, else the same slots):
-  //   XOR_{k<6} t_k wr_lane[k] ^ wr_wave[t >> 6] ^ XOR_{tile bits} wr_aff ^ XOR_{j in i} wr_reg[j].
-  // Entries for thread bits at or above m - r are zero.
-  uint16_t rd_lane[6];
   uint16_t rd_wave[16];
-  uint16_t rd_reg[8];
-  uint16_t wr_lane[6];
   uint16_t wr_wave[16];
-  uint16_t wr_reg[8];
   uint16_t wr_aff[kMaxAffine];
 };
-static_assert(sizeof(StageDesc) == 324, "StageDesc layout");
+// StageDesc flags: the stage has ops that read index bits (controls,
+// diagonals, measurement signs: the thread's local index is needed); its last
+// op is a factored rotation group (run after the op loop).
+enum StageFlags : uint32_t { SF_INDEX_OPS = 1, SF_LAST_UTAB = 2 };
+static_assert(sizeof(StageDesc) == 320, "StageDesc layout");
+static_assert(offsetof(StageDesc, rb) == 64, "StageDesc header");
 
 enum PassFlags : int32_t {
   PF_INIT = 1,      // first stage generates |0...0> instead of loading a
