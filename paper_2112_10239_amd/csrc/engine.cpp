@@ -592,6 +592,7 @@ struct ConePacker {
       st.op_end += ob;
       all.stages.push_back(st);
     }
+    const size_t first_new_stage = all.stages.size() - cp.stages.size();
     std::vector<int> remap(slots.size(), -1);
     for (size_t k = 0; k < slots.size(); ++k) {
       if (remap[k] >= 0) continue;
@@ -640,6 +641,11 @@ struct ConePacker {
           rec.slot = remap[rec.slot];
           all.ops.push_back(rec);
         }
+    }
+    // a stage header names its trailing factored group's slot: follow the remap
+    for (size_t k = first_new_stage; k < all.stages.size(); ++k) {
+      StageDesc& st = all.stages[k];
+      if (st.flags & SF_LAST_UTAB) st.flags = (st.flags & 0xffu) | ((uint32_t)remap[st.flags >> 8] << 8);
     }
     for (int g = 0; g < cp.n_gslots; ++g) {
       all.gslot_param.push_back(cp.gslot_param[g]);

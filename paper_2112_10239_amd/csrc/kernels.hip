@@ -783,9 +783,9 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     // the P table; the swaps X^f stay pending as an XOR mask on the register
     // index, which the stage's exit addressing applies (block: 32 + 32 table
     // scalars, k per bit, swap mask as a raw word).
-    auto utab = [&](kptr<DevOp> op) __attribute__((always_inline)) {
+    auto utab = [&](int slot) __attribute__((always_inline)) {
       if constexpr (!DUAL && R <= 4 && std::is_same<T, float>::value) {
-        const kptr<T> blk = coef + (int64_t)op->slot * 8;
+        const kptr<T> blk = coef + (int64_t)slot * 8;
         ap_tan<T, R, 0>(a, blk[64]);
         if constexpr (R > 1) {
           __builtin_amdgcn_sched_barrier(0);
@@ -1081,7 +1081,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         }
       }
     }
-    if (last_utab) utab(OPS + o_end);
+    if (last_utab) utab((int)(sflags >> 8));  // the group's first coefficient slot, from the header
     // A pass that stores in its first stage (no exchange barrier between the
     // loads and the stores) and whose loads or stores go through a permutation
     // stores to addresses that other waves load from: every wave's loads must be

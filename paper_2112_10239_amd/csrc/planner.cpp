@@ -1149,6 +1149,7 @@ void stage_addressing(Plan& plan) {
       // the ops before a trailing factored group (that one runs after the op loop)
       const bool utab = st.op_end > st.op_begin && plan.ops[st.op_end - 1].type == OP_UTAB;
       st.flags = (utab ? SF_LAST_UTAB : 0u) | ((st.op_end - st.op_begin > (utab ? 1 : 0)) ? SF_INDEX_OPS : 0u);
+      if (utab) st.flags |= (uint32_t)plan.ops[st.op_end - 1].slot << 8;
     }
   }
 }

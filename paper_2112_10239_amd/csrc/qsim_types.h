@@ -115,7 +115,8 @@ struct StageDesc {
 };
 // StageDesc flags: the stage has ops that read index bits (controls,
 // diagonals, measurement signs: the thread's local index is needed); its last
-// op is a factored rotation group (run after the op loop).
+// op is a factored rotation group (run after the op loop), whose first
+// coefficient slot is flags >> 8.
 enum StageFlags : uint32_t { SF_INDEX_OPS = 1, SF_LAST_UTAB = 2 };
 static_assert(sizeof(StageDesc) == 320, "StageDesc layout");
 static_assert(offsetof(StageDesc, rb) == 64, "StageDesc header");
