@@ -130,10 +130,6 @@ struct KWords {
 template <int N>
 using IC = std::integral_constant<int, N>;
 
-// XOR swizzle of an LDS slot index: lanes that differ only in bits 5..9 of
-// the local index land in different banks.
-__device__ __forceinline__ uint32_t swz(uint32_t l) { return l ^ ((l >> 5) & 31u); }
-
 template <int R, int J = 0, class F>
 __device__ __forceinline__ void for_bit(int j, F&& f) {
   if constexpr (J < R) {
@@ -478,10 +474,6 @@ __device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t M) {
 // Physical index of a tile's first amplitude: the tile number deposited at the
 // non-local positions.  Walking tiles by a fixed stride d, the next base is
 // ((base | ~M) + deposit(d, M)) & M: the carries skip the local positions.
-__device__ __forceinline__ uint64_t tile_base(kptr<PassDesc> P, uint64_t tile) {
-  return deposit(tile, nonlocal_mask(P));
-}
-
 __device__ __forceinline__ uint64_t next_base(uint64_t base, uint64_t M, uint64_t dstep) {
   return ((base | ~M) + dstep) & M;
 }
@@ -688,13 +680,51 @@ __device__ __forceinline__ void tile_load(kptr<PassDesc> P, kptr<StageDesc> S0, 
   }
 }
 
+// Stages of a pass whose LDS lane parts come from a table in LDS (the rest
+// compute them from the stage header).
+constexpr int kLaneTabStages = 24;
+
+// The lane parts of the LDS byte offsets of the pass's first kLaneTabStages
+// stages, for reads and for the writes at the stage's exit: entry 2 (64 k + l)
+// is XOR_{b : bit b of lane l} rd_lane[b] << sh of stage s0 + k, entry
+// 2 (64 k + l) + 1 the same over wr_lane.  Written by the whole workgroup
+// once per launch (the pass is the same for every tile).
+template <class T>
+__device__ __forceinline__ void fill_lane_table(kptr<PassDesc> P, kptr<StageDesc> SD, uint32_t* ltab) {
+  constexpr uint32_t kSh = sizeof(cpx<T>) == 8 ? 3u : 4u;
+  const int s0 = P->stage_begin;
+  const int nst = min(P->stage_end - s0, kLaneTabStages);
+  for (int k = threadIdx.x; k < nst * 64; k += blockDim.x) {
+    const kptr<StageDesc> S = SD + s0 + (k >> 6);
+    const int l = k & 63;
+    uint32_t r = 0, w = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+      if ((l >> b) & 1) {
+        r ^= S->rd_lane[b];
+        w ^= S->wr_lane[b];
+      }
+    ltab[2 * k] = r << kSh;
+    ltab[2 * k + 1] = w << kSh;
+  }
+  lds_sync();
+}
+
+// Byte size of the lane table of a pass with the given stage count.
+__host__ __device__ constexpr size_t lane_table_bytes(int stages) {
+  return (size_t)(stages < kLaneTabStages ? stages : kLaneTabStages) * 64 * 2 * sizeof(uint32_t);
+}
+
 // All stages of a tile whose first-stage registers are loaded: ops, LDS
 // exchanges (with exit permutations), the store, and the block's partial sums.
-template <class T, int R, bool DUAL, bool TAIL = false>
+// With LT, the lane parts of the LDS offsets of the first kLaneTabStages stages
+// are read from ltab (fill_lane_table).
+template <class T, int R, bool DUAL, bool TAIL = false, bool LT = false>
 __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD, kptr<DevOp> OPS,
                                            cpx<T>* __restrict__ A, cpx<T>* __restrict__ B, kptr<T> coef, uint64_t base,
                                            TileRegs<T, R, DUAL>& t, cpx<T>* lds, double* red, double* gacc,
-                                           double* __restrict__ grad_out, int64_t grad_stride, bool grad_add = false) {
+                                           double* __restrict__ grad_out, int64_t grad_stride, bool grad_add = false,
+                                           const uint32_t* ltab = nullptr) {
   constexpr int NR = 1 << R;
   const int m = P->m, flags = P->flags;
   const int tid = threadIdx.x;
@@ -739,9 +769,17 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     // LDS addressing precomputed per stage (swizzled slots, linear over XOR):
     // lane bits per lane, wave bits by the wave's index, register bits uniform
     // (header words: rd_lane 4..6, wr_lane 7..9, rd_reg 10..12, wr_reg 13..15)
-    uint32_t rd = rdw;
+    const bool tab = LT && s - s0 < kLaneTabStages;
+    const uint32_t* lt = ltab + 2 * ((s - s0) * 64 + lane);
+    uint32_t rd_b;  // byte offset of the thread's slot (register index 0)
+    if (tab) {
+      rd_b = lt[0] ^ (rdw << kSh);
+    } else {
+      uint32_t rd = rdw;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) rd ^= ((uint32_t)(tid >> k) & 1u) ? hd.u16(8 + k) : 0u;
+      for (int k = 0; k < 6; ++k) rd ^= ((uint32_t)(tid >> k) & 1u) ? hd.u16(8 + k) : 0u;
+      rd_b = rd << kSh;
+    }
     uint32_t sb[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) sb[j] = hd.u16(20 + j) << kSh;
@@ -754,7 +792,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     };
     // full LDS address of the thread's slot (tile at address 0), opaque to the
     // optimiser so each access is one XOR with a uniform offset
-    uint32_t tl_b = lds0 + (rd << kSh);
+    uint32_t tl_b = lds0 + rd_b;
     asm volatile("" : "+v"(tl_b));
     // the thread's local index, for ops that read index bits (controls,
     // diagonals, measurement signs); stages of a factored op alone need none
@@ -1120,14 +1158,21 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         // every amplitude to its slot in the next layout: through the stage's
         // exit permutation when it has one (the precomputed write parts are its
         // images), else the slots it was read from; register i holds index i ^ pend
-        uint32_t wr = wrw;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) wr ^= ((uint32_t)(tid >> k) & 1u) ? hd.u16(14 + k) : 0u;
-        if (n_aff > 0) {  // affine part: the tile's non-local control bits (uniform)
+        uint32_t wu = wrw;  // uniform part: wave bits and the affine part (the tile's non-local control bits)
+        if (n_aff > 0) {
           uint32_t wa = 0;
           for (int j = 0; j < (int)n_aff; ++j)
             if ((base >> kb(&S->aff_pos[j])) & 1) wa ^= kh(&S->wr_aff[j]);
-          wr ^= wa;
+          wu ^= wa;
+        }
+        uint32_t wr_b;
+        if (tab) {
+          wr_b = lt[1] ^ (wu << kSh);
+        } else {
+          uint32_t wr = wu;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) wr ^= ((uint32_t)(tid >> k) & 1u) ? hd.u16(14 + k) : 0u;
+          wr_b = wr << kSh;
         }
         uint32_t pb[R];  // byte offsets of the images of the register bits
 #pragma unroll
@@ -1136,7 +1181,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
 #pragma unroll
         for (int j = 0; j < R; ++j)
           if ((pend >> j) & 1u) wp ^= pb[j];
-        uint32_t w_b = (lds0 + (wr << kSh)) ^ wp;
+        uint32_t w_b = (lds0 + wr_b) ^ wp;
         asm volatile("" : "+v"(w_b));
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
@@ -1236,6 +1281,11 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass(
   uint64_t base = deposit(tile, M);
   tile_load<T, R, DUAL>(P, S0, A + row * row_stride, DUAL ? B + row * row_stride : nullptr, base, cur,
                         coef + row * coef_row_stride);
+  // the pass's lane table after the tile, reduction and gradient slots (while the loads are in flight)
+  uint32_t* ltab = reinterpret_cast<uint32_t*>(
+      smem + ((size_t)(DUAL ? 2 : 1) * sizeof(cpx<T>) << m) + kRedSlots * sizeof(double) +
+      (DUAL ? (size_t)kRedSlots * kMaxGradPerPass * sizeof(double) : 0));
+  fill_lane_table<T>(P, SD, ltab);
   while (true) {
     const int64_t wn = w + gridDim.x;
     const bool more = wn < total;
@@ -1248,17 +1298,20 @@ __global__ __launch_bounds__((pass_max_threads<T, R, DUAL>())) void k_pass(
         tile_load<T, R, DUAL>(P, S0, A + rown * row_stride, DUAL ? B + rown * row_stride : nullptr, basen, nxt,
                               coef + rown * coef_row_stride);
       double* gout = (DUAL && grad) ? grad + row * n_gslots * tiles + (int64_t)tile : nullptr;
-      const double v = tile_run<T, R, DUAL, TAIL>(P, SD, OPS, A + row * row_stride,
-                                                  DUAL ? B + row * row_stride : nullptr, coef + row * coef_row_stride,
-                                                  base, cur, lds, red, gacc, gout, tiles);
+      const double v = tile_run<T, R, DUAL, TAIL, true>(P, SD, OPS, A + row * row_stride,
+                                                        DUAL ? B + row * row_stride : nullptr,
+                                                        coef + row * coef_row_stride, base, cur, lds, red, gacc, gout,
+                                                        tiles, false, ltab);
       if ((P->flags & PF_MEASURE) && threadIdx.x == 0)
         meas[(row * n_meas + P->meas_index) * tiles + (int64_t)tile] = v;
       if (!more) break;
       cur = nxt;
     } else {
       double* gout = (DUAL && grad) ? grad + row * n_gslots * tiles + (int64_t)tile : nullptr;
-      const double v = tile_run<T, R, DUAL>(P, SD, OPS, A + row * row_stride, DUAL ? B + row * row_stride : nullptr,
-                                            coef + row * coef_row_stride, base, cur, lds, red, gacc, gout, tiles);
+      const double v = tile_run<T, R, DUAL, false, true>(P, SD, OPS, A + row * row_stride,
+                                                         DUAL ? B + row * row_stride : nullptr,
+                                                         coef + row * coef_row_stride, base, cur, lds, red, gacc,
+                                                         gout, tiles, false, ltab);
       if ((P->flags & PF_MEASURE) && threadIdx.x == 0)
         meas[(row * n_meas + P->meas_index) * tiles + (int64_t)tile] = v;
       if (!more) break;
@@ -1494,7 +1547,8 @@ int resident_per_cu(K kernel, int threads, size_t lds) {
 template <class T, int R, bool DUAL, bool PF, bool TAIL = false>
 hipError_t launch_pass_t(const PassLaunch& L, hipStream_t stream) {
   const int m = L.h_pass->m, n = L.h_pass->n;
-  const size_t lds = pass_lds_bytes(m, sizeof(T) == 8, DUAL);
+  const size_t lds = pass_lds_bytes(m, sizeof(T) == 8, DUAL) +
+                     lane_table_bytes(L.h_pass->stage_end - L.h_pass->stage_begin);
   auto kern = k_pass<T, R, DUAL, PF, TAIL>;
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
