@@ -481,16 +481,13 @@ __device__ __forceinline__ uint64_t next_base(uint64_t base, uint64_t M, uint64_
 // Thread-local part of stage S's local index (thread bits deposited into tb).
 template <int R>
 __device__ __forceinline__ uint32_t thread_local_index(kptr<StageDesc> S, int m, int tid) {
-  // tid's bits deposited into the thread bits (ascending) = a zero inserted at
-  // each register bit (ascending); bits past the tile are dropped
-  const KWords<2> rs(S->rbs);
-  uint32_t tl = (uint32_t)tid;
+  // tid's bit k is the local index bit tb[k]; bits past the tile are dropped
+  const KWords<kMaxLocal / 4> tb(S->tb);
+  uint32_t tl = 0;
 #pragma unroll
-  for (int j = 0; j < R; ++j) {
-    const uint32_t lo = (1u << rs.u8(j)) - 1u;
-    tl = (tl & lo) | ((tl << 1) & ~(2u * lo + 1u));
-  }
-  return tl & ((1u << m) - 1u);
+  for (int k = 0; k < kMaxLocal - R; ++k)
+    if (k < m - R) tl |= (((uint32_t)tid >> k) & 1u) << tb.u8(k);
+  return tl;
 }
 
 // Global offsets (physical index bits) of stage S: per-thread part and per-register-bit parts.
@@ -758,6 +755,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
   constexpr uint32_t kSh = sizeof(cpx<T>) == 8 ? 3u : 4u;  // slot -> byte offset
   const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
   uint32_t pend = 0;  // register i holds the amplitude of register index i ^ pend
+  bool prev_wl = false;  // the tile's previous exchange kept every amplitude in its wave
   for (int s = s0; s < s1; ++s) {
     kptr<StageDesc> S = SD + s;
     pend = 0;
@@ -1153,7 +1151,13 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
       }
     }
     if (s + 1 < s1) {
-      lds_sync();
+      // An exchange that keeps every amplitude in its wave needs no barrier
+      // before its writes when the tile's previous exchange kept them too (each
+      // wave then only ever touches its own block), and none after them (a
+      // wave's LDS operations complete in order).
+      const bool wl = (sflags & SF_WAVE_LOCAL) != 0;
+      if (!(wl && prev_wl)) lds_sync();
+      else asm volatile("" ::: "memory");
       if (active) {
         // every amplitude to its slot in the next layout: through the stage's
         // exit permutation when it has one (the precomputed write parts are its
@@ -1194,7 +1198,9 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
           if constexpr (DUAL) st_lds<T>(l + bofs, b[i]);
         }
       }
-      lds_sync();
+      if (wl) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      else lds_sync();
+      prev_wl = wl;
     }
   }
   if constexpr (TAIL) {
@@ -1556,7 +1562,12 @@ hipError_t launch_pass_t(const PassLaunch& L, hipStream_t stream) {
   // persistent workgroups: as many as fit on the device at once (registers, LDS, threads)
   const int per_cu = resident_per_cu(kern, threads, lds);
   const int64_t total = (int64_t)L.rows << (n - m);
-  const int64_t grid = std::min<int64_t>(total, (int64_t)device_cus() * per_cu);
+  static const int persist = [] {
+    const char* e = getenv("QSIM_PERSIST");
+    return e ? atoi(e) : 1;
+  }();
+  const int64_t grid = (PF || persist) ? std::min<int64_t>(total, (int64_t)device_cus() * per_cu)
+                                       : std::min<int64_t>(total, 0x7fffffff);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, stream, L.d_pass, L.d_stages, L.d_ops,
                      reinterpret_cast<cpx<T>*>(L.A), reinterpret_cast<cpx<T>*>(L.B), L.row_stride,
                      reinterpret_cast<const T*>(L.coef), L.coef_row_stride, L.meas, L.n_meas, L.grad, L.n_gslots,

@@ -297,6 +297,7 @@ struct StageBuild {
   std::vector<int> rb;  // local indices
   std::vector<const PGate*> items;
   std::vector<const PGate*> perm;  // CNOTs applied as the stage's exit permutation, in order
+  std::vector<int> tord;           // thread bits as local indices: lane bits first, then wave bits
 };
 
 // Relative costs used to choose between stage layouts (one LDS exchange of the
@@ -636,6 +637,93 @@ struct PassEmitter {
     return v;
   }
 
+  // Thread orders of stages first.. of a pass.  Lane bits are the lowest
+  // non-register local indices except for the wave bits (the top m - r - 6
+  // thread bits); the wave bits are chosen per stage so that as many exchanges
+  // as possible keep every amplitude in its wave: the same wave bits on both
+  // sides and no CNOT of the writer's exit permutation targeting one of them.
+  // Such an exchange needs no workgroup barrier (each wave writes and reads its
+  // own block of LDS).  Stages that load or store keep the lowest bits as lane
+  // bits (whole segments per access).
+  void choose_thread_orders(std::vector<StageBuild>& sb, int first, bool load_first, int store_idx) const {
+    const int ns = (int)sb.size(), nt = m - r, nw = nt - 6;
+    for (int s = first; s < ns; ++s) {
+      sb[s].tord.clear();
+      for (int k = 0; k < m; ++k)
+        if (!rb_has(sb[s].rb, k)) sb[s].tord.push_back(k);
+    }
+    if (nw <= 0 || ns - first < 2) return;
+    std::vector<std::vector<uint32_t>> cand(ns);
+    std::vector<uint32_t> tgt(ns, 0);
+    size_t width = 1;
+    for (int s = first; s < ns; ++s) {
+      const std::vector<int>& T = sb[s].tord;
+      for (const PGate* g : sb[s].perm) tgt[s] |= 1u << lidx[g->q];
+      uint32_t top = 0;
+      for (int k = nt - nw; k < nt; ++k) top |= 1u << T[k];
+      if ((s == first && load_first) || s == store_idx) {
+        cand[s] = {top};
+        continue;
+      }
+      // every nw-subset of the thread bits (the default, the top ones, first)
+      cand[s].push_back(top);
+      std::vector<int> idx(nw);
+      for (int i = 0; i < nw; ++i) idx[i] = i;
+      while (true) {
+        uint32_t w = 0;
+        for (int i = 0; i < nw; ++i) w |= 1u << T[idx[i]];
+        if (w != top) cand[s].push_back(w);
+        int i = nw - 1;
+        while (i >= 0 && idx[i] == nt - nw + i) --i;
+        if (i < 0) break;
+        ++idx[i];
+        for (int j = i + 1; j < nw; ++j) idx[j] = idx[j - 1] + 1;
+      }
+      width = std::max(width, cand[s].size());
+    }
+    // longest chain of barrier-free exchanges: dynamic programme over the
+    // stages (greedy beyond a size bound: keep the previous wave bits when allowed)
+    std::vector<uint32_t> pick(ns);
+    if ((double)ns * (double)width * (double)width <= 4e6) {
+      std::vector<std::vector<int>> score(ns), from(ns);
+      score[first].assign(cand[first].size(), 0);
+      from[first].assign(cand[first].size(), -1);
+      for (int s = first + 1; s < ns; ++s) {
+        score[s].assign(cand[s].size(), -1);
+        from[s].assign(cand[s].size(), 0);
+        for (size_t c = 0; c < cand[s].size(); ++c)
+          for (size_t p = 0; p < cand[s - 1].size(); ++p) {
+            const int v = score[s - 1][p] + ((cand[s - 1][p] == cand[s][c] && !(tgt[s - 1] & cand[s][c])) ? 1 : 0);
+            if (v > score[s][c]) {
+              score[s][c] = v;
+              from[s][c] = (int)p;
+            }
+          }
+      }
+      int c = 0;
+      for (size_t k = 1; k < cand[ns - 1].size(); ++k)
+        if (score[ns - 1][k] > score[ns - 1][c]) c = (int)k;
+      for (int s = ns - 1; s >= first; --s) {
+        pick[s] = cand[s][c];
+        c = from[s][c];
+      }
+    } else {
+      pick[first] = cand[first][0];
+      for (int s = first + 1; s < ns; ++s) {
+        pick[s] = cand[s][0];
+        if (!(tgt[s - 1] & pick[s - 1]))
+          for (uint32_t w : cand[s])
+            if (w == pick[s - 1]) pick[s] = w;
+      }
+    }
+    for (int s = first; s < ns; ++s) {
+      std::vector<int> lanes, waves;
+      for (int k : sb[s].tord) ((pick[s] >> k) & 1u ? waves : lanes).push_back(k);
+      sb[s].tord = lanes;
+      sb[s].tord.insert(sb[s].tord.end(), waves.begin(), waves.end());
+    }
+  }
+
   // The first stage of a loading pass only permutes: fold its CNOT run into the
   // loads of the next stage (registers read from M^-1 (l ^ b)) and drop it.
   bool fold_entry(std::vector<StageBuild>& sb, PassDesc& pd) const {
@@ -676,8 +764,7 @@ struct PassEmitter {
     const StageBuild& s1 = sb[1];
     pd.entry_perm = 1;
     int t = 0;
-    for (int k = 0; k < m; ++k)
-      if (!rb_has(s1.rb, k)) pd.ecol[t++] = phys(minv(1u << k));
+    for (int k : s1.tord) pd.ecol[t++] = phys(minv(1u << k));
     for (int j = 0; j < r; ++j) pd.ereg[j] = phys(minv(1u << s1.rb[j]));
     pd.n_eaff = 0;
     for (auto& a : aff)
@@ -718,8 +805,7 @@ struct PassEmitter {
     if (s.perm.empty()) return;
     st.has_perm = 1;
     int t = 0;
-    for (int k = 0; k < m; ++k)
-      if (!rb_has(s.rb, k)) st.tcol[t++] = (uint16_t)col[k];
+    for (int k : s.tord) st.tcol[t++] = (uint16_t)col[k];
     for (int i = 0; i < (1 << r); ++i) {
       uint32_t v = 0;
       for (int j = 0; j < r; ++j)
@@ -770,8 +856,13 @@ struct PassEmitter {
     pd.r = r;
     pd.flags = flags;
     const int pass_no0 = (int)plan.passes.size();
-    if (allow_entry && (flags & PF_LOAD_A) && !(flags & (PF_LOAD_B | PF_INIT)) && store_rel != 0 &&
-        fold_entry(sb, pd)) {
+    bool folded = false;
+    if (allow_entry && (flags & PF_LOAD_A) && !(flags & (PF_LOAD_B | PF_INIT)) && store_rel != 0 && sb.size() >= 2) {
+      choose_thread_orders(sb, 1, true, store_rel);  // the second stage loads once the first is folded
+      folded = fold_entry(sb, pd);
+    }
+    if (!folded) choose_thread_orders(sb, 0, loads, store_rel);
+    if (folded) {
       for (const PGate* g : sb[0].perm)
         for (int src : g->srcs) {  // applied while loading: ahead of the first stage's ops
           plan.order.push_back(pass_no0);
@@ -809,11 +900,10 @@ struct PassEmitter {
       }
       {
         int t = 0;
-        for (int k = 0; k < m; ++k)
-          if (!rb_has(rb, k)) {
-            st.tpos[t] = (uint8_t)L[k];
-            st.tb[t++] = (uint8_t)k;
-          }
+        for (int k : sb[si].tord) {
+          st.tpos[t] = (uint8_t)L[k];
+          st.tb[t++] = (uint8_t)k;
+        }
       }
       st.op_begin = (int)plan.ops.size();
       const auto& its = sb[si].items;
@@ -1085,8 +1175,7 @@ struct PassEmitter {
       const StageBuild& sl = sb.back();
       pd.exit_perm = 1;
       int t = 0;
-      for (int k = 0; k < m; ++k)
-        if (!rb_has(sl.rb, k)) pd.xcol[t++] = phys(col[k]);
+      for (int k : sl.tord) pd.xcol[t++] = phys(col[k]);
       for (int j = 0; j < r; ++j) pd.xreg[j] = phys(col[sl.rb[j]]);
       pd.n_xaff = 0;
       for (auto& a : aff)
@@ -1110,46 +1199,144 @@ struct PassEmitter {
   }
 };
 
-// The swizzled LDS slot of a local index: lanes that differ only in bits 5..9
-// land in different banks.  Linear over XOR.
-uint32_t swz_slot(uint32_t l) { return l ^ ((l >> 5) & 31u); }
+// LDS slot maps.  The exchange after stage s of a pass (written by stage s
+// through its exit permutation, read by stage s + 1) stores local index l at
+// slot sigma(l), a linear bijection over GF(2) (rows: sigma(l) bit i = parity
+// of row[i] & l).  An 8-byte slot's bank pair is its low five bits: reads serve
+// 32 lanes per cycle and writes 16, so the low five rows are the reader's lane
+// bits 0..4 plus terms outside them chosen so that the writer's lane bits 0..3
+// also land in distinct banks.  In an exchange that keeps every amplitude in
+// its wave the wave bits are the top rows: each wave owns one block of slots.
+struct SlotMap {
+  int m = 0;
+  uint32_t row[kMaxLocal] = {0};
+  uint32_t operator()(uint32_t l) const {
+    uint32_t v = 0;
+    for (int i = 0; i < m; ++i) v |= (uint32_t)(__builtin_popcount(row[i] & l) & 1) << i;
+    return v;
+  }
+};
+
+static int rank_low5(const SlotMap& sg, const uint32_t* v, int k) {
+  uint32_t b[5] = {0, 0, 0, 0, 0};
+  int r = 0;
+  for (int i = 0; i < k; ++i) {
+    uint32_t x = sg(v[i]) & 31u;
+    for (int j = 4; j >= 0 && x; --j)
+      if ((x >> j) & 1u) {
+        if (!b[j]) {
+          b[j] = x;
+          ++r;
+          break;
+        }
+        x ^= b[j];
+      }
+  }
+  return r;
+}
+
+// reader lanes 0..4 (local indices), writer lane images 0..3, wave bits (mask, 0: none)
+static SlotMap make_slot_map(int m, const uint8_t* rd_lanes, int n_rd, const uint32_t* wr_imgs, int n_wr,
+                             uint32_t waves) {
+  SlotMap sg;
+  sg.m = m;
+  if (n_rd < 5 || m < 5 + __builtin_popcount(waves)) {
+    for (int i = 0; i < m; ++i) sg.row[i] = 1u << i;
+    return sg;
+  }
+  uint32_t P = 0;
+  for (int i = 0; i < 5; ++i) P |= 1u << rd_lanes[i];
+  std::vector<int> Q;  // the rest, outside the wave bits
+  for (int k = 0; k < m; ++k)
+    if (!((P | waves) >> k & 1u)) Q.push_back(k);
+  int i = 5;
+  for (int k : Q) sg.row[i++] = 1u << k;
+  for (int k = 0; k < m; ++k)
+    if ((waves >> k) & 1u) sg.row[i++] = 1u << k;
+  // low rows: the reader's lane bits, plus terms over Q (zero on the reader's
+  // lanes) until the writer's lanes 0..3 reach four distinct bank bits
+  for (int b = 0; b < 5; ++b) sg.row[b] = 1u << rd_lanes[b];
+  const int want = std::min(n_wr, 4);
+  int best = rank_low5(sg, wr_imgs, want);
+  uint32_t rs = 0x9e3779b9u;
+  SlotMap trial = sg;
+  for (int t = 0; t < 256 && best < want && !Q.empty(); ++t) {
+    for (int b = 0; b < 5; ++b) {
+      uint32_t g = 0;
+      for (int k : Q) {
+        rs = rs * 1664525u + 1013904223u;
+        if (rs >> 31) g |= 1u << k;
+      }
+      trial.row[b] = (1u << rd_lanes[b]) | g;
+    }
+    const int rk = rank_low5(trial, wr_imgs, want);
+    if (rk > best) {
+      best = rk;
+      sg = trial;
+    }
+  }
+  return sg;
+}
 
 // Fills the precomputed LDS addressing of every stage of a plan (StageDesc
-// rd_* / wr_* fields) from its register bits, thread bits and exit permutation.
+// rd_* / wr_* fields and flags) from its register bits, thread bits and exit
+// permutation, with one slot map per exchange.
 void stage_addressing(Plan& plan) {
   for (const PassDesc& pd : plan.passes) {
-    const int m = pd.m, r = pd.r, nt = m - r;
+    const int m = pd.m, r = pd.r, nt = m - r, nw = std::max(0, nt - 6);
     for (int s = pd.stage_begin; s < pd.stage_end; ++s) {
       StageDesc& st = plan.stages[s];
-      uint32_t rd_t[kMaxLocal] = {0}, wr_t[kMaxLocal] = {0};
-      for (int k = 0; k < nt && k < kMaxLocal; ++k) {
-        rd_t[k] = swz_slot(1u << st.tb[k]);
-        wr_t[k] = st.has_perm ? swz_slot(st.tcol[k]) : rd_t[k];
-      }
-      for (int k = 0; k < 6; ++k) {
-        st.rd_lane[k] = (uint16_t)rd_t[k];
-        st.wr_lane[k] = (uint16_t)wr_t[k];
-      }
-      for (int w = 0; w < 16; ++w) {
-        uint32_t a = 0, b = 0;
-        for (int bit = 0; bit < 4; ++bit)
-          if ((w >> bit) & 1) {
-            a ^= rd_t[6 + bit];
-            b ^= wr_t[6 + bit];
-          }
-        st.rd_wave[w] = (uint16_t)a;
-        st.wr_wave[w] = (uint16_t)b;
-      }
-      for (int j = 0; j < 6; ++j) {
-        st.rd_reg[j] = j < r ? (uint16_t)swz_slot(1u << st.rb[j]) : 0;
-        st.wr_reg[j] = j < r ? (uint16_t)(st.has_perm ? swz_slot(st.preg[1u << j]) : st.rd_reg[j]) : 0;
-      }
-      for (int j = 0; j < kMaxAffine; ++j)
-        st.wr_aff[j] = (st.has_perm && j < st.n_aff) ? (uint16_t)swz_slot(st.aff_mask[j]) : 0;
-      // the ops before a trailing factored group (that one runs after the op loop)
+      std::memset(st.rd_lane, 0, sizeof(st.rd_lane));
+      std::memset(st.rd_reg, 0, sizeof(st.rd_reg));
+      std::memset(st.rd_wave, 0, sizeof(st.rd_wave));
+      std::memset(st.wr_lane, 0, sizeof(st.wr_lane));
+      std::memset(st.wr_reg, 0, sizeof(st.wr_reg));
+      std::memset(st.wr_wave, 0, sizeof(st.wr_wave));
+      std::memset(st.wr_aff, 0, sizeof(st.wr_aff));
       const bool utab = st.op_end > st.op_begin && plan.ops[st.op_end - 1].type == OP_UTAB;
       st.flags = (utab ? SF_LAST_UTAB : 0u) | ((st.op_end - st.op_begin > (utab ? 1 : 0)) ? SF_INDEX_OPS : 0u);
       if (utab) st.flags |= (uint32_t)plan.ops[st.op_end - 1].slot << 8;
+    }
+    for (int s = pd.stage_begin; s + 1 < pd.stage_end; ++s) {
+      StageDesc& w = plan.stages[s];
+      StageDesc& rd = plan.stages[s + 1];
+      // images of the writer's thread and register bits (and affine terms) in the local index
+      uint32_t img_t[kMaxLocal] = {0}, img_r[8] = {0};
+      for (int k = 0; k < nt; ++k) img_t[k] = w.has_perm ? w.tcol[k] : 1u << w.tb[k];
+      for (int j = 0; j < r; ++j) img_r[j] = w.has_perm ? w.preg[1u << j] : 1u << w.rb[j];
+      // every amplitude stays in its wave: the same wave bits on both sides,
+      // and the writer's images keep the wave coordinates
+      uint32_t wmask = 0;
+      bool local = nw > 0;
+      for (int k = 6; k < nt && local; ++k) {
+        wmask |= 1u << w.tb[k];
+        local = w.tb[k] == rd.tb[k];
+      }
+      for (int k = 0; k < nt && local; ++k) local = (img_t[k] & wmask) == ((1u << w.tb[k]) & wmask);
+      for (int j = 0; j < r && local; ++j) local = (img_r[j] & wmask) == ((1u << w.rb[j]) & wmask);
+      for (int j = 0; j < (int)w.n_aff && local && w.has_perm; ++j) local = (w.aff_mask[j] & wmask) == 0;
+      const SlotMap sg = make_slot_map(m, rd.tb, std::min(nt, 6), img_t, std::min(nt, 6), local ? wmask : 0u);
+      if (local) w.flags |= SF_WAVE_LOCAL;
+      for (int k = 0; k < 6; ++k) {
+        rd.rd_lane[k] = k < nt ? (uint16_t)sg(1u << rd.tb[k]) : 0;
+        w.wr_lane[k] = k < nt ? (uint16_t)sg(img_t[k]) : 0;
+      }
+      for (int v = 0; v < 16; ++v) {
+        uint32_t a = 0, b = 0;
+        for (int bit = 0; bit < 4; ++bit)
+          if (((v >> bit) & 1) && 6 + bit < nt) {
+            a ^= sg(1u << rd.tb[6 + bit]);
+            b ^= sg(img_t[6 + bit]);
+          }
+        rd.rd_wave[v] = (uint16_t)a;
+        w.wr_wave[v] = (uint16_t)b;
+      }
+      for (int j = 0; j < r; ++j) {
+        rd.rd_reg[j] = (uint16_t)sg(1u << rd.rb[j]);
+        w.wr_reg[j] = (uint16_t)sg(img_r[j]);
+      }
+      for (int j = 0; j < kMaxAffine; ++j)
+        w.wr_aff[j] = (w.has_perm && j < w.n_aff) ? (uint16_t)sg(w.aff_mask[j]) : 0;
     }
   }
 }

@@ -101,7 +101,7 @@ struct StageDesc {
   uint16_t wr_reg[6];
   // the rest
   uint8_t rb[8];            // register bits as local indices
-  uint8_t tb[kMaxLocal];    // thread bits as local indices, ascending (m - r used)
+  uint8_t tb[kMaxLocal];    // thread bits as local indices: lane bits, then wave bits (m - r used)
   uint16_t tcol[kMaxLocal]; // M applied to thread bit k
   uint16_t preg[1 << kMaxRegBits];  // M applied to register offset i
   uint8_t aff_pos[kMaxAffine];      // physical non-local bit of affine term j
@@ -116,8 +116,10 @@ struct StageDesc {
 // StageDesc flags: the stage has ops that read index bits (controls,
 // diagonals, measurement signs: the thread's local index is needed); its last
 // op is a factored rotation group (run after the op loop), whose first
-// coefficient slot is flags >> 8.
-enum StageFlags : uint32_t { SF_INDEX_OPS = 1, SF_LAST_UTAB = 2 };
+// coefficient slot is flags >> 8; the exchange that ends the stage keeps every
+// amplitude in its wave (each wave writes and reads its own block of slots, no
+// workgroup barrier).
+enum StageFlags : uint32_t { SF_INDEX_OPS = 1, SF_LAST_UTAB = 2, SF_WAVE_LOCAL = 4 };
 static_assert(sizeof(StageDesc) == 320, "StageDesc layout");
 static_assert(offsetof(StageDesc, rb) == 64, "StageDesc header");
 
