@@ -300,7 +300,8 @@ int to_terms(qsim_ctx* ctx, const qsim_hamiltonian* H, int n, std::vector<Term>&
       return QSIM_EINVAL;
     }
     out[t].c = H->coeff[t];
-    for (int k = a; k < b; ++k) out[t].ops.emplace_back(H->qubits[k], (char)H->paulis[k]);
+    out[t].ops.resize(b - a);
+    for (int k = a; k < b; ++k) out[t].ops[k - a] = {H->qubits[k], (char)H->paulis[k]};
   }
   const std::string err = validate_terms(out, n);
   if (!err.empty()) {
@@ -449,9 +450,13 @@ std::shared_ptr<DevPlan> get_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, con
   for (const PGate& t : meas) diag &= t.fmask == 0;
   if (!measure || meas.empty() || diag) {
     // gates from the structure cache, diagonal terms appended to its last stage
+    // (the combined plan cached under the circuit and the terms)
     auto gp = gate_plan(ctx, c, c128, init, store_final, rc);
     if (!gp) return nullptr;
     if (meas.empty() && cst == 0.0) return gp;
+    const int dextra = 0x700 | c128 | (init << 1) | (store_final << 2) | (measure << 3);
+    const std::string dkey = structure_key(c, terms, dextra);
+    if (auto p = cache_get(ctx, dkey)) return p;
     auto dp = std::make_shared<DevPlan>();
     dp->plan = gp->plan;
     append_diag_measure(dp->plan, meas);
@@ -461,6 +466,7 @@ std::shared_ptr<DevPlan> get_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, con
       rc = hip_fail(ctx, e, "plan upload");
       return nullptr;
     }
+    cache_put(ctx, dkey, dp);
     return dp;
   }
   const int extra = 0x100 | c128 | (init << 1) | (store_final << 2) | (measure << 3);
@@ -746,6 +752,16 @@ struct ConePacker {
   }
 };
 
+// HBM scratch bytes (only cones above the tile size touch it) and algorithmic
+// flops of a cone launch, for its timing record.
+static void cone_costs(DevPlan& dp, int c128) {
+  dp.cone_bytes = dp.cone_flops = 0;
+  for (const PassDesc& pd : dp.plan.passes) {
+    if (pd.n > pd.m) dp.cone_bytes += pass_bytes(pd, 1, c128);
+    dp.cone_flops += pass_flops_per_amp(dp.plan, pd) * (double)(1ull << pd.n);
+  }
+}
+
 std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, int c128,
                                        int& rc) {
   rc = QSIM_OK;
@@ -765,6 +781,7 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
     }
   }
   pk.finish();
+  cone_costs(*dp, c128);
   hipError_t e = dp->upload(ctx->mock);
   if (e != hipSuccess) {
     rc = hip_fail(ctx, e, "plan upload");
@@ -860,6 +877,7 @@ std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, co
       for (int k = dp->t_off[t]; k < dp->t_off[t + 1]; ++k) dp->f_terms[fill[dp->t_fac[k]]++] = t;
   }
   pk.finish();
+  cone_costs(*dp, c128);
   hipError_t e = dp->upload(ctx->mock);
   if (e != hipSuccess) {
     rc = hip_fail(ctx, e, "plan upload");
@@ -876,6 +894,9 @@ std::shared_ptr<DevPlan> get_factor_plan(qsim_ctx* ctx, const CircuitDesc& c, co
 // Coefficient rows of a plan's slots: built on the host from host parameters and
 // uploaded, or built on the device from device parameters (the circuit's gate
 // table is uploaded when it differs from the last one).
+// Slots x rows from which coefficient rows of host parameters are built on the device.
+constexpr size_t kDeviceCoefSlots = 512;
+
 static int stage_coefficients(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c,
                               const ParamSrc& params, int rows, int c128, hipStream_t st, int64_t& crs) {
   const std::vector<PGate>& slots = dp.plan.slots;
@@ -883,7 +904,18 @@ static int stage_coefficients(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, c
   crs = (int64_t)std::max<size_t>(1, slots.size()) * 8;
   const size_t bytes = (size_t)rows * crs * scal;
   HIP_TRY(ws.coef.ensure(bytes), "coefficient buffer");
-  if (params.dev) {
+  // many slots: the parameters go to the device and the rows are built there
+  // (the same definition as on the host, bit for bit)
+  const double* dev_params = params.dev ? params.p : nullptr;
+  if (!params.dev && params.p && c.n_params > 0 && slots.size() * (size_t)rows >= kDeviceCoefSlots) {
+    const size_t pb = (size_t)rows * c.n_params * sizeof(double);
+    HIP_TRY(ws.params.ensure(pb), "parameter buffer");
+    HIP_TRY(ws.h_params.ensure(pb), "pinned parameter buffer");
+    std::memcpy(ws.h_params.p, params.p, pb);
+    HIP_TRY(hipMemcpyAsync(ws.params.p, ws.h_params.p, pb, hipMemcpyHostToDevice, st), "parameter upload");
+    dev_params = (const double*)ws.params.p;
+  }
+  if (dev_params) {
     if (slots.empty()) return QSIM_OK;
     std::vector<CoefGate> gt;
     coef_gate_table(c, gt);
@@ -900,7 +932,7 @@ static int stage_coefficients(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, c
       }
       ws.last_gates.swap(gt);
     }
-    HIP_TRY(launch_build_coef(dp.d_cslots, (int)slots.size(), dp.d_csrcs, (const CoefGate*)ws.gates.p, params.p,
+    HIP_TRY(launch_build_coef(dp.d_cslots, (int)slots.size(), dp.d_csrcs, (const CoefGate*)ws.gates.p, dev_params,
                               c.n_params, rows, ws.coef.p, crs, c128, st),
             "coefficient build");
     return QSIM_OK;
@@ -1104,12 +1136,7 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
   L.r = 4;
   L.c128 = c128;
   L.dual = 0;
-  double cone_bytes = 0, cone_flops = 0;  // only cones above the tile size touch HBM scratch
-  for (const PassDesc& pd : P.passes) {
-    if (pd.n > pd.m) cone_bytes += pass_bytes(pd, 1, c128);
-    cone_flops += pass_flops_per_amp(P, pd) * (double)(1ull << pd.n);
-  }
-  const int ti = timing_begin(ctx, st, cone_bytes, 0, 1, cone_flops);
+  const int ti = timing_begin(ctx, st, dp.cone_bytes, 0, 1, dp.cone_flops);
   HIP_TRY(launch_cones(L, st), "cone launch");
   timing_end(ctx, ti, st);
   HIP_TRY(ws.out.ensure(sizeof(double)), "result buffer");

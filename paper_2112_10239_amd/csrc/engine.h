@@ -93,13 +93,15 @@ struct DevPlan {
   int32_t* d_gcone = nullptr;
   int32_t* d_foff = nullptr;
   int32_t* d_fterms = nullptr;
+  // cone launches: HBM scratch bytes and algorithmic flops (timing records), once per plan
+  double cone_bytes = -1, cone_flops = 0;
   ~DevPlan();
   hipError_t upload(bool mock);
 };
 
 struct Workspace {
-  DevBuf coef, meas, grad, slot_total, out, scratch, lambda, weights, table, dens, gates, block;
-  HostBuf h_coef, h_out, h_gates;
+  DevBuf coef, meas, grad, slot_total, out, scratch, lambda, weights, table, dens, gates, block, params;
+  HostBuf h_coef, h_out, h_gates, h_params;
   std::vector<CoefGate> last_gates;  // content of 'gates' (device gate table)
   void release() {
     gates.release();
@@ -118,6 +120,8 @@ struct Workspace {
     block.release();
     h_coef.release();
     h_out.release();
+    params.release();
+    h_params.release();
   }
 };
 

@@ -35,18 +35,18 @@ std::string validate_circuit(const CircuitDesc& c) {
   if (c.n_params < 0) return "n_params < 0";
   for (size_t g = 0; g < c.gates.size(); ++g) {
     const Gate& x = c.gates[g];
-    const std::string at = "gate " + std::to_string(g) + ": ";
-    if (x.q0 < 0 || x.q0 >= c.n) return at + "qubit out of range";
+    auto at = [g](const char* what) { return "gate " + std::to_string(g) + ": " + what; };
+    if (x.q0 < 0 || x.q0 >= c.n) return at("qubit out of range");
     switch (x.kind) {
       case G_CZ:
       case G_CNOT:
-        if (x.q1 < 0 || x.q1 >= c.n) return at + "second qubit out of range";
-        if (x.q1 == x.q0) return at + "duplicate qubit";
+        if (x.q1 < 0 || x.q1 >= c.n) return at("second qubit out of range");
+        if (x.q1 == x.q0) return at("duplicate qubit");
         break;
       case G_RX:
       case G_RY:
       case G_RZ:
-        if (x.param >= c.n_params) return at + "parameter index out of range";
+        if (x.param >= c.n_params) return at("parameter index out of range");
         break;
       case G_U1: {  // the factored rotation form relies on unitarity
         double err = 0;
@@ -61,11 +61,11 @@ std::string validate_circuit(const CircuitDesc& c) {
             }
             err = std::max(err, std::max(std::fabs(re), std::fabs(im)));
           }
-        if (!(err <= 1e-8)) return at + "U1 matrix is not unitary";
+        if (!(err <= 1e-8)) return at("U1 matrix is not unitary");
         break;
       }
       default:
-        return at + "unknown gate kind";
+        return at("unknown gate kind");
     }
   }
   return "";
@@ -1799,9 +1799,14 @@ void coef_gate_table(const CircuitDesc& c, std::vector<CoefGate>& out) {
 
 std::string structure_key(const CircuitDesc& c, const std::vector<Term>& terms, int extra) {
   // every field a plan depends on, in a fixed byte layout: equal keys mean equal structure
-  std::string k;
-  k.reserve(24 + 16 * c.gates.size() + 24 * terms.size());
-  auto put = [&](uint64_t v) { k.append(reinterpret_cast<const char*>(&v), sizeof v); };
+  size_t words = 5 + 2 * c.gates.size();
+  for (const Term& t : terms) words += 2 + t.ops.size();
+  std::string k(words * sizeof(uint64_t), '\0');
+  char* wp = &k[0];
+  auto put = [&](uint64_t v) {
+    std::memcpy(wp, &v, sizeof v);
+    wp += sizeof v;
+  };
   put((uint64_t)c.n);
   put((uint64_t)c.n_params);
   put((uint64_t)(uint32_t)extra);
