@@ -157,7 +157,9 @@ PlanOptions fwd_options(const qsim_options& co, int c128) {
 PlanOptions cone_options(const qsim_options& co, int c128) {
   PlanOptions o = fwd_options(co, c128);
   o.r = 4;  // the cone kernel keeps 16 amplitudes per thread
-  o.factored = false;
+  // factored rotation groups (float cones); every cone starts from |0...0>
+  // (its coefficient slots are shared between cones, the start state's are not)
+  o.init_factors = false;
   o.io_lo = -1;
   return o;
 }
@@ -174,6 +176,11 @@ PlanOptions dual_options(const qsim_options& co, int c128) {
 }
 
 bool prefetch_on(const qsim_options& co) { return !opt_off(co, QSIM_OFF_PREFETCH, "QSIM_FWD_PF", true); }
+
+DevPlan::DevPlan() {
+  static std::atomic<uint64_t> next{1};
+  uid = next++;
+}
 
 DevPlan::~DevPlan() {
   (void)hipFree(d_passes);
@@ -631,7 +638,8 @@ struct ConePacker {
     }
     for (size_t k = 0; k < cp.ops.size(); ++k) {
       DevOp op = cp.ops[k];
-      if (op.type == OP_U || op.type == OP_RY || op.type == OP_PHASE || (op.type == OP_PTAB && op.slot >= 0))
+      if (op.type == OP_U || op.type == OP_RY || op.type == OP_PHASE || op.type == OP_UTAB || op.type == OP_DTAB ||
+          (op.type == OP_PTAB && op.slot >= 0))
         op.slot = remap[op.slot];
       if (op.type == OP_GRAD_X || op.type == OP_GRAD_Y || op.type == OP_GRAD_Z) op.slot += gb;
       all.ops.push_back(op);
@@ -702,6 +710,7 @@ struct ConePacker {
     o.init = true;
     o.store_final = grad;
     Plan cp;
+    cp.slots = slots;  // factored groups append their table blocks after these
     if (plan_forward(s_eff, pg, meas, o, cp, err)) return QSIM_EINVAL;
     const int cone = (int)dp.cones.size();
     ConeDesc cd;
@@ -714,7 +723,7 @@ struct ConePacker {
       cd.scratch_off = dp.scratch_amps;
       dp.scratch_amps += (int64_t)(grad ? 2 : 1) << s_eff;
     }
-    append(cp, slots, cone);
+    append(cp, cp.slots, cone);
     if (grad) {
       Plan hp, ap;
       if (plan_happly(s_eff, hterms, base, hp, err)) return QSIM_EINVAL;
@@ -762,6 +771,43 @@ static void cone_costs(DevPlan& dp, int c128) {
   }
 }
 
+// Levels of batched passes for canonical cones (complex64): every cone's k-th
+// pass in level k, the measuring passes' tile partials laid out cone after
+// cone.  Left empty (cones run one workgroup each) when a measuring pass has a
+// measurement index above 0.
+static void cone_levels(DevPlan& dp) {
+  const Plan& P = dp.plan;
+  int depth = 0;
+  for (const ConeDesc& x : dp.cones) depth = std::max(depth, x.pass_end - x.pass_begin);
+  dp.lvl_cone.assign(depth, {});
+  dp.lvl_pass.assign(depth, {});
+  dp.lvl_part.assign(depth, {});
+  int64_t parts = 0;
+  for (int ci = 0; ci < (int)dp.cones.size(); ++ci) {
+    const ConeDesc& x = dp.cones[ci];
+    for (int p = x.pass_begin; p < x.pass_end; ++p) {
+      const PassDesc& pd = P.passes[p];
+      const int k = p - x.pass_begin;
+      int64_t off = -1;
+      if (pd.flags & PF_MEASURE) {
+        if (pd.meas_index != 0) {
+          dp.lvl_cone.clear();
+          dp.lvl_pass.clear();
+          dp.lvl_part.clear();
+          dp.n_parts = 0;
+          return;
+        }
+        off = parts;
+        parts += 1ll << (pd.n - pd.m);
+      }
+      dp.lvl_cone[k].push_back(ci);
+      dp.lvl_pass[k].push_back(p);
+      dp.lvl_part[k].push_back(off);
+    }
+  }
+  dp.n_parts = parts;
+}
+
 std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, int c128,
                                        int& rc) {
   rc = QSIM_OK;
@@ -782,6 +828,7 @@ std::shared_ptr<DevPlan> get_cone_plan(qsim_ctx* ctx, const CircuitDesc& c, cons
   }
   pk.finish();
   cone_costs(*dp, c128);
+  if (!c128) cone_levels(*dp);
   hipError_t e = dp->upload(ctx->mock);
   if (e != hipSuccess) {
     rc = hip_fail(ctx, e, "plan upload");
@@ -1136,6 +1183,64 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
   L.r = 4;
   L.c128 = c128;
   L.dual = 0;
+  if (!dp.factored && !terms_host && !c128 && !dp.lvl_pass.empty()) {
+    // every cone's k-th pass in one launch, its tiles spread over workgroups;
+    // E = the sum of all measuring tiles' partials
+    HIP_TRY(ws.slot_total.ensure(std::max<int64_t>(1, dp.n_parts) * sizeof(double)), "cone tile partials");
+    const float* cf = (const float*)ws.coef.p;
+    if (ws.items_uid != dp.uid || ws.items_coef != ws.coef.p || ws.items_scratch != ws.scratch.p ||
+        ws.items_parts != ws.slot_total.p) {
+      std::vector<PassItem> items;
+      ws.items_lvl_begin.clear();
+      ws.items_lvl_tiles.clear();
+      ws.items_lvl_m.clear();
+      for (size_t k = 0; k < dp.lvl_pass.size(); ++k) {
+        ws.items_lvl_begin.push_back((int64_t)items.size());
+        int64_t tiles = 0;
+        int mm = 0;
+        for (size_t i = 0; i < dp.lvl_pass[k].size(); ++i) {
+          const ConeDesc& x = dp.cones[dp.lvl_cone[k][i]];
+          const int p = dp.lvl_pass[k][i];
+          const PassDesc& pd = P.passes[p];
+          PassItem it;
+          it.pass = dp.d_passes + p;
+          it.stages = dp.d_stages;
+          it.ops = dp.d_ops;
+          it.A = (char*)ws.scratch.p + (size_t)x.scratch_off * amp;
+          it.B = nullptr;
+          it.coef = cf + (int64_t)x.coef_begin * 8;
+          it.meas = dp.lvl_part[k][i] >= 0 ? (double*)ws.slot_total.p + dp.lvl_part[k][i] : nullptr;
+          it.grad = nullptr;
+          it.tile_begin = tiles;
+          tiles += 1ll << (pd.n - pd.m);
+          mm = std::max(mm, (int)pd.m);
+          items.push_back(it);
+        }
+        ws.items_lvl_tiles.push_back(tiles);
+        ws.items_lvl_m.push_back(mm);
+      }
+      ws.items_lvl_begin.push_back((int64_t)items.size());
+      HIP_TRY(ws.items.ensure(items.size() * sizeof(PassItem)), "cone items");
+      HIP_TRY(hipMemcpy(ws.items.p, items.data(), items.size() * sizeof(PassItem), hipMemcpyHostToDevice),
+              "cone items upload");
+      ws.items_uid = dp.uid;
+      ws.items_coef = ws.coef.p;
+      ws.items_scratch = ws.scratch.p;
+      ws.items_parts = ws.slot_total.p;
+    }
+    const int ti = timing_begin(ctx, st, dp.cone_bytes, 0, 1, dp.cone_flops);
+    for (size_t k = 0; k + 1 < ws.items_lvl_begin.size(); ++k) {
+      const int64_t b = ws.items_lvl_begin[k], e = ws.items_lvl_begin[k + 1];
+      HIP_TRY(launch_pass_multi((const PassItem*)ws.items.p + b, (int)(e - b), ws.items_lvl_tiles[k],
+                                ws.items_lvl_m[k], 4, 0, 0, st),
+              "cone pass launch");
+    }
+    timing_end(ctx, ti, st);
+    HIP_TRY(ws.out.ensure(sizeof(double)), "result buffer");
+    HIP_TRY(launch_reduce_rows((const double*)ws.slot_total.p, 1, dp.n_parts, P.const_term, (double*)ws.out.p, st),
+            "cone reduce");
+    return fetch_out(ctx, ws, 1, st, out_host);
+  }
   const int ti = timing_begin(ctx, st, dp.cone_bytes, 0, 1, dp.cone_flops);
   HIP_TRY(launch_cones(L, st), "cone launch");
   timing_end(ctx, ti, st);

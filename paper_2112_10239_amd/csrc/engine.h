@@ -95,13 +95,26 @@ struct DevPlan {
   int32_t* d_fterms = nullptr;
   // cone launches: HBM scratch bytes and algorithmic flops (timing records), once per plan
   double cone_bytes = -1, cone_flops = 0;
+  // canonical cones as batched passes: level k holds the k-th pass of every
+  // cone that has one (each pass split into its tiles across workgroups); the
+  // measuring passes write their tile partials at part_off (empty: not batched)
+  std::vector<std::vector<int32_t>> lvl_cone, lvl_pass;
+  std::vector<std::vector<int64_t>> lvl_part;  // partial offset of the item, -1: none
+  int64_t n_parts = 0;
+  uint64_t uid = 0;  // distinct per plan object (workspace caches of device pointers)
+  DevPlan();
   ~DevPlan();
   hipError_t upload(bool mock);
 };
 
 struct Workspace {
-  DevBuf coef, meas, grad, slot_total, out, scratch, lambda, weights, table, dens, gates, block, params;
+  DevBuf coef, meas, grad, slot_total, out, scratch, lambda, weights, table, dens, gates, block, params, items;
   HostBuf h_coef, h_out, h_gates, h_params;
+  // batched cone items on the device: plan uid and the buffers they point into
+  uint64_t items_uid = 0;
+  const void *items_coef = nullptr, *items_scratch = nullptr, *items_parts = nullptr;
+  std::vector<int64_t> items_lvl_begin, items_lvl_tiles;
+  std::vector<int> items_lvl_m;
   std::vector<CoefGate> last_gates;  // content of 'gates' (device gate table)
   void release() {
     gates.release();
@@ -122,6 +135,8 @@ struct Workspace {
     h_out.release();
     params.release();
     h_params.release();
+    items.release();
+    items_uid = 0;
   }
 };
 

@@ -646,3 +646,22 @@ def test_density_errors(Q, eng):
                 st.reduced_density(bad)
     finally:
         st.destroy()
+
+
+@pytest.mark.parametrize("n,depth", [(16, 2), (20, 3), (22, 4)])
+def test_lightcone_factored_groups_vs_oracle(Q, eng, oracle_mod, n, depth):
+    """RY+RZ+CNOT brickwork cones: rotation runs on register bits become factored
+    groups and CNOT runs exit permutations inside the cones; cones above 13 qubits
+    (n = 22, depth 4) keep their state in scratch between passes."""
+    say("lightcone factored groups", n, depth)
+    c = W.brickwork_ry_rz_cnot(n, depth)
+    H = W.tfim(n, 0.7)
+    th = W.angles(c.n_params, [33, n, depth])
+    want = oracle_mod.expect(c, H, th)
+    for mode in (Q.MODE_LIGHTCONE, Q.MODE_LIGHTCONE_FACTORED):
+        got = eng.expect_circuit(c, H, th, mode=mode)
+        assert abs(got - want) <= tol(H, 0), (mode, got, want)
+    # term by term (the cone of each term against the oracle's full state)
+    _, ref, _ = oracle_mod.expect_state(n, oracle_mod.statevector(c, th), H)
+    for mode in (Q.MODE_LIGHTCONE, Q.MODE_LIGHTCONE_FACTORED):
+        np.testing.assert_allclose(eng.expect_terms(c, H, th, mode=mode), ref, atol=TOL64, err_msg=f"mode {mode}")
