@@ -102,6 +102,7 @@ static double pass_flops_per_amp(const Plan& P, const PassDesc& pd, bool dual = 
         case OP_GRAD_X: case OP_GRAD_Y: case OP_GRAD_Z: f += 4; break;
         case OP_PTAB: f += 6 * g; o += op.j; break;
         case OP_GZS: case OP_GXYS: f += 4.0 * op.slot; o += op.slot; break;
+        case OP_CZS: o += op.j; break;  // sign flips
         case OP_H_Z: case OP_H_F: f += 4; break;
         default: break;
       }

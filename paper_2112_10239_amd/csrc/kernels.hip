@@ -320,11 +320,34 @@ __device__ __forceinline__ void ap_phase(cpx<T>* a, kptr<T> d, const BitSel& b) 
   }
 }
 
+template <int R>
+__device__ __forceinline__ constexpr uint32_t reg_pattern_all() {
+  return R >= 5 ? 0xFFFFFFFFu : ((1u << (1 << R)) - 1u);
+}
+
 template <class T, int R>
 __device__ __forceinline__ void ap_cz(cpx<T>* a, const BitSel& b1, const BitSel& b2) {
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
     const bool neg = (bitv(b1, i) & bitv(b2, i)) != 0u;
+    a[i].x = neg ? -a[i].x : a[i].x;
+    a[i].y = neg ? -a[i].y : a[i].y;
+  }
+}
+
+// Register indices i (of 2^R) with bit j set, as a bit mask over i; all of them.
+template <int R>
+__device__ __forceinline__ uint32_t reg_pattern(uint32_t j) {
+  constexpr uint32_t pat[5] = {0xAAAAAAAAu, 0xCCCCCCCCu, 0xF0F0F0F0u, 0xFF00FF00u, 0xFFFF0000u};
+  return pat[j] & reg_pattern_all<R>();
+}
+
+// a_i *= -1 where bit i of S is set (the sign bits of both components)
+template <class T, int R>
+__device__ __forceinline__ void ap_signs(cpx<T>* a, uint32_t S) {
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const bool neg = ((S >> i) & 1u) != 0u;
     a[i].x = neg ? -a[i].x : a[i].x;
     a[i].y = neg ? -a[i].y : a[i].y;
   }
@@ -979,6 +1002,23 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         const BitSel c2 = mkbit(ck2, cb2, tl, base);
         ap_cz<T, R>(a, c1, c2);
         if constexpr (DUAL) ap_cz<T, R>(b, c1, c2);
+      } else if (type == OP_CZS) {
+        // the sign pattern over the register index: the pairs on two register
+        // bits from the planner, then per record a register bit's pattern when
+        // the other bit is set, or every register when both are
+        uint32_t S = op->rz;
+        const int nrec = (int)opj;
+        for (int k = 1; k <= nrec; ++k) {
+          const uint32_t wr = *(kptr<uint32_t>)(OPS + o + k), wr1 = *((kptr<uint32_t>)(OPS + o + k) + 1);
+          const BitSel c1 = mkbit((wr >> 16) & 0xffu, wr >> 24, tl, base);
+          const BitSel c2 = mkbit(wr1 & 0xffu, (wr1 >> 8) & 0xffu, tl, base);
+          if (c1.kind == BK_REG) S ^= c2.val ? reg_pattern<R>(c1.idx) : 0u;
+          else if (c2.kind == BK_REG) S ^= c1.val ? reg_pattern<R>(c2.idx) : 0u;
+          else S ^= (c1.val & c2.val) ? reg_pattern_all<R>() : 0u;
+        }
+        ap_signs<T, R>(a, S);
+        if constexpr (DUAL) ap_signs<T, R>(b, S);
+        o += nrec;
       } else if (type == OP_MEAS_Z) {
         T p[NR];  // |a_i|^2
 #pragma unroll

@@ -1130,6 +1130,32 @@ struct PassEmitter {
             continue;
           }
         }
+        if (g->kind == PG_CZ && ii + 1 < its.size() && its[ii + 1]->kind == PG_CZ) {
+          // a run of CZs (diagonal, they commute): one sign pattern over the
+          // register index, the pairs on two register bits folded in on the host
+          size_t jj = ii;
+          while (jj < its.size() && its[jj]->kind == PG_CZ) ++jj;
+          DevOp head;
+          std::memset(&head, 0, sizeof(head));
+          head.type = OP_CZS;
+          std::vector<DevOp> recs;
+          for (size_t k = ii; k < jj; ++k) {
+            const BitRef a = bitref(its[k]->q, rb), b = bitref(its[k]->q2, rb);
+            if (a.kind == BK_REG && b.kind == BK_REG) {
+              for (int i = 0; i < (1 << r); ++i)
+                if (((i >> a.idx) & 1) && ((i >> b.idx) & 1)) head.rz ^= 1u << i;
+            } else {
+              recs.push_back(to_devop(*its[k], rb));
+            }
+          }
+          head.j = (uint8_t)recs.size();
+          const int at = (int)plan.ops.size() - st.op_begin;
+          for (size_t k = ii; k < jj; ++k) record_order(its[k], at);
+          plan.ops.push_back(head);
+          for (const DevOp& d : recs) plan.ops.push_back(d);
+          ii = jj - 1;
+          continue;
+        }
         if (g->kind == PG_MEAS_Z) {  // a run of diagonal terms becomes one grouped op
           size_t jj = ii;
           while (jj < its.size() && its[jj]->kind == PG_MEAS_Z) ++jj;

@@ -49,6 +49,9 @@ enum OpType : uint8_t {
                   // (ck, cb: the qubit's bit; slot: gradient slot); g += Im sum_i conj(b_i) (-1)^{bit(i)} a_i
   OP_GXYS = 20,   // X/Y-generator probes on register bits: the next 'slot' ops (at most 4) are records
                   // (j: register bit; ph: 0 for X, 1 for Y; slot: gradient slot), as OP_GRAD_X / OP_GRAD_Y
+  OP_CZS = 21,    // a run of CZs as one sign pattern over the register index: rz holds the pairs on two
+                  // register bits (bit i set: register index i changes sign); the next j ops are OP_CZ
+                  // records of the other pairs (one register bit: a linear term; none: a constant)
 };
 
 // Bit reference kinds for controls, diagonal bits and z-masks.
