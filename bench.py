@@ -38,9 +38,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_SOURCES = ("kernels.hip", "planner.cpp", "engine.cpp", "qsim_types.h")
+
+
 def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_2112_10239_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256/16 over the sources that decide a pass's HBM access pattern: the kernels, the
+    planner (layouts, permutations) and the engine (plan options)."""
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2112_10239_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(name: str):
@@ -52,7 +60,7 @@ def load_traffic(name: str):
     except (OSError, ValueError):
         return None
     e = d.get(name)
-    if not e or e.get("kernel_source_sha256_16") != kernel_source_hash():
+    if not e or e.get("sources_sha256_16") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
 
@@ -144,7 +152,13 @@ def bench_lightcone(Q, W, reps=20):
     import torch
 
     w = W.lightcone_maxcut()
-    out = dict(workload="lightcone_maxcut_n500_d4 (750 terms, one cone launch)")
+    out = dict(workload="lightcone_maxcut_n500_d4 (750 terms)")
+    kernels = {"canonical": ("k_pass_multi<float, 4, false> (every cone's k-th pass in one launch, tiles over "
+                             "workgroups; the figure spans the launches of one evaluation)",
+                             "cones of at most 13 qubits stay in LDS; larger cones keep their state in scratch "
+                             "between passes"),
+               "factored": ("k_cones<float, 4, false> (one workgroup per cone, one launch)",
+                            "cones of at most six qubits, LDS-resident: a latency-bound launch")}
     for name, mode in (("canonical", Q.MODE_LIGHTCONE), ("factored", Q.MODE_LIGHTCONE_FACTORED)):
         ctx = Q.Context(0)
         ctx.expect_circuit(w.circuit, w.H, w.theta, mode=mode)
@@ -163,8 +177,7 @@ def bench_lightcone(Q, W, reps=20):
         out[name] = dict(evals_per_s=reps / (t1 - t0), cone_kernel_ms=ms, E=E,
                          roofline=dict(bound="alu", achieved=tf, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                                        frac=tf / FP32_PEAK_TFLOPS, algorithmic_flops_per_launch=fl,
-                                       kernel="k_cones<float, 4, false>",
-                                       note="cones of at most 14 qubits stay in LDS: no HBM state traffic"))
+                                       kernel=kernels[name][0], note=kernels[name][1]))
     return out
 
 

@@ -188,8 +188,21 @@ class CCircuit:
 
     @classmethod
     def of(cls, circ) -> "CCircuit":
-        """From any object with ``n``, ``gates`` (structured array), ``n_params`` and ``mats``."""
-        return cls(circ.n, circ.gates, circ.n_params, getattr(circ, "mats", None))
+        """From any object with ``n``, ``gates`` (structured array), ``n_params`` and ``mats``.
+        The marshalled copy is kept on the object and reused while its gate array is the
+        same object with the same bytes (circuits with U1 matrices are marshalled anew)."""
+        gates, mats = circ.gates, getattr(circ, "mats", None)
+        hit = getattr(circ, "_qsim_marshalled", None)
+        if (hit is not None and not mats and hit[0] is gates and hit[1] == (circ.n, circ.n_params)
+                and hit[2] == gates.tobytes()):
+            return hit[3]
+        cc = cls(circ.n, gates, circ.n_params, mats)
+        if not mats and isinstance(gates, np.ndarray):
+            try:
+                circ._qsim_marshalled = (gates, (circ.n, circ.n_params), gates.tobytes(), cc)
+            except (AttributeError, TypeError):
+                pass
+        return cc
 
 
 class CHamiltonian:
@@ -210,7 +223,20 @@ class CHamiltonian:
 
     @classmethod
     def of(cls, H) -> "CHamiltonian":
-        return cls(H.coeff, H.term_off, H.qubits, H.paulis)
+        """The C view of H.  When H's four arrays need no conversion the view points into
+        them (later in-place edits are seen) and is kept on H for as long as they are the
+        same objects."""
+        hit = getattr(H, "_qsim_marshalled", None)
+        if (hit is not None and hit._coeff is H.coeff and hit._off is H.term_off and hit._q is H.qubits
+                and hit._p is H.paulis):
+            return hit
+        ch = cls(H.coeff, H.term_off, H.qubits, H.paulis)
+        if ch._coeff is H.coeff and ch._off is H.term_off and ch._q is H.qubits and ch._p is H.paulis:
+            try:
+                H._qsim_marshalled = ch
+            except (AttributeError, TypeError):
+                pass
+        return ch
 
 
 def _dptr(a: np.ndarray):

@@ -251,3 +251,31 @@ def test_plan_passes_store_first_stage_shapes(Q):
     finally:
         ctx.close()
 
+
+
+def test_marshalling_cache_follows_edits():
+    """The C views kept on circuits and Hamiltonians are reused only while they still
+    describe the object: an in-place gate edit, a replaced array or U1 matrices give a
+    fresh view; a Hamiltonian view points into its arrays, so edits in place are seen."""
+    from paper_2112_10239_amd import qsim as qs
+
+    w = W.small_ring_maxcut()
+    c = w.circuit
+    a = qs.CCircuit.of(c)
+    assert qs.CCircuit.of(c) is a
+    c.gates["q0"][0] = (c.gates["q0"][0] + 1) % c.n
+    b = qs.CCircuit.of(c)
+    assert b is not a and b._rec["q0"][0] == c.gates["q0"][0]
+    c.gates = c.gates.copy()
+    assert qs.CCircuit.of(c) is not b
+    bld = W.GateListBuilder(2)
+    bld.custom(0, np.eye(2))
+    u = bld.build()
+    assert qs.CCircuit.of(u) is not qs.CCircuit.of(u)  # U1 matrices: never cached
+    H = w.H
+    h = qs.CHamiltonian.of(H)
+    assert qs.CHamiltonian.of(H) is h
+    H.coeff[0] = 7.0
+    assert h.h.coeff[0] == 7.0  # the view points into the live array
+    H.coeff = H.coeff.copy()
+    assert qs.CHamiltonian.of(H) is not h
