@@ -644,10 +644,9 @@ struct PassEmitter {
   // sides and no CNOT of the writer's exit permutation targeting one of them.
   // Such an exchange needs no workgroup barrier (each wave writes and reads its
   // own block of LDS).  Stages that load or store keep the lowest bits as lane
-  // bits (whole segments per access): their wave bits avoid the c_low lowest
-  // local indices.
-  void choose_thread_orders(std::vector<StageBuild>& sb, int first, bool load_first, int store_idx,
-                            int c_low) const {
+  // bits (whole segments per access; the lane bits above the always-local ones
+  // are often the next index bits, which makes the segments longer).
+  void choose_thread_orders(std::vector<StageBuild>& sb, int first, bool load_first, int store_idx) const {
     const int ns = (int)sb.size(), nt = m - r, nw = nt - 6;
     for (int s = first; s < ns; ++s) {
       sb[s].tord.clear();
@@ -663,8 +662,10 @@ struct PassEmitter {
       for (const PGate* g : sb[s].perm) tgt[s] |= 1u << lidx[g->q];
       uint32_t top = 0;
       for (int k = nt - nw; k < nt; ++k) top |= 1u << T[k];
-      const bool io = (s == first && load_first) || s == store_idx;
-      const uint32_t low = io ? (1u << std::max(0, c_low)) - 1u : 0u;  // kept as lane bits
+      if ((s == first && load_first) || s == store_idx) {
+        cand[s] = {top};  // the lowest thread bits stay lane bits: whole segments per access
+        continue;
+      }
       // every nw-subset of the thread bits (the default, the top ones, first)
       cand[s].push_back(top);
       std::vector<int> idx(nw);
@@ -672,7 +673,7 @@ struct PassEmitter {
       while (true) {
         uint32_t w = 0;
         for (int i = 0; i < nw; ++i) w |= 1u << T[idx[i]];
-        if (w != top && !(w & low)) cand[s].push_back(w);
+        if (w != top) cand[s].push_back(w);
         int i = nw - 1;
         while (i >= 0 && idx[i] == nt - nw + i) --i;
         if (i < 0) break;
@@ -858,10 +859,10 @@ struct PassEmitter {
     const int pass_no0 = (int)plan.passes.size();
     bool folded = false;
     if (allow_entry && (flags & PF_LOAD_A) && !(flags & (PF_LOAD_B | PF_INIT)) && store_rel != 0 && sb.size() >= 2) {
-      choose_thread_orders(sb, 1, true, store_rel, c_low);  // the second stage loads once the first is folded
+      choose_thread_orders(sb, 1, true, store_rel);  // the second stage loads once the first is folded
       folded = fold_entry(sb, pd);
     }
-    if (!folded) choose_thread_orders(sb, 0, loads, store_rel, c_low);
+    if (!folded) choose_thread_orders(sb, 0, loads, store_rel);
     if (folded) {
       for (const PGate* g : sb[0].perm)
         for (int src : g->srcs) {  // applied while loading: ahead of the first stage's ops
