@@ -173,6 +173,8 @@ PlanOptions dual_options(const qsim_options& co, int c128) {
   o.c_low = std::min(6, std::max(3, opt_int(co.dual_coalesce_bits, "QSIM_DUAL_CLOW", 6)));
   o.fuse = false;
   o.batch_probes = !opt_off(co, QSIM_OFF_BATCH_PROBES, "QSIM_BATCH_PROBES", true);
+  // the rotations that end a stage as one factored group on both states (float, r <= 4)
+  o.factored = !c128 && o.r <= 4 && !opt_off(co, QSIM_OFF_FACTORED, "QSIM_FACTORED", true);
   return o;
 }
 
@@ -569,6 +571,7 @@ std::shared_ptr<DevPlan> get_adjoint_plan(qsim_ctx* ctx, const CircuitDesc& c, i
 PlanOptions cone_grad_options(const qsim_options& co, int c128) {
   PlanOptions o = dual_options(co, c128);
   o.r = 4;  // the cone kernel keeps 16 amplitudes per thread and state
+  o.init_factors = false;  // every cone starts from |0...0> (its slots are shared between cones)
   return o;
 }
 

@@ -842,24 +842,32 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     // the P table; the swaps X^f stay pending as an XOR mask on the register
     // index, which the stage's exit addressing applies (block: 32 + 32 table
     // scalars, k per bit, swap mask as a raw word).
-    auto utab = [&](int slot) __attribute__((always_inline)) {
-      if constexpr (!DUAL && R <= 4 && std::is_same<T, float>::value) {
-        const kptr<T> blk = coef + (int64_t)slot * 8;
-        ap_tan<T, R, 0>(a, blk[64]);
-        if constexpr (R > 1) {
-          __builtin_amdgcn_sched_barrier(0);
-          ap_tan<T, R, 1>(a, blk[65]);
-        }
-        if constexpr (R > 2) {
-          __builtin_amdgcn_sched_barrier(0);
-          ap_tan<T, R, 2>(a, blk[66]);
-        }
-        if constexpr (R > 3) {
-          __builtin_amdgcn_sched_barrier(0);
-          ap_tan<T, R, 3>(a, blk[67]);
-        }
+    // (two-state kernels apply the same group to both states; the swaps are common)
+    auto utab1 = [&](cpx<T>* x, const kptr<T>& blk) __attribute__((always_inline)) {
+      ap_tan<T, R, 0>(x, blk[64]);
+      if constexpr (R > 1) {
         __builtin_amdgcn_sched_barrier(0);
-        ap_table<T, R>(a, blk);
+        ap_tan<T, R, 1>(x, blk[65]);
+      }
+      if constexpr (R > 2) {
+        __builtin_amdgcn_sched_barrier(0);
+        ap_tan<T, R, 2>(x, blk[66]);
+      }
+      if constexpr (R > 3) {
+        __builtin_amdgcn_sched_barrier(0);
+        ap_tan<T, R, 3>(x, blk[67]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      ap_table<T, R>(x, blk);
+    };
+    auto utab = [&](int slot) __attribute__((always_inline)) {
+      if constexpr (R <= 4 && std::is_same<T, float>::value) {
+        const kptr<T> blk = coef + (int64_t)slot * 8;
+        utab1(a, blk);
+        if constexpr (DUAL) {
+          __builtin_amdgcn_sched_barrier(0);
+          utab1(b, blk);
+        }
         pend = *(kptr<uint32_t>)(blk + 68) & (uint32_t)(NR - 1);
       }
     };
@@ -867,7 +875,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     // op dispatch (the loop is empty for the common stage holding only it)
     int o_end = op_end;
     bool last_utab = false;
-    if constexpr (!DUAL && R <= 4 && std::is_same<T, float>::value) {
+    if constexpr (R <= 4 && std::is_same<T, float>::value) {
       last_utab = (sflags & SF_LAST_UTAB) != 0u;
       if (last_utab) --o_end;
     }
@@ -951,8 +959,9 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
           }
         }
         o += R;
-      } else if (!DUAL && R <= 4 && std::is_same<T, float>::value && type == OP_DTAB) {
+      } else if (R <= 4 && std::is_same<T, float>::value && type == OP_DTAB) {
         ap_table<T, R>(a, coef + (int64_t)op->slot * 8 + 32);
+        if constexpr (DUAL) ap_table<T, R>(b, coef + (int64_t)op->slot * 8 + 32);
       } else if (R <= 4 && type == OP_PTAB) {
         // the per-thread factor of the thread- and tile-bit phases, then one
         // complex product per amplitude with the register table times that factor

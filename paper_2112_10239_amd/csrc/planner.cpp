@@ -181,6 +181,7 @@ void adjoint_pgates(const CircuitDesc& c, std::vector<PGate>& out, std::vector<P
     p.q = x.q0;
     p.srcs = {g};
     p.inverse = true;
+    p.real_pre = x.kind == G_RY;  // RY^-1 is real: a factored group needs no pre-diagonal for it
     p.slot = (int)slots.size();
     slots.push_back(p);
     out.push_back(p);
@@ -916,6 +917,51 @@ struct PassEmitter {
           plan.order.push_back(src);
         }
       };
+      // Uncontrolled rotations on distinct register bits that end the stage's ops
+      // (they commute) as one factored op, U_j = X^f P_j T_j E_j with diagonal P_j,
+      // E_j, a real T_j of two multiply-adds per amplitude and a swap X^f left to
+      // the stage's exit addressing; the P's (and E's) form one table over the
+      // register index.  Taken (returns true) when cheaper than the rotations one
+      // by one (instructions per amplitude pair: 16 per general rotation, 8 per
+      // RY; factored 4 per register bit, 8 per table).
+      auto emit_factored = [&](const std::vector<const PGate*>& run) {
+        std::vector<const PGate*> member(r, nullptr);
+        int cost = 0;
+        bool pre = false;
+        for (const PGate* h : run) {
+          member[bitref(h->q, rb).idx] = h;
+          cost += h->kind == PG_U ? 16 : 8;
+          pre = pre || !h->real_pre;
+        }
+        if (!(cost > 4 * r + 8 + (pre ? 8 : 0))) return false;
+        DevOp head;
+        std::memset(&head, 0, sizeof(head));
+        head.type = OP_UTAB;
+        head.j = pre ? 1 : 0;
+        head.slot = (int)plan.slots.size();
+        PGate tab;
+        tab.kind = PG_TAB;
+        tab.q = r;
+        for (int j = 0; j < r; ++j) {
+          tab.srcs.push_back(member[j] ? member[j]->slot : -1);
+          if (member[j]) head.fr |= 1u << j;
+        }
+        for (int chunk = 0; chunk < kTabSlots; ++chunk) {
+          tab.gen = chunk;
+          tab.slot = (int)plan.slots.size();
+          plan.slots.push_back(tab);
+        }
+        if (pre) {
+          DevOp d = head;
+          d.type = OP_DTAB;
+          plan.ops.push_back(d);
+        }
+        const int at = (int)plan.ops.size() - st.op_begin;
+        plan.ops.push_back(head);
+        for (int j = 0; j < r; ++j)
+          if (member[j]) record_order(member[j], at);
+        return true;
+      };
       // gradient probes in groups of up to four (OP_GZS / OP_GXYS + records)
       auto emit_probes = [&](const std::vector<const PGate*>& probes, bool zgen) {
         for (size_t k0 = 0; k0 < probes.size(); k0 += 4) {
@@ -1029,10 +1075,19 @@ struct PassEmitter {
           std::vector<const PGate*> probes, rots;
           for (size_t k = ii; k < jj; ++k) (its[k]->kind == PG_GRAD ? probes : rots).push_back(its[k]);
           emit_probes(probes, false);
+          // rotations that end the stage, one per register bit at most: a factored group
+          bool distinct = !rots.empty();
+          uint32_t used = 0;
           for (const PGate* h : rots) {
-            record_order(h, (int)plan.ops.size() - st.op_begin);
-            plan.ops.push_back(to_devop(*h, rb));
+            const uint32_t bit = 1u << bitref(h->q, rb).idx;
+            distinct = distinct && !(used & bit);
+            used |= bit;
           }
+          if (!(allow_factored && r <= 4 && jj == its.size() && distinct && emit_factored(rots)))
+            for (const PGate* h : rots) {
+              record_order(h, (int)plan.ops.size() - st.op_begin);
+              plan.ops.push_back(to_devop(*h, rb));
+            }
           ii = jj - 1;
           continue;
         }
@@ -1044,52 +1099,18 @@ struct PassEmitter {
         // by one (instructions per amplitude pair: 16 per general rotation, 8 per
         // RY; factored 4 per register bit, 8 per table).
         if (allow_factored && r <= 4 && (g->kind == PG_U || g->kind == PG_RY) && g->q2 < 0) {
-          std::vector<int> member(r, -1);
           size_t jj = ii;
-          int cost = 0;
-          bool pre = false;
+          std::vector<const PGate*> run;
+          uint32_t used = 0;
           for (; jj < its.size(); ++jj) {
             const PGate* h = its[jj];
             if ((h->kind != PG_U && h->kind != PG_RY) || h->q2 >= 0) break;
             const BitRef b = bitref(h->q, rb);
-            if (b.kind != BK_REG || member[b.idx] >= 0) break;
-            member[b.idx] = (int)jj;
-            cost += h->kind == PG_U ? 16 : 8;
-            pre = pre || !h->real_pre;
+            if (b.kind != BK_REG || ((used >> b.idx) & 1u)) break;
+            used |= 1u << b.idx;
+            run.push_back(h);
           }
-          if (jj == its.size() && cost > 4 * r + 8 + (pre ? 8 : 0)) {
-            DevOp head;
-            std::memset(&head, 0, sizeof(head));
-            head.type = OP_UTAB;
-            head.j = pre ? 1 : 0;
-            head.slot = (int)plan.slots.size();
-            PGate tab;
-            tab.kind = PG_TAB;
-            tab.q = r;
-            for (int j = 0; j < r; ++j) {
-              tab.srcs.push_back(member[j] >= 0 ? its[member[j]]->slot : -1);
-              if (member[j] >= 0) head.fr |= 1u << j;
-            }
-            for (int chunk = 0; chunk < kTabSlots; ++chunk) {
-              tab.gen = chunk;
-              tab.slot = (int)plan.slots.size();
-              plan.slots.push_back(tab);
-            }
-            if (pre) {
-              DevOp d = head;
-              d.type = OP_DTAB;
-              plan.ops.push_back(d);
-            }
-            const int at = (int)plan.ops.size() - st.op_begin;
-            plan.ops.push_back(head);
-            for (int j = 0; j < r; ++j)
-              if (member[j] >= 0)
-                for (int src : its[member[j]]->srcs) {
-                  plan.order.push_back(pass_no);
-                  plan.order.push_back(si);
-                  plan.order.push_back(at);
-                  plan.order.push_back(src);
-                }
+          if (jj == its.size() && emit_factored(run)) {
             ii = jj - 1;
             continue;
           }
@@ -1597,6 +1618,7 @@ int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, P
     PassEmitter em(plan, n, m, r, Ls[p]);
     em.allow_absorb = o.absorb;
     em.batch_probes = o.batch_probes;
+    em.allow_factored = o.factored && !plan.slots.empty();
     std::vector<const PGate*> mod;
     for (int idx : lists[p]) mod.push_back(&gates[idx]);
     em.emit(mod, {}, flags, c_low, p);
