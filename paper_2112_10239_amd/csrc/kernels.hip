@@ -307,6 +307,17 @@ __device__ __forceinline__ void ap_table(cpx<T>* a, kptr<T> d) {
   }
 }
 
+// The same with a real table (imaginary parts zero): one real product per component.
+template <class T, int R>
+__device__ __forceinline__ void ap_table_real(cpx<T>* a, kptr<T> d) {
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    const T dr = d[2 * i];
+    a[i].x = dr * a[i].x;
+    a[i].y = dr * a[i].y;
+  }
+}
+
 template <class T, int R>
 __device__ __forceinline__ void ap_phase(cpx<T>* a, kptr<T> d, const BitSel& b) {
   const T d0r = d[0], d0i = d[1], d1r = d[2], d1i = d[3];
@@ -843,7 +854,7 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
     // index, which the stage's exit addressing applies (block: 32 + 32 table
     // scalars, k per bit, swap mask as a raw word).
     // (two-state kernels apply the same group to both states; the swaps are common)
-    auto utab1 = [&](cpx<T>* x, const kptr<T>& blk) __attribute__((always_inline)) {
+    auto utab1 = [&](cpx<T>* x, const kptr<T>& blk, bool real) __attribute__((always_inline)) {
       ap_tan<T, R, 0>(x, blk[64]);
       if constexpr (R > 1) {
         __builtin_amdgcn_sched_barrier(0);
@@ -858,15 +869,21 @@ __device__ __forceinline__ double tile_run(kptr<PassDesc> P, kptr<StageDesc> SD,
         ap_tan<T, R, 3>(x, blk[67]);
       }
       __builtin_amdgcn_sched_barrier(0);
-      ap_table<T, R>(x, blk);
+      if constexpr (DUAL) {
+        if (real) ap_table_real<T, R>(x, blk);
+        else ap_table<T, R>(x, blk);
+      } else {
+        ap_table<T, R>(x, blk);
+      }
     };
     auto utab = [&](int slot) __attribute__((always_inline)) {
       if constexpr (R <= 4 && std::is_same<T, float>::value) {
         const kptr<T> blk = coef + (int64_t)slot * 8;
-        utab1(a, blk);
+        const bool real = (sflags & SF_REAL_TAB) != 0u;
+        utab1(a, blk, real);
         if constexpr (DUAL) {
           __builtin_amdgcn_sched_barrier(0);
-          utab1(b, blk);
+          utab1(b, blk, real);
         }
         pend = *(kptr<uint32_t>)(blk + 68) & (uint32_t)(NR - 1);
       }

@@ -1343,7 +1343,13 @@ void stage_addressing(Plan& plan) {
       std::memset(st.wr_aff, 0, sizeof(st.wr_aff));
       const bool utab = st.op_end > st.op_begin && plan.ops[st.op_end - 1].type == OP_UTAB;
       st.flags = (utab ? SF_LAST_UTAB : 0u) | ((st.op_end - st.op_begin > (utab ? 1 : 0)) ? SF_INDEX_OPS : 0u);
-      if (utab) st.flags |= (uint32_t)plan.ops[st.op_end - 1].slot << 8;
+      if (utab) {
+        const int slot = plan.ops[st.op_end - 1].slot;
+        st.flags |= (uint32_t)slot << 8;
+        bool real = !(plan.ops[st.op_end - 1].j & 1);  // no pre-diagonal
+        for (int m : plan.slots[slot].srcs) real = real && (m < 0 || plan.slots[m].kind == PG_RY);
+        if (real) st.flags |= SF_REAL_TAB;
+      }
     }
     for (int s = pd.stage_begin; s + 1 < pd.stage_end; ++s) {
       StageDesc& w = plan.stages[s];

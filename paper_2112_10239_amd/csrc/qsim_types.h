@@ -121,8 +121,9 @@ struct StageDesc {
 // op is a factored rotation group (run after the op loop), whose first
 // coefficient slot is flags >> 8; the exchange that ends the stage keeps every
 // amplitude in its wave (each wave writes and reads its own block of slots, no
-// workgroup barrier).
-enum StageFlags : uint32_t { SF_INDEX_OPS = 1, SF_LAST_UTAB = 2, SF_WAVE_LOCAL = 4 };
+// workgroup barrier); the trailing factored group's tables are real (every
+// member a real rotation: one real product per amplitude in two-state kernels).
+enum StageFlags : uint32_t { SF_INDEX_OPS = 1, SF_LAST_UTAB = 2, SF_WAVE_LOCAL = 4, SF_REAL_TAB = 8 };
 static_assert(sizeof(StageDesc) == 320, "StageDesc layout");
 static_assert(offsetof(StageDesc, rb) == 64, "StageDesc header");
 
