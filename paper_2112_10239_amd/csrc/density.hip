@@ -12,7 +12,8 @@
 // Tiling: a workgroup of four waves owns a (32*WB) x (32*WB) output tile of
 // the lower triangle (tile row >= tile column); each wave owns a
 // (16*WB) x (16*WB) corner of it as WB x WB blocks of 16 x 16, and writes
-// each element below the diagonal both at (i, j) and, conjugated, at (j, i).
+// each element below the diagonal both at (i, j) and, conjugated, at (j, i)
+// (the mirror block transposed through LDS, so both writes are row segments).
 // Operands come straight from HBM/L2 (each amplitude of a k-slice is read by
 // the tiles of its row and column); the next k-slice is loaded before the
 // current one is multiplied.
@@ -131,23 +132,35 @@ __global__ __launch_bounds__(256) void k_density(const T* __restrict__ psi, int6
   // Each pair (i > j) is written from one value, at (i, j) and conjugated at
   // (j, i); the diagonal keeps its real part (its imaginary part is zero up to
   // rounding).  The upper half of a diagonal tile is left to the mirror writes.
+  // The mirror writes go through a per-wave 16 x 16 block in LDS (rows padded to
+  // 17), so both writes store 16 consecutive entries of a row per 16 lanes.
+  __shared__ A2 tb[4][16][17];
   A2* out = reinterpret_cast<A2*>(rho) + (int64_t)blockIdx.y * N * N;
 #pragma unroll
   for (int a = 0; a < WB; ++a)
 #pragma unroll
-    for (int b = 0; b < WB; ++b)
+    for (int b = 0; b < WB; ++b) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t i = i0 + 16 * a + Mfma<T>::row(kq, v), j = j0 + 16 * b + r16;
+        const int il = Mfma<T>::row(kq, v);
+        const int64_t i = i0 + 16 * a + il, j = j0 + 16 * b + r16;
         if (i < N && j < N && i >= j) {
-          if (i == j) {
-            out[i * N + i] = A2{cr[a][b][v], T(0)};
-          } else {
-            out[i * N + j] = A2{cr[a][b][v], ci[a][b][v]};
-            out[j * N + i] = A2{cr[a][b][v], -ci[a][b][v]};
-          }
+          if (i == j) out[i * N + i] = A2{cr[a][b][v], T(0)};
+          else out[i * N + j] = A2{cr[a][b][v], ci[a][b][v]};
         }
+        tb[wave][r16][il] = A2{cr[a][b][v], -ci[a][b][v]};  // (j, i) = conj of (i, j)
       }
+      // a wave's LDS operations complete in order: its reads below see its writes
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int jl = (lane >> 4) + 4 * s4, il = lane & 15;
+        const int64_t i = i0 + 16 * a + il, j = j0 + 16 * b + jl;
+        const A2 val = tb[wave][jl][il];
+        if (i < N && j < N && i > j) out[j * N + i] = val;
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // reads done before the next block's writes
+    }
 }
 
 template <class T, int WB>
