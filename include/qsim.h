@@ -124,6 +124,8 @@ typedef struct {
 #define QSIM_OFF_PREFETCH 32  /* register prefetch of the next tile */
 #define QSIM_OFF_IO_REGS 64   /* load/store stages may hold the always-local low bits in registers */
 #define QSIM_OFF_BATCH_PROBES 128  /* adjoint: inverse phases as one table, gradient probes in groups */
+#define QSIM_OFF_RELABEL 256  /* forward plans whose final state is not kept: the qubits held in the
+                                 coalesced low index bits may change from pass to pass */
 
 typedef struct qsim_ctx qsim_ctx;
 typedef struct qsim_state qsim_state;
@@ -271,7 +273,8 @@ int qsim_lightcone_sets(const qsim_circuit* c, const qsim_hamiltonian* H, int32_
                         int cap);
 
 /* Plan summary for a dense evaluation on the host (no device use): passes,
- * stages and ops that the given options produce.  info[0] = passes, info[1] =
+ * stages and ops of the plan that an expectation with default options runs
+ * (final state not kept).  info[0] = passes, info[1] =
  * stages, info[2] = device ops, info[3] = measurement passes.  If 'order' is not
  * NULL it receives, for every gate of c in execution order, (pass, stage, op,
  * gate index) quadruples of int32 (op: the op's index within its stage; -1 for a

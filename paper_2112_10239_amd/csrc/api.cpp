@@ -746,6 +746,7 @@ int qsim_plan_dense(const qsim_circuit* c, const qsim_hamiltonian* H, int dtype,
   term_pgates(terms, false, meas, cst);
   const qsim_options defaults{};
   PlanOptions o = fwd_options(defaults, dtype == QSIM_C128);
+  o.store_final = false;
   std::string err;
   if (plan_forward(cd.n, pg, meas, o, plan, err)) return QSIM_EINVAL;
   info[0] = (int64_t)plan.passes.size();

@@ -130,6 +130,9 @@ PlanOptions fwd_options(const qsim_options& co, int c128) {
   // cache line) while leaving more local positions for gates (23 passes instead
   // of 33 at six for the n=30 workload; measured faster)
   const int clow = std::min(6, std::max(3, opt_int(co.coalesce_bits, "QSIM_FWD_CLOW", 4)));
+  // with relabelling, five (256-byte segments): the passes it adds are fewer
+  // than without (17 instead of 15 at n=30; measured faster)
+  const int clow_rl = std::min(6, std::max(3, opt_int(co.coalesce_bits, "QSIM_FWD_CLOW", 5)));
   const bool absorb = !opt_off(co, QSIM_OFF_ABSORB, "QSIM_ABSORB", true);
   // uncontrolled rotations on a stage's register bits as one factored op (two
   // multiply-adds per amplitude and bit plus one diagonal table) in float plans
@@ -152,11 +155,16 @@ PlanOptions fwd_options(const qsim_options& co, int c128) {
   o.entry_perm = (folds & 1) != 0 && !(co.disable & QSIM_OFF_ENTRY);
   o.exit_perm = (folds & 2) != 0 && !(co.disable & QSIM_OFF_EXIT);
   o.init_factors = (folds & 4) != 0 && !(co.disable & QSIM_OFF_PRODUCT);
+  // expectation-only plans: any c_low qubits shared by consecutive passes may
+  // sit in the low index bits (fewer passes; measured faster)
+  o.relabel = !opt_off(co, QSIM_OFF_RELABEL, "QSIM_RELABEL", true);
+  o.c_low_relabel = clow_rl;
   return o;
 }
 
 PlanOptions cone_options(const qsim_options& co, int c128) {
   PlanOptions o = fwd_options(co, c128);
+  o.relabel = false;  // a cone's sub-state keeps its qubit order
   o.r = 4;  // the cone kernel keeps 16 amplitudes per thread
   // factored rotation groups (float cones); every cone starts from |0...0>
   // (its coefficient slots are shared between cones, the start state's are not)

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -369,6 +370,8 @@ struct PassEmitter {
   bool batch_probes = false;      // adjoint sweeps: diagonals and probes regrouped (see emit)
   bool allow_entry = false;       // fold a permute-only first stage into the loads
   bool allow_exit = false;        // apply the last stage's CNOT run in the store addresses
+  bool lanes_by_image = false;    // store stage with an exit permutation: lane bits are the thread
+                                  // bits whose images are lowest (the permutation may move index bits)
 
   PassEmitter(Plan& p, int n_, int m_, int r_, uint64_t Lmask) : plan(p), n(n_), m(m_), r(r_), lidx(n_, -1) {
     for (int q = 0; q < n; ++q)
@@ -653,6 +656,18 @@ struct PassEmitter {
       sb[s].tord.clear();
       for (int k = 0; k < m; ++k)
         if (!rb_has(sb[s].rb, k)) sb[s].tord.push_back(k);
+    }
+    if (lanes_by_image && store_idx == ns - 1 && store_idx >= first && !sb[store_idx].perm.empty()) {
+      // the store addresses apply the stage's permutation: order the thread bits
+      // by the highest index bit of their image, so that the lane bits write
+      // the lowest index bits
+      std::vector<uint32_t> col;
+      std::vector<std::pair<int, uint32_t>> aff;
+      perm_images(sb[store_idx], col, aff);
+      std::vector<int>& T = sb[store_idx].tord;
+      std::stable_sort(T.begin(), T.end(), [&](int a, int b) {
+        return 31 - __builtin_clz(col[a]) < 31 - __builtin_clz(col[b]);
+      });
     }
     if (nw <= 0 || ns - first < 2) return;
     std::vector<std::vector<uint32_t>> cand(ns);
@@ -1395,9 +1410,35 @@ void stage_addressing(Plan& plan) {
   }
 }
 
+// Candidate local sets of a pass that may hold any qubits in the always-local
+// low positions, provided it shares at least c_low qubits with the previous
+// pass (those are moved into the low positions when the previous pass stores):
+// windows of w = m - c_low .. m consecutive qubits topped up with the previous
+// pass's qubits nearest to the window, and the set grown from the earliest ready gates.
+void relabel_candidates(const std::vector<PGate>& G, const std::vector<int>& pending, uint64_t prev, int n, int m,
+                        int c_low, std::vector<uint64_t>& cands) {
+  for (int w = m - c_low; w <= m; ++w)
+    for (int s = 0; s + w <= n; ++s) {
+      const uint64_t win = ((1ull << w) - 1) << s;
+      std::vector<std::pair<int, int>> extra;  // (distance to the window, qubit)
+      for (int q = 0; q < n; ++q)
+        if (((prev >> q) & 1) && !((win >> q) & 1)) extra.push_back({std::min(std::abs(q - s), std::abs(q - (s + w - 1))), q});
+      std::sort(extra.begin(), extra.end());
+      uint64_t L = win;
+      for (auto& e : extra) {
+        if (popcount64(L) >= m) break;
+        L |= 1ull << e.second;
+      }
+      if (popcount64(L & prev) >= c_low && popcount64(L) == m) cands.push_back(L);
+    }
+  const uint64_t g = grow_candidate(G, pending, 0, n, m);
+  if (popcount64(g & prev) >= c_low) cands.push_back(g);
+}
+
 // Split gates into passes; returns the local masks and applied gate lists.
+// Without 'relabel' the c_low lowest qubits are local in every pass.
 void split_passes(int n, int m, int c_low, const std::vector<PGate>& G, int max_grad, std::vector<uint64_t>& Ls,
-                  std::vector<std::vector<int>>& applied_lists) {
+                  std::vector<std::vector<int>>& applied_lists, bool relabel = false) {
   std::vector<int> pending;
   for (int i = 0; i < (int)G.size(); ++i)
     if (!is_term(G[i])) pending.push_back(i);
@@ -1407,6 +1448,8 @@ void split_passes(int n, int m, int c_low, const std::vector<PGate>& G, int max_
     std::vector<uint64_t> cands;
     if (n <= m) {
       cands.push_back(all);
+    } else if (relabel) {
+      relabel_candidates(G, pending, Ls.empty() ? base : Ls.back(), n, m, c_low, cands);
     } else {
       cands.push_back(grow_candidate(G, pending, base, n, m));
       const int w = m - c_low;
@@ -1504,40 +1547,116 @@ int plan_forward(int n, const std::vector<PGate>& gates_in, const std::vector<PG
   plan.m = std::min(n, o.m_max);
   plan.r = std::min(o.r, plan.m);
   const int m = plan.m, r = plan.r;
-  const int c_low = n <= m ? 0 : std::min(o.c_low, m - r);
+  const bool relabel = o.relabel && !o.store_final && n > m;
+  const int c_low = n <= m ? 0 : std::min(relabel ? o.c_low_relabel : o.c_low, m - r);
   if (check_terms(meas, r, err)) return -1;
 
+  // Relabelling: when the final state is not kept, the qubit held at each
+  // index bit may change from pass to pass.  A pass that stores moves the
+  // c_low qubits the next pass will hold in its low positions there (swaps of
+  // index bits local to both, applied as CNOT triples in the pass's last
+  // permutation), so any qubits can be local together as long as consecutive
+  // passes share c_low of them.  Gates and terms are rewritten in index-bit
+  // coordinates; plan.qmap keeps the final map for terms added later.
   std::vector<uint64_t> Ls;
   std::vector<std::vector<int>> lists;
-  split_passes(n, m, c_low, gates, 1 << 30, Ls, lists);
+  split_passes(n, m, c_low, gates, 1 << 30, Ls, lists, relabel && c_low > 0);
   if (Ls.empty()) {
     Ls.push_back(n <= m ? ((1ull << n) - 1) : ((1ull << m) - 1));
     lists.emplace_back();
   }
+  const int np = (int)Ls.size();
+  std::vector<int> pos(n), occ(n);  // qubit -> index bit, index bit -> qubit
+  std::iota(pos.begin(), pos.end(), 0);
+  std::iota(occ.begin(), occ.end(), 0);
+  std::vector<std::vector<PGate>> pass_gates(np);
+  std::vector<uint64_t> Sp(np);
+  auto to_bits = [&](uint64_t mask) {
+    uint64_t v = 0;
+    for (int q = 0; q < n; ++q)
+      if ((mask >> q) & 1) v |= 1ull << pos[q];
+    return v;
+  };
+  for (int p = 0; p < np; ++p) {
+    Sp[p] = to_bits(Ls[p]);
+    std::vector<PGate>& pgl = pass_gates[p];
+    for (int idx : lists[p]) {
+      PGate g = gates[idx];
+      if (g.q >= 0) g.q = pos[g.q];
+      if (g.q2 >= 0) g.q2 = pos[g.q2];
+      pgl.push_back(std::move(g));
+    }
+    if (!relabel || p + 1 == np) continue;
+    if ((Sp[p] & ((1ull << c_low) - 1)) != ((1ull << c_low) - 1)) {
+      err = "internal: a pass does not hold the low index bits";
+      return -1;
+    }
+    // qubits for the next pass's low positions: the shared ones already there first
+    const uint64_t shared = Ls[p] & Ls[p + 1];
+    std::vector<int> want;
+    for (int b = 0; b < c_low; ++b)
+      if ((shared >> occ[b]) & 1) want.push_back(occ[b]);
+    for (int q = 0; q < n && (int)want.size() < c_low; ++q)
+      if (((shared >> q) & 1) && pos[q] >= c_low) want.push_back(q);
+    for (int b = 0; b < c_low; ++b) {
+      if (std::find(want.begin(), want.end(), occ[b]) != want.end()) continue;
+      int a = -1;
+      for (int q : want)
+        if (pos[q] >= c_low) {
+          a = q;
+          break;
+        }
+      if (a < 0) {
+        err = "internal: consecutive passes share too few qubits";
+        return -1;
+      }
+      const int hb = pos[a];  // swap index bits b and hb (both local in this pass)
+      for (int k = 0; k < 3; ++k) {
+        PGate x;
+        x.kind = PG_X;
+        x.q = (k == 1) ? b : hb;   // target
+        x.q2 = (k == 1) ? hb : b;  // control
+        pgl.push_back(x);
+      }
+      const int ob = occ[b];
+      pos[a] = b;
+      pos[ob] = hb;
+      occ[b] = a;
+      occ[hb] = ob;
+    }
+  }
+  bool moved = false;
+  for (int q = 0; q < n; ++q) moved |= pos[q] != q;
+  if (moved) plan.qmap = pos;
+  std::vector<PGate> meas_b = meas;  // terms in index-bit coordinates
+  for (PGate& t : meas_b) {
+    t.fmask = to_bits(t.fmask);
+    t.zmask = to_bits(t.zmask);
+  }
   // terms measured in the final gate pass vs. extra read-only passes
   std::vector<const PGate*> fin, extra;
-  for (const PGate& t : meas) {
-    if ((t.fmask & ~Ls.back()) == 0) fin.push_back(&t);
+  for (const PGate& t : meas_b) {
+    if ((t.fmask & ~Sp.back()) == 0) fin.push_back(&t);
     else extra.push_back(&t);
   }
   std::vector<uint64_t> mLs;
   std::vector<std::vector<const PGate*>> mgroups;
   cover_terms(n, m, c_low, extra, mLs, mgroups);
 
-  const int np = (int)Ls.size();
   for (int p = 0; p < np; ++p) {
     int flags = (p == 0 && o.init) ? PF_INIT : PF_LOAD_A;
     const bool last = p == np - 1;
     if (!last || o.store_final || !mLs.empty()) flags |= PF_STORE_A;
-    PassEmitter em(plan, n, m, r, Ls[p]);
+    PassEmitter em(plan, n, m, r, Sp[p]);
     em.allow_absorb = o.absorb;
     em.allow_fused_bits = true;
     em.allow_factored = o.factored && !plan.slots.empty();
     em.io_lo = o.io_lo;
     em.allow_entry = o.factored && o.entry_perm;
     em.allow_exit = o.factored && o.exit_perm;
+    em.lanes_by_image = relabel && !last;
     std::vector<const PGate*> mod;
-    for (int idx : lists[p]) mod.push_back(&gates[idx]);
+    for (const PGate& g : pass_gates[p]) mod.push_back(&g);
     em.emit(mod, last ? fin : std::vector<const PGate*>{}, flags, c_low, p);
   }
   for (size_t k = 0; k < mLs.size(); ++k) {
@@ -1654,8 +1773,16 @@ void append_diag_measure(Plan& plan, const std::vector<PGate>& meas) {
   for (int k = 0; k < pd.m; ++k) L |= 1ull << pd.lpos[k];
   PassEmitter em(plan, pd.n, pd.m, pd.r, L);
   std::vector<int> rb(st.rb, st.rb + pd.r);
+  std::vector<PGate> meas_b = meas;  // in the index bits the plan ends with
+  if (!plan.qmap.empty())
+    for (PGate& t : meas_b) {
+      uint64_t z = 0;
+      for (int q = 0; q < pd.n; ++q)
+        if ((t.zmask >> q) & 1) z |= 1ull << plan.qmap[q];
+      t.zmask = z;
+    }
   std::vector<const PGate*> items;
-  for (const PGate& g : meas) items.push_back(&g);
+  for (const PGate& g : meas_b) items.push_back(&g);
   em.emit_zgroup(items, 0, items.size(), rb);
   st.op_end = (int)plan.ops.size();
   if (!(pd.flags & PF_MEASURE)) {

@@ -82,6 +82,7 @@ struct Plan {
   double const_term = 0;          // identity terms, added on the host
   std::vector<int32_t> order;     // (pass, stage, op, source gate) quadruples
   int meas_passes = 0;
+  std::vector<int> qmap;          // qubit -> index bit after the last gate pass (empty: identity)
 };
 
 enum PlanMode { PM_FWD = 0, PM_ADJ = 1 };
@@ -104,6 +105,9 @@ struct PlanOptions {
                               // OP_GZS, OP_GXYS)
   bool factored = false;  // runs of uncontrolled rotations on register bits as one OP_UTAB
                           // (single-state float kernels with r <= 4; needs plan.slots)
+  bool relabel = false;   // without store_final: the qubits held in the low index bits change
+                          // between passes (plan.qmap: the final map)
+  int c_low_relabel = 5;  // c_low of plans that relabel
 };
 
 // Validation; returns "" when fine.

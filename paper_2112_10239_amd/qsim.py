@@ -54,6 +54,7 @@ class Options(ctypes.Structure):
 
 
 OFF_FACTORED, OFF_ABSORB, OFF_ENTRY, OFF_EXIT, OFF_PRODUCT, OFF_PREFETCH, OFF_IO_REGS = 1, 2, 4, 8, 16, 32, 64
+OFF_BATCH_PROBES, OFF_RELABEL = 128, 256
 
 
 class Request(ctypes.Structure):

@@ -237,10 +237,11 @@ def test_plan_passes_store_first_stage_shapes(Q):
             return [p for p in ps if p["store_stage"] == 0 and (p["entry_perm"] or p["exit_perm"])
                     and p["stages"] > 1]
 
+        # (plans that keep the final state: expectation-only plans relabel qubits)
         w = W.dense_tfim()
-        assert hazards(w.circuit, w.H)
-        assert hazards(W.brickwork_ry_rz_cnot(15, 9), W.tfim(15, 1.0))
-        assert hazards(W.brickwork_ry_rz_cnot(23, 20), W.tfim(23, 1.0))
+        assert hazards(w.circuit, w.H, keep=True)
+        assert hazards(W.brickwork_ry_rz_cnot(15, 9), W.tfim(15, 1.0), keep=True)
+        assert hazards(W.brickwork_ry_rz_cnot(23, 20), W.tfim(23, 1.0), keep=True)
         zz = W.Hamiltonian.from_terms([(1.0, [(i, "Z"), ((i + 1) % 14, "Z")]) for i in range(14)])
         assert hazards(W.brickwork_ry_rz_cnot(14, 2), zz, keep=True)
         # every pass record is consistent with its flags
