@@ -126,6 +126,8 @@ typedef struct {
 #define QSIM_OFF_BATCH_PROBES 128  /* adjoint: inverse phases as one table, gradient probes in groups */
 #define QSIM_OFF_RELABEL 256  /* forward plans whose final state is not kept: the qubits held in the
                                  coalesced low index bits may change from pass to pass */
+#define QSIM_OFF_EARLY_TERMS 512  /* terms with X/Y factors measured in the gate passes once every gate
+                                     they do not commute with has been applied */
 
 typedef struct qsim_ctx qsim_ctx;
 typedef struct qsim_state qsim_state;
@@ -294,6 +296,22 @@ int qsim_plan_dense(const qsim_circuit* c, const qsim_hamiltonian* H, int dtype,
  * with *count = the number needed when cap is short. */
 int qsim_plan_passes(qsim_ctx* ctx, const qsim_circuit* c, const qsim_hamiltonian* H, int dtype, int keep,
                      int32_t* rec, int cap, int* count);
+
+/* Stage trace of the same plan (diagnostic for host tests; no device use): what
+ * every stage applies, in order, on index bits (the qubit held at an index bit
+ * may change between passes).  One record of 8 int64 per entry:
+ *   {kind, q, q2, src_begin, src_count, ph, fmask, zmask}
+ * kind 0: single-qubit gate on index bit q, the product of the circuit gates
+ * srcs[src_begin .. src_begin + src_count) applied in that order; 1: CNOT, q
+ * target, q2 control; 2: CZ on q, q2; 3: Pauli term measured here, i^ph times
+ * the product over index bits of X (fmask only), Y (both) or Z (zmask only),
+ * weight coef[i]; 4: a stage ends (its permutation has been applied); 5: a
+ * circuit gate srcs[src_begin] folded into the start state (these come first).
+ * cap bounds the records, cap_srcs the source indices; QSIM_ETOOBIG (with
+ * *count and *n_srcs set to the sizes needed) when either is too small.  The
+ * identity part of H is not recorded. */
+int qsim_plan_trace(qsim_ctx* ctx, const qsim_circuit* c, const qsim_hamiltonian* H, int dtype, int keep,
+                    int64_t* rec, double* coef, int cap, int32_t* srcs, int cap_srcs, int* count, int* n_srcs);
 
 /* Coefficient rows (diagnostic for tests): the scalars that the dense passes of
  * the gate plan of c read, for batch parameter rows, built on the host

@@ -1,5 +1,6 @@
 // The C-ABI of libqsim (declared in include/qsim.h).
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <new>
 
@@ -793,6 +794,64 @@ int qsim_plan_passes(qsim_ctx* ctx, const qsim_circuit* c, const qsim_hamiltonia
     o[7] = pd.m;
   }
   *count = np;
+  return QSIM_OK;
+}
+
+int qsim_plan_trace(qsim_ctx* ctx, const qsim_circuit* c, const qsim_hamiltonian* H, int dtype, int keep,
+                    int64_t* rec, double* coef, int cap, int32_t* srcs, int cap_srcs, int* count, int* n_srcs) {
+  if (!ctx || !H || !count || !n_srcs || !valid_dtype(dtype) || (cap > 0 && (!rec || !coef)) ||
+      (cap_srcs > 0 && !srcs))
+    return QSIM_EINVAL;
+  *count = 0;
+  *n_srcs = 0;
+  CircuitDesc cd;
+  int rc = to_circuit(ctx, c, cd);
+  if (rc) return rc;
+  std::vector<Term> terms;
+  if ((rc = to_terms(ctx, H, cd.n, terms))) return rc;
+  if (cd.n > kMaxQubits) return QSIM_ETOOBIG;
+  std::lock_guard<std::mutex> g(ctx->api_mu);
+  Plan P;
+  if ((rc = host_dense_plan(ctx, cd, terms, dtype == QSIM_C128, true, keep != 0, P, true))) return rc;
+  std::vector<std::array<int64_t, 8>> out;
+  std::vector<double> w;
+  std::vector<int32_t> sv;
+  for (size_t k = 0; k + 3 < P.order.size(); k += 4)
+    if (P.order[k + 2] == -2) {
+      out.push_back({5, -1, -1, (int64_t)sv.size(), 1, 0, 0, 0});
+      w.push_back(0);
+      sv.push_back(P.order[k + 3]);
+    }
+  for (const PGate& g : P.trace) {
+    std::array<int64_t, 8> r{0, g.q, g.q2, 0, 0, 0, 0, 0};
+    if (g.kind == -1) {
+      r = {4, -1, -1, 0, 0, 0, 0, 0};
+    } else if (g.kind == PG_X) {
+      r[0] = 1;
+    } else if (g.kind == PG_CZ) {
+      r[0] = 2;
+    } else if (g.kind == PG_MEAS_Z || g.kind == PG_MEAS_F) {
+      r = {3, -1, -1, 0, 0, g.ph, (int64_t)g.fmask, (int64_t)g.zmask};
+    } else if (g.kind == PG_U || g.kind == PG_RY || g.kind == PG_PHASE) {
+      r[2] = -1;
+      r[3] = (int64_t)sv.size();
+      r[4] = (int64_t)g.srcs.size();
+      for (int src : g.srcs) sv.push_back(src);
+    } else {
+      set_error(ctx, "plan_trace: unexpected item");
+      return QSIM_EINVAL;
+    }
+    out.push_back(r);
+    w.push_back(r[0] == 3 ? g.c : 0.0);
+  }
+  *count = (int)out.size();
+  *n_srcs = (int)sv.size();
+  if ((int)out.size() > cap || (int)sv.size() > cap_srcs) return QSIM_ETOOBIG;
+  for (size_t i = 0; i < out.size(); ++i) {
+    std::memcpy(rec + 8 * i, out[i].data(), 8 * sizeof(int64_t));
+    coef[i] = w[i];
+  }
+  if (!sv.empty()) std::memcpy(srcs, sv.data(), sv.size() * sizeof(int32_t));
   return QSIM_OK;
 }
 

@@ -159,12 +159,14 @@ PlanOptions fwd_options(const qsim_options& co, int c128) {
   // sit in the low index bits (fewer passes; measured faster)
   o.relabel = !opt_off(co, QSIM_OFF_RELABEL, "QSIM_RELABEL", true);
   o.c_low_relabel = clow_rl;
+  o.early_terms = !opt_off(co, QSIM_OFF_EARLY_TERMS, "QSIM_EARLY_TERMS", true);
   return o;
 }
 
 PlanOptions cone_options(const qsim_options& co, int c128) {
   PlanOptions o = fwd_options(co, c128);
   o.relabel = false;  // a cone's sub-state keeps its qubit order
+  o.early_terms = false;  // its terms are measured at its end
   o.r = 4;  // the cone kernel keeps 16 amplitudes per thread
   // factored rotation groups (float cones); every cone starts from |0...0>
   // (its coefficient slots are shared between cones, the start state's are not)
@@ -346,8 +348,10 @@ static void cache_put(qsim_ctx* ctx, const std::string& key, std::shared_ptr<Dev
 }
 
 // Plan of the gates alone (no measurement), on the host.
-static int plan_gates_host(qsim_ctx* ctx, const CircuitDesc& c, int c128, bool init, bool store_final, Plan& out) {
+static int plan_gates_host(qsim_ctx* ctx, const CircuitDesc& c, int c128, bool init, bool store_final, Plan& out,
+                           bool trace = false) {
   out = Plan();
+  out.want_trace = trace;
   std::vector<PGate> pg;
   forward_pgates(c, true, pg, out.slots);
   PlanOptions o = fwd_options(ctx->opt, c128);
@@ -379,7 +383,7 @@ static std::shared_ptr<DevPlan> gate_plan(qsim_ctx* ctx, const CircuitDesc& c, i
 }
 
 int host_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, int c128, bool init,
-                    bool store_final, Plan& out) {
+                    bool store_final, Plan& out, bool trace) {
   // the same plan get_dense_plan(..., measure = true) builds, without its device copy
   std::vector<PGate> meas;
   double cst = 0;
@@ -387,7 +391,7 @@ int host_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>
   bool diag = true;
   for (const PGate& t : meas) diag &= t.fmask == 0;
   if (meas.empty() || diag) {
-    int rc = plan_gates_host(ctx, c, c128, init, store_final, out);
+    int rc = plan_gates_host(ctx, c, c128, init, store_final, out, trace);
     if (rc) return rc;
     if (meas.empty() && cst == 0.0) return QSIM_OK;
     append_diag_measure(out, meas);
@@ -395,6 +399,7 @@ int host_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>
     return QSIM_OK;
   }
   out = Plan();
+  out.want_trace = trace;
   std::vector<PGate> pg;
   forward_pgates(c, true, pg, out.slots);
   PlanOptions o = fwd_options(ctx->opt, c128);

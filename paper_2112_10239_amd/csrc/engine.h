@@ -200,8 +200,9 @@ std::shared_ptr<DevPlan> get_grad_plans(qsim_ctx* ctx, const CircuitDesc& c, con
 std::shared_ptr<DevPlan> get_adjoint_plan(qsim_ctx* ctx, const CircuitDesc& c, int c128, int& rc);
 // The plan get_dense_plan(..., measure = true) returns, built on the host only
 // (no device copy, not cached).
+// With 'trace' the plan records its stage trace (Plan::trace).
 int host_dense_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, int c128, bool init,
-                    bool store_final, Plan& out);
+                    bool store_final, Plan& out, bool trace = false);
 // Host-only plans for the serving loop (complex64): the forward plan reuses
 // the structure-cached gate plan and appends this H's measurement.
 int host_forward_plan(qsim_ctx* ctx, const CircuitDesc& c, const std::vector<Term>& terms, bool store_final,

@@ -239,6 +239,25 @@ uint64_t need_mask(const PGate& g) {
   }
 }
 
+// Whether gate g commutes with the Pauli term t (fmask: X/Y factors, zmask:
+// Y/Z factors): a CNOT fixes X on its target and Z on its control, a diagonal
+// gate fixes Z on its qubits; other single-qubit gates are taken not to commute
+// with any factor on their qubit.
+bool commutes_with_term(const PGate& g, const PGate& t) {
+  auto f = [&](int q) { return q >= 0 && ((t.fmask >> q) & 1); };
+  auto z = [&](int q) { return q >= 0 && ((t.zmask >> q) & 1); };
+  switch (g.kind) {
+    case PG_X:
+      return !z(g.q) && !f(g.q2);
+    case PG_CZ:
+      return !f(g.q) && !f(g.q2);
+    case PG_PHASE:
+      return !f(g.q) && g.q2 < 0;
+    default:
+      return !f(g.q) && !z(g.q) && !f(g.q2) && !z(g.q2);
+  }
+}
+
 // Qubits that order g against other gates.
 int order_qubits(const PGate& g, int out[2]) {
   if (is_term(g)) return 0;
@@ -258,6 +277,19 @@ double scan_pass(const std::vector<PGate>& G, const std::vector<int>& pending, u
   int ngrad = 0;
   for (int idx : pending) {
     const PGate& g = G[idx];
+    if (is_term(g)) {
+      // a term placed after the last gate it does not commute with: measured
+      // once no earlier gate on its qubits waits; later gates commute with it,
+      // so it blocks nothing
+      const uint64_t supp = g.fmask | g.zmask;
+      bool b = false;
+      for (int q = 0; q < n; ++q) b |= ((supp >> q) & 1) && blocked[q];
+      if (!b && (g.fmask & ~L) == 0) {
+        score += 0.01;
+        if (applied) applied->push_back(idx);
+      }
+      continue;
+    }
     int qs[2];
     const int k = order_qubits(g, qs);
     bool b = false;
@@ -282,6 +314,7 @@ uint64_t grow_candidate(const std::vector<PGate>& G, const std::vector<int>& pen
   uint64_t L = base;
   for (int idx : pending) {
     const PGate& g = G[idx];
+    if (is_term(g)) continue;
     int qs[2];
     const int k = order_qubits(g, qs);
     bool b = false;
@@ -479,12 +512,43 @@ struct PassEmitter {
     const int lo_store = stores ? lo_io : 0;
     std::vector<StageBuild> sb;
     std::vector<const PGate*> pending = mod;
-    bool first = true;
+    bool first = true, stalled = false;
     while (!pending.empty()) {
       StageBuild s;
       std::vector<char> blocked(n, 0), permuted(n, 0);
       std::vector<const PGate*> rest;
+      // gates that will want register bits (CNOTs go to the permutation)
+      bool gates_left = false;
+      for (const PGate* g : pending)
+        gates_left |= !is_term(*g) && need_mask(*g) != 0 && !(absorb && g->kind == PG_X);
+      gates_left &= !stalled;
+      std::vector<const PGate*> held;  // terms left to a later stage
       for (const PGate* g : pending) {
+        if (is_term(*g)) {
+          // a term among the gates (after the last one it does not commute
+          // with): in the first stage where no earlier gate on its qubits waits
+          // or is left to the stage's permutation, on register bits the gates
+          // already use while gates remain; blocks nothing
+          const uint64_t supp = g->fmask | g->zmask;
+          bool b = false;
+          for (int q = 0; q < n; ++q) b |= ((supp >> q) & 1) && (blocked[q] || permuted[q]);
+          for (const PGate* it : s.items) {
+            if (is_term(*it)) continue;
+            int iq[2];
+            const int ik = order_qubits(*it, iq);
+            for (int t = 0; t < ik; ++t) b |= ((supp >> iq[t]) & 1) != 0;
+          }
+          if (gates_left)
+            for (int k : local_bits(g->fmask, lidx)) b |= !rb_has(s.rb, k);
+          // it commutes with every item of the stage, so it is measured first
+          if (!b && try_place(*g, s.rb, r, first ? lo_load : 0, lidx)) {
+            s.items.insert(s.items.begin(), g);
+          } else {
+            rest.push_back(g);
+            held.push_back(g);
+          }
+          continue;
+        }
         int qs[2];
         const int k = order_qubits(*g, qs);
         bool b = false, pt = false;
@@ -492,6 +556,9 @@ struct PassEmitter {
           b |= blocked[qs[t]] != 0;
           pt |= permuted[qs[t]] != 0;
         }
+        // the gates after a term commute with it, except the index-bit swaps a
+        // relabelling pass ends with: those wait for the terms they move
+        for (const PGate* t : held) b |= !commutes_with_term(*g, *t);
         if (!b && absorb && g->kind == PG_X) {
           s.perm.push_back(g);
           for (int t = 0; t < k; ++t) permuted[qs[t]] = 1;
@@ -504,6 +571,8 @@ struct PassEmitter {
           rest.push_back(g);
         }
       }
+      // a stage that placed nothing: the terms take free register bits next
+      stalled = s.items.empty() && s.perm.empty();
       fill_rb(s.rb, r, m, first ? lo_load : 0);
       sb.push_back(std::move(s));
       pending.swap(rest);
@@ -879,6 +948,10 @@ struct PassEmitter {
       folded = fold_entry(sb, pd);
     }
     if (!folded) choose_thread_orders(sb, 0, loads, store_rel);
+    if (folded && plan.want_trace) {
+      for (const PGate* g : sb[0].perm) plan.trace.push_back(*g);
+      plan.trace.push_back(PGate{-1});
+    }
     if (folded) {
       for (const PGate* g : sb[0].perm)
         for (int src : g->srcs) {  // applied while loading: ahead of the first stage's ops
@@ -924,6 +997,11 @@ struct PassEmitter {
       }
       st.op_begin = (int)plan.ops.size();
       const auto& its = sb[si].items;
+      if (plan.want_trace) {
+        for (const PGate* g : its) plan.trace.push_back(*g);
+        for (const PGate* g : sb[si].perm) plan.trace.push_back(*g);
+        plan.trace.push_back(PGate{-1});
+      }
       auto record_order = [&](const PGate* h, int at) {
         for (int src : h->srcs) {
           plan.order.push_back(pass_no);
@@ -1437,14 +1515,21 @@ void relabel_candidates(const std::vector<PGate>& G, const std::vector<int>& pen
 
 // Split gates into passes; returns the local masks and applied gate lists.
 // Without 'relabel' the c_low lowest qubits are local in every pass.
+// With 'left' the terms in G are measured in the passes where they are ready
+// and local; 'left' receives those that no gate pass reaches.
 void split_passes(int n, int m, int c_low, const std::vector<PGate>& G, int max_grad, std::vector<uint64_t>& Ls,
-                  std::vector<std::vector<int>>& applied_lists, bool relabel = false) {
+                  std::vector<std::vector<int>>& applied_lists, bool relabel = false,
+                  std::vector<int>* left = nullptr) {
   std::vector<int> pending;
-  for (int i = 0; i < (int)G.size(); ++i)
-    if (!is_term(G[i])) pending.push_back(i);
+  int n_gates = 0;
+  for (int i = 0; i < (int)G.size(); ++i) {
+    const bool t = is_term(G[i]);
+    if (!t || left) pending.push_back(i);
+    n_gates += !t;
+  }
   const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
   const uint64_t base = (1ull << c_low) - 1;
-  while (!pending.empty()) {
+  while (n_gates > 0) {
     std::vector<uint64_t> cands;
     if (n <= m) {
       cands.push_back(all);
@@ -1470,13 +1555,18 @@ void split_passes(int n, int m, int c_low, const std::vector<PGate>& G, int max_
     std::vector<int> rest;
     size_t a = 0;
     for (int idx : pending) {
-      if (a < applied.size() && applied[a] == idx) ++a;
-      else rest.push_back(idx);
+      if (a < applied.size() && applied[a] == idx) {
+        ++a;
+        n_gates -= !is_term(G[idx]);
+      } else {
+        rest.push_back(idx);
+      }
     }
     Ls.push_back(bestL);
     applied_lists.push_back(std::move(applied));
     pending.swap(rest);
   }
+  if (left) *left = pending;
 }
 
 // Measurement-only (or H-apply) passes for flip terms not covered yet.
@@ -1558,9 +1648,38 @@ int plan_forward(int n, const std::vector<PGate>& gates_in, const std::vector<PG
   // permutation), so any qubits can be local together as long as consecutive
   // passes share c_low of them.  Gates and terms are rewritten in index-bit
   // coordinates; plan.qmap keeps the final map for terms added later.
+  // Early terms: a term with X/Y factors is measured in the first pass that
+  // holds its flipped qubits after the last gate it does not commute with
+  // (every later gate commutes with it, so the value is the final state's);
+  // such terms ride along in the op list after that gate.  Diagonal terms and
+  // those no gate pass reaches are measured at the end as before.
+  std::vector<PGate> G2;
+  G2.reserve(gates.size() + meas.size());
+  std::vector<const PGate*> diag_terms;
+  {
+    std::vector<std::vector<const PGate*>> after(gates.size() + 1);
+    for (const PGate& t : meas) {
+      if (!o.early_terms || t.fmask == 0 || t.kind != PG_MEAS_F) {
+        diag_terms.push_back(&t);
+        continue;
+      }
+      int last = -1;
+      for (int i = (int)gates.size() - 1; i >= 0; --i)
+        if (!commutes_with_term(gates[i], t)) {
+          last = i;
+          break;
+        }
+      after[last + 1].push_back(&t);
+    }
+    for (size_t i = 0; i <= gates.size(); ++i) {
+      if (i > 0) G2.push_back(gates[i - 1]);
+      for (const PGate* t : after[i]) G2.push_back(*t);
+    }
+  }
   std::vector<uint64_t> Ls;
   std::vector<std::vector<int>> lists;
-  split_passes(n, m, c_low, gates, 1 << 30, Ls, lists, relabel && c_low > 0);
+  std::vector<int> late;  // early terms no gate pass reached
+  split_passes(n, m, c_low, G2, 1 << 30, Ls, lists, relabel && c_low > 0, &late);
   if (Ls.empty()) {
     Ls.push_back(n <= m ? ((1ull << n) - 1) : ((1ull << m) - 1));
     lists.emplace_back();
@@ -1581,9 +1700,11 @@ int plan_forward(int n, const std::vector<PGate>& gates_in, const std::vector<PG
     Sp[p] = to_bits(Ls[p]);
     std::vector<PGate>& pgl = pass_gates[p];
     for (int idx : lists[p]) {
-      PGate g = gates[idx];
+      PGate g = G2[idx];
       if (g.q >= 0) g.q = pos[g.q];
       if (g.q2 >= 0) g.q2 = pos[g.q2];
+      g.fmask = to_bits(g.fmask);
+      g.zmask = to_bits(g.zmask);
       pgl.push_back(std::move(g));
     }
     if (!relabel || p + 1 == np) continue;
@@ -1628,7 +1749,9 @@ int plan_forward(int n, const std::vector<PGate>& gates_in, const std::vector<PG
   bool moved = false;
   for (int q = 0; q < n; ++q) moved |= pos[q] != q;
   if (moved) plan.qmap = pos;
-  std::vector<PGate> meas_b = meas;  // terms in index-bit coordinates
+  std::vector<PGate> meas_b;  // terms left to the end, in index-bit coordinates
+  for (const PGate* t : diag_terms) meas_b.push_back(*t);
+  for (int idx : late) meas_b.push_back(G2[idx]);
   for (PGate& t : meas_b) {
     t.fmask = to_bits(t.fmask);
     t.zmask = to_bits(t.zmask);
@@ -1784,6 +1907,10 @@ void append_diag_measure(Plan& plan, const std::vector<PGate>& meas) {
   std::vector<const PGate*> items;
   for (const PGate& g : meas_b) items.push_back(&g);
   em.emit_zgroup(items, 0, items.size(), rb);
+  if (plan.want_trace) {
+    for (const PGate& g : meas_b) plan.trace.push_back(g);
+    plan.trace.push_back(PGate{-1});
+  }
   st.op_end = (int)plan.ops.size();
   if (!(pd.flags & PF_MEASURE)) {
     pd.flags |= PF_MEASURE;

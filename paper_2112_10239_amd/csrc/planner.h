@@ -83,6 +83,8 @@ struct Plan {
   std::vector<int32_t> order;     // (pass, stage, op, source gate) quadruples
   int meas_passes = 0;
   std::vector<int> qmap;          // qubit -> index bit after the last gate pass (empty: identity)
+  bool want_trace = false;        // host checks: record every stage's items, then its permutation,
+  std::vector<PGate> trace;       // in index-bit coordinates (kind -1: a stage ends)
 };
 
 enum PlanMode { PM_FWD = 0, PM_ADJ = 1 };
@@ -108,6 +110,7 @@ struct PlanOptions {
   bool relabel = false;   // without store_final: the qubits held in the low index bits change
                           // between passes (plan.qmap: the final map)
   int c_low_relabel = 5;  // c_low of plans that relabel
+  bool early_terms = true;  // terms with X/Y factors measured in the gate passes once ready
 };
 
 // Validation; returns "" when fine.

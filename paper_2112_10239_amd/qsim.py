@@ -54,7 +54,7 @@ class Options(ctypes.Structure):
 
 
 OFF_FACTORED, OFF_ABSORB, OFF_ENTRY, OFF_EXIT, OFF_PRODUCT, OFF_PREFETCH, OFF_IO_REGS = 1, 2, 4, 8, 16, 32, 64
-OFF_BATCH_PROBES, OFF_RELABEL = 128, 256
+OFF_BATCH_PROBES, OFF_RELABEL, OFF_EARLY_TERMS = 128, 256, 512
 
 
 class Request(ctypes.Structure):
@@ -77,7 +77,7 @@ EXPORTS = [
     "qsim_expect_grad", "qsim_lightcone_sets", "qsim_plan_dense", "qsim_submit", "qsim_poll", "qsim_cancel",
     "qsim_server_stats_get", "qsim_timing_enable", "qsim_timing_get", "qsim_poll_timed", "qsim_clock",
     "qsim_copy_probe", "qsim_expect_grad_cones", "qsim_reduced_density", "qsim_plan_passes", "qsim_expect_terms",
-    "qsim_coef_rows",
+    "qsim_coef_rows", "qsim_plan_trace",
     "qsim_expect_circuit_noalloc",
     "qsim_apply_block5",
 ]
@@ -115,6 +115,8 @@ def _load():
         "qsim_lightcone_sets": (I, [P(Circuit), P(Hamiltonian), P(ctypes.c_int32), P(ctypes.c_int32), I]),
         "qsim_plan_dense": (I, [P(Circuit), P(Hamiltonian), I, P(ctypes.c_int64), P(ctypes.c_int32), I]),
         "qsim_plan_passes": (I, [V, P(Circuit), P(Hamiltonian), I, I, P(ctypes.c_int32), I, P(I)]),
+        "qsim_plan_trace": (I, [V, P(Circuit), P(Hamiltonian), I, I, P(ctypes.c_int64), P(D), I, P(ctypes.c_int32), I,
+                                P(I), P(I)]),
         "qsim_coef_rows": (I, [V, P(Circuit), V, I, I, I, V, ctypes.c_uint64, P(ctypes.c_uint64)]),
         "qsim_expect_circuit_noalloc": (I, [V, P(Circuit), V, I, I, P(Hamiltonian), I, V, ctypes.c_uint64, V, P(D)]),
         "qsim_apply_block5": (I, [V, P(D), I, P(D)]),
@@ -450,6 +452,26 @@ class Context:
         self._check(rc, "qsim_plan_passes")
         keys = ("flags", "stages", "store_stage", "entry_perm", "exit_perm", "meas_index", "grad_count", "m")
         return [dict(zip(keys, (int(v) for v in rec[8 * p:8 * p + 8]))) for p in range(cnt.value)]
+
+    def plan_trace(self, circ, H, dtype: int = C64, keep: bool = False):
+        """Stage trace of that plan: (records int64 [count, 8], coef float64 [count], srcs int32);
+        see qsim_plan_trace for the record layout."""
+        cc, ch = CCircuit.of(circ), CHamiltonian.of(H)
+        cnt, nsrc = ctypes.c_int(), ctypes.c_int()
+        rc = lib.qsim_plan_trace(self.ptr, ctypes.byref(cc.c), ctypes.byref(ch.h), dtype, int(keep), None, None, 0,
+                                 None, 0, ctypes.byref(cnt), ctypes.byref(nsrc))
+        if rc != ETOOBIG:
+            self._check(rc, "qsim_plan_trace")
+        rec = np.zeros((max(cnt.value, 1), 8), dtype=np.int64)
+        coef = np.zeros(max(cnt.value, 1))
+        srcs = np.zeros(max(nsrc.value, 1), dtype=np.int32)
+        rc = lib.qsim_plan_trace(self.ptr, ctypes.byref(cc.c), ctypes.byref(ch.h), dtype, int(keep),
+                                 rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), rec.shape[0],
+                                 srcs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), srcs.size, ctypes.byref(cnt),
+                                 ctypes.byref(nsrc))
+        self._check(rc, "qsim_plan_trace")
+        return rec[:cnt.value], coef[:cnt.value], srcs[:nsrc.value]
 
     def coef_rows(self, circ, theta, dtype: int = C64) -> np.ndarray:
         """Raw coefficient rows of the dense gate plan (uint8 [rows, row_bytes]), built on the

@@ -51,37 +51,57 @@ def ring_zz(n):
 
 # --- the dense family at the sizes where the tile walk and the plan shapes change -----
 
-@pytest.mark.parametrize("n,depth", [(23, 20), (24, 20)])
-def test_dense_tfim_full_paths(Q, eng, oracle_mod, n, depth):
+@pytest.mark.parametrize("n,depth,fixed", [(23, 20, False), (24, 20, False), (24, 20, True)])
+def test_dense_tfim_full_paths(Q, eng, oracle_mod, n, depth, fixed):
     """n=23: each resident workgroup walks more than one tile (non-zero stride);
-    n=24: plans with two measurement passes, as at n=30.  A second call on the
-    same inputs gives the same bits (fixed reduction order)."""
+    n=24: the relabelled plan with X terms measured in the gate passes and one
+    measurement pass, and (fixed) the plan that keeps every qubit at its own
+    index bit and measures X terms at the end (two measurement passes).  A second
+    call on the same inputs gives the same bits (fixed reduction order)."""
+    import paper_2112_10239_amd.qsim as qs
+
     c = W.brickwork_ry_rz_cnot(n, depth)
     H = W.tfim(n, 1.0)
     th = W.angles(c.n_params, [2, 1, n, depth])
-    info, _ = Q.plan_dense(c, H)
-    say("dense tfim full paths", n, depth, info)
-    if n == 24:
-        assert info["meas_passes"] == 2
-    want = oracle_mod.expect(c, H, th)
-    got = eng.expect_circuit(c, H, th, mode=Q.MODE_DENSE)
-    assert abs(got - want) <= tol(H), (got, want)
-    again = eng.expect_circuit(c, H, th, mode=Q.MODE_DENSE)
-    assert again == got
+    ctx = Q.Context(0, disable=qs.OFF_RELABEL | qs.OFF_EARLY_TERMS) if fixed else eng
+    try:
+        ps = ctx.plan_passes(c, H)
+        meas_only = sum(1 for p in ps if p["flags"] == 66)
+        early = sum(1 for p in ps if p["flags"] & 64 and p["flags"] & 4)
+        say("dense tfim full paths", n, depth, "fixed" if fixed else "relabel", len(ps), "passes", meas_only,
+            "measurement passes", early, "storing passes that measure")
+        if n == 24:
+            assert meas_only == (2 if fixed else 1)
+            assert fixed or early >= 2
+        want = oracle_mod.expect(c, H, th)
+        got = ctx.expect_circuit(c, H, th, mode=Q.MODE_DENSE)
+        assert abs(got - want) <= tol(H), (got, want)
+        again = ctx.expect_circuit(c, H, th, mode=Q.MODE_DENSE)
+        assert again == got
+    finally:
+        if fixed:
+            ctx.close()
 
 
 # --- passes that store in their first stage through a permutation -----------------------
 
 def test_store_first_stage_tfim_n15(Q, eng, oracle_mod):
-    """Kept final state (the plan keeps every qubit at its own index bit and has
-    the shape); the expectation alone runs the relabelled plan."""
+    """Kept final state with X terms measured at the end (the plan keeps every
+    qubit at its own index bit and has the shape); the default expectation runs
+    the relabelled plan with X terms measured in the gate passes."""
+    import paper_2112_10239_amd.qsim as qs
+
     c = W.brickwork_ry_rz_cnot(15, 9)
     H = W.tfim(15, 1.0)
     th = W.angles(c.n_params, [40, 15, 9])
     say("store-first-stage tfim n15 d9")
     want = oracle_mod.expect(c, H, th)
-    got, st = eng.expect_circuit(c, H, th, mode=Q.MODE_DENSE, keep=True)
-    st.destroy()
+    fixed = Q.Context(0, disable=qs.OFF_EARLY_TERMS)
+    try:
+        got, st = fixed.expect_circuit(c, H, th, mode=Q.MODE_DENSE, keep=True)
+        st.destroy()
+    finally:
+        fixed.close()
     assert abs(got - want) <= tol(H), (got, want)
     again = eng.expect_circuit(c, H, th, mode=Q.MODE_DENSE)
     assert abs(again - want) <= tol(H), (again, want)

@@ -69,7 +69,7 @@ def test_tile_shapes_vs_oracle(Q, cases, m, r, clow):
 
 
 @pytest.mark.parametrize("off", ["OFF_FACTORED", "OFF_ABSORB", "OFF_ENTRY", "OFF_EXIT", "OFF_PRODUCT",
-                                 "OFF_PREFETCH", "OFF_IO_REGS"])
+                                 "OFF_PREFETCH", "OFF_IO_REGS", "OFF_RELABEL", "OFF_EARLY_TERMS"])
 def test_switches_vs_oracle(Q, cases, off):
     import paper_2112_10239_amd.qsim as qs
 

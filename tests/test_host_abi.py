@@ -230,14 +230,18 @@ def test_plan_passes_store_first_stage_shapes(Q):
     """Plans with a pass that stores in its first stage through a permutation and
     measures in later stages (the loads of every wave must finish before any wave
     stores): the dense n=30 workload, and the shapes the GPU parity tests run."""
+    import paper_2112_10239_amd.qsim as qs
+
     ctx = Q.Context(-1)
+    # the shape is that of plans that measure X terms at the end
+    fixed = Q.Context(-1, disable=qs.OFF_EARLY_TERMS)
     try:
         def hazards(c, H, keep=False):
-            ps = ctx.plan_passes(c, H, keep=keep)
+            ps = (fixed if keep else ctx).plan_passes(c, H, keep=keep)
             return [p for p in ps if p["store_stage"] == 0 and (p["entry_perm"] or p["exit_perm"])
                     and p["stages"] > 1]
 
-        # (plans that keep the final state: expectation-only plans relabel qubits)
+        # (plans that keep the final state, X terms at the end: expectation-only plans relabel qubits)
         w = W.dense_tfim()
         assert hazards(w.circuit, w.H, keep=True)
         assert hazards(W.brickwork_ry_rz_cnot(15, 9), W.tfim(15, 1.0), keep=True)
@@ -251,6 +255,7 @@ def test_plan_passes_store_first_stage_shapes(Q):
             assert (p["meas_index"] >= 0) == bool(p["flags"] & 64)
     finally:
         ctx.close()
+        fixed.close()
 
 
 
