@@ -585,6 +585,8 @@ PlanOptions cone_grad_options(const qsim_options& co, int c128) {
   PlanOptions o = dual_options(co, c128);
   o.r = 4;  // the cone kernel keeps 16 amplitudes per thread and state
   o.init_factors = false;  // every cone starts from |0...0> (its slots are shared between cones)
+  o.relabel = false;       // cone sub-states keep their qubit order
+  o.early_terms = false;
   return o;
 }
 

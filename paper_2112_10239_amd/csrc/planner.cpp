@@ -1592,6 +1592,79 @@ void cover_terms(int n, int m, int c_low, const std::vector<const PGate*>& terms
   }
 }
 
+// Gates (and terms) of every pass in index-bit coordinates; with 'relabel' a
+// storing pass ends with the swaps that move the next pass's c_low chosen
+// qubits into the low index bits (the shared ones already there stay).  Sp:
+// local index bits per pass; pos: qubit -> index bit after the last pass.
+int relabel_passes(int n, int c_low, bool relabel, const std::vector<PGate>& G, const std::vector<uint64_t>& Ls,
+                   const std::vector<std::vector<int>>& lists, std::vector<std::vector<PGate>>& pass_gates,
+                   std::vector<uint64_t>& Sp, std::vector<int>& pos, std::string& err) {
+  const int np = (int)Ls.size();
+  pos.assign(n, 0);
+  std::vector<int> occ(n);  // index bit -> qubit
+  std::iota(pos.begin(), pos.end(), 0);
+  std::iota(occ.begin(), occ.end(), 0);
+  pass_gates.assign(np, {});
+  Sp.assign(np, 0);
+  auto to_bits = [&](uint64_t mask) {
+    uint64_t v = 0;
+    for (int q = 0; q < n; ++q)
+      if ((mask >> q) & 1) v |= 1ull << pos[q];
+    return v;
+  };
+  for (int p = 0; p < np; ++p) {
+    Sp[p] = to_bits(Ls[p]);
+    std::vector<PGate>& pgl = pass_gates[p];
+    for (int idx : lists[p]) {
+      PGate g = G[idx];
+      if (g.q >= 0) g.q = pos[g.q];
+      if (g.q2 >= 0) g.q2 = pos[g.q2];
+      g.fmask = to_bits(g.fmask);
+      g.zmask = to_bits(g.zmask);
+      pgl.push_back(std::move(g));
+    }
+    if (!relabel || p + 1 == np) continue;
+    if ((Sp[p] & ((1ull << c_low) - 1)) != ((1ull << c_low) - 1)) {
+      err = "internal: a pass does not hold the low index bits";
+      return -1;
+    }
+    // qubits for the next pass's low positions: the shared ones already there first
+    const uint64_t shared = Ls[p] & Ls[p + 1];
+    std::vector<int> want;
+    for (int b = 0; b < c_low; ++b)
+      if ((shared >> occ[b]) & 1) want.push_back(occ[b]);
+    for (int q = 0; q < n && (int)want.size() < c_low; ++q)
+      if (((shared >> q) & 1) && pos[q] >= c_low) want.push_back(q);
+    for (int b = 0; b < c_low; ++b) {
+      if (std::find(want.begin(), want.end(), occ[b]) != want.end()) continue;
+      int a = -1;
+      for (int q : want)
+        if (pos[q] >= c_low) {
+          a = q;
+          break;
+        }
+      if (a < 0) {
+        err = "internal: consecutive passes share too few qubits";
+        return -1;
+      }
+      const int hb = pos[a];  // swap index bits b and hb (both local in this pass)
+      for (int k = 0; k < 3; ++k) {
+        PGate x;
+        x.kind = PG_X;
+        x.q = (k == 1) ? b : hb;   // target
+        x.q2 = (k == 1) ? hb : b;  // control
+        pgl.push_back(x);
+      }
+      const int ob = occ[b];
+      pos[a] = b;
+      pos[ob] = hb;
+      occ[b] = a;
+      occ[hb] = ob;
+    }
+  }
+  return 0;
+}
+
 int check_terms(const std::vector<PGate>& terms, int r, std::string& err) {
   for (const PGate& t : terms)
     if (popcount64(t.fmask) > r) {
@@ -1685,67 +1758,16 @@ int plan_forward(int n, const std::vector<PGate>& gates_in, const std::vector<PG
     lists.emplace_back();
   }
   const int np = (int)Ls.size();
-  std::vector<int> pos(n), occ(n);  // qubit -> index bit, index bit -> qubit
-  std::iota(pos.begin(), pos.end(), 0);
-  std::iota(occ.begin(), occ.end(), 0);
-  std::vector<std::vector<PGate>> pass_gates(np);
-  std::vector<uint64_t> Sp(np);
+  std::vector<std::vector<PGate>> pass_gates;
+  std::vector<uint64_t> Sp;
+  std::vector<int> pos;
+  if (relabel_passes(n, c_low, relabel, G2, Ls, lists, pass_gates, Sp, pos, err)) return -1;
   auto to_bits = [&](uint64_t mask) {
     uint64_t v = 0;
     for (int q = 0; q < n; ++q)
       if ((mask >> q) & 1) v |= 1ull << pos[q];
     return v;
   };
-  for (int p = 0; p < np; ++p) {
-    Sp[p] = to_bits(Ls[p]);
-    std::vector<PGate>& pgl = pass_gates[p];
-    for (int idx : lists[p]) {
-      PGate g = G2[idx];
-      if (g.q >= 0) g.q = pos[g.q];
-      if (g.q2 >= 0) g.q2 = pos[g.q2];
-      g.fmask = to_bits(g.fmask);
-      g.zmask = to_bits(g.zmask);
-      pgl.push_back(std::move(g));
-    }
-    if (!relabel || p + 1 == np) continue;
-    if ((Sp[p] & ((1ull << c_low) - 1)) != ((1ull << c_low) - 1)) {
-      err = "internal: a pass does not hold the low index bits";
-      return -1;
-    }
-    // qubits for the next pass's low positions: the shared ones already there first
-    const uint64_t shared = Ls[p] & Ls[p + 1];
-    std::vector<int> want;
-    for (int b = 0; b < c_low; ++b)
-      if ((shared >> occ[b]) & 1) want.push_back(occ[b]);
-    for (int q = 0; q < n && (int)want.size() < c_low; ++q)
-      if (((shared >> q) & 1) && pos[q] >= c_low) want.push_back(q);
-    for (int b = 0; b < c_low; ++b) {
-      if (std::find(want.begin(), want.end(), occ[b]) != want.end()) continue;
-      int a = -1;
-      for (int q : want)
-        if (pos[q] >= c_low) {
-          a = q;
-          break;
-        }
-      if (a < 0) {
-        err = "internal: consecutive passes share too few qubits";
-        return -1;
-      }
-      const int hb = pos[a];  // swap index bits b and hb (both local in this pass)
-      for (int k = 0; k < 3; ++k) {
-        PGate x;
-        x.kind = PG_X;
-        x.q = (k == 1) ? b : hb;   // target
-        x.q2 = (k == 1) ? hb : b;  // control
-        pgl.push_back(x);
-      }
-      const int ob = occ[b];
-      pos[a] = b;
-      pos[ob] = hb;
-      occ[b] = a;
-      occ[hb] = ob;
-    }
-  }
   bool moved = false;
   for (int q = 0; q < n; ++q) moved |= pos[q] != q;
   if (moved) plan.qmap = pos;
