@@ -1631,12 +1631,7 @@ hipError_t launch_pass_t(const PassLaunch& L, hipStream_t stream) {
   // persistent workgroups: as many as fit on the device at once (registers, LDS, threads)
   const int per_cu = resident_per_cu(kern, threads, lds);
   const int64_t total = (int64_t)L.rows << (n - m);
-  static const int persist = [] {
-    const char* e = getenv("QSIM_PERSIST");
-    return e ? atoi(e) : 1;
-  }();
-  const int64_t grid = (PF || persist) ? std::min<int64_t>(total, (int64_t)device_cus() * per_cu)
-                                       : std::min<int64_t>(total, 0x7fffffff);
+  const int64_t grid = std::min<int64_t>(total, (int64_t)device_cus() * per_cu);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, stream, L.d_pass, L.d_stages, L.d_ops,
                      reinterpret_cast<cpx<T>*>(L.A), reinterpret_cast<cpx<T>*>(L.B), L.row_stride,
                      reinterpret_cast<const T*>(L.coef), L.coef_row_stride, L.meas, L.n_meas, L.grad, L.n_gslots,
