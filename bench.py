@@ -350,6 +350,10 @@ def _serve_run(Q, reqs, prep, budget, max_queue):
             del pending[tk]
         if i < nreq:
             time.sleep(max(0.0, min(0.0005, t0 + reqs[i].arrival_s - Q.qsim.clock())))
+        else:
+            # every request submitted: poll at the closed run's cadence (each poll takes the
+            # server's lock, which a busy loop would keep from the scheduler)
+            time.sleep(0.0005)
     stats = ctx.server_stats()
     ctx.close()
     lat = np.asarray(lat)
