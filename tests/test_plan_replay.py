@@ -65,8 +65,8 @@ def replay(oracle_mod, c, H, th, rec, coef, srcs):
     return E, n_terms
 
 
-def _check(Q, oracle_mod, ctx, c, H, th, keep=False):
-    rec, coef, srcs = ctx.plan_trace(c, H, keep=keep)
+def _check(Q, oracle_mod, ctx, c, H, th, keep=False, dtype=None):
+    rec, coef, srcs = ctx.plan_trace(c, H, keep=keep, dtype=Q.qsim.C64 if dtype is None else dtype)
     got, n_terms = replay(oracle_mod, c, H, th, rec, coef, srcs)
     assert n_terms == sum(1 for _, ops in H.terms() if ops)
     want = oracle_mod.expect(c, H, th)
@@ -102,6 +102,19 @@ def test_replay_switches(Q, oracle_mod, off, keep):
     ctx = Q.Context(-1, tile_qubits=12, disable=getattr(qs, off) if off else 0)
     try:
         _check(Q, oracle_mod, ctx, c, H, th, keep=keep)
+    finally:
+        ctx.close()
+
+
+def test_replay_complex128(Q, oracle_mod):
+    """complex128 plans (2^13-amplitude tiles, rotations one by one) relabel and measure early too."""
+    n, depth = 16, 5
+    c = W.brickwork_ry_rz_cnot(n, depth)
+    H = W.tfim(n, 0.9)
+    th = W.angles(c.n_params, [63, n])
+    ctx = Q.Context(-1)
+    try:
+        _check(Q, oracle_mod, ctx, c, H, th, dtype=Q.qsim.C128)
     finally:
         ctx.close()
 
