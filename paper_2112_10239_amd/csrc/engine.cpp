@@ -159,6 +159,7 @@ PlanOptions fwd_options(const qsim_options& co, int c128) {
   // sit in the low index bits (fewer passes; measured faster)
   o.relabel = !opt_off(co, QSIM_OFF_RELABEL, "QSIM_RELABEL", true);
   o.c_low_relabel = clow_rl;
+  o.relabel_kept = o.relabel && env_int("QSIM_RELABEL_KEPT", 1) != 0;
   o.early_terms = !opt_off(co, QSIM_OFF_EARLY_TERMS, "QSIM_EARLY_TERMS", true);
   return o;
 }

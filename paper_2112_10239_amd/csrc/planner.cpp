@@ -1596,9 +1596,12 @@ void cover_terms(int n, int m, int c_low, const std::vector<const PGate*>& terms
 // storing pass ends with the swaps that move the next pass's c_low chosen
 // qubits into the low index bits (the shared ones already there stay).  Sp:
 // local index bits per pass; pos: qubit -> index bit after the last pass.
+// With 'restore' the last pass ends with the swaps that put every qubit back at
+// its own index bit; returns 1 (nothing else changed) when those bits are not all
+// local in the last pass.
 int relabel_passes(int n, int c_low, bool relabel, const std::vector<PGate>& G, const std::vector<uint64_t>& Ls,
                    const std::vector<std::vector<int>>& lists, std::vector<std::vector<PGate>>& pass_gates,
-                   std::vector<uint64_t>& Sp, std::vector<int>& pos, std::string& err) {
+                   std::vector<uint64_t>& Sp, std::vector<int>& pos, std::string& err, bool restore = false) {
   const int np = (int)Ls.size();
   pos.assign(n, 0);
   std::vector<int> occ(n);  // index bit -> qubit
@@ -1622,6 +1625,56 @@ int relabel_passes(int n, int c_low, bool relabel, const std::vector<PGate>& G, 
       g.fmask = to_bits(g.fmask);
       g.zmask = to_bits(g.zmask);
       pgl.push_back(std::move(g));
+    }
+    auto swap_bits = [&](int b, int hb) {  // index bits b and hb, both local in this pass
+      for (int k = 0; k < 3; ++k) {
+        PGate x;
+        x.kind = PG_X;
+        x.q = (k == 1) ? b : hb;   // target
+        x.q2 = (k == 1) ? hb : b;  // control
+        pgl.push_back(x);
+      }
+      const int qa = occ[b], qb = occ[hb];
+      pos[qa] = hb;
+      pos[qb] = b;
+      occ[b] = qb;
+      occ[hb] = qa;
+    };
+    if (relabel && restore && p + 1 == np) {
+      bool inside = true;
+      for (int b = 0; b < n; ++b) inside &= occ[b] == b || ((Sp[p] >> b) & 1);
+      if (inside) {
+        for (int b = 0; b < n; ++b)
+          while (occ[b] != b) swap_bits(b, pos[b]);
+        continue;
+      }
+      // else a pass of its own holding the displaced index bits and the low ones
+      uint64_t S = (1ull << c_low) - 1;
+      for (int b = 0; b < n; ++b)
+        if (occ[b] != b) S |= 1ull << b;
+      const int m = __builtin_popcountll(Sp[p]);
+      if (__builtin_popcountll(S) > m) return 1;
+      for (int b = 0; b < n && __builtin_popcountll(S) < m; ++b) S |= 1ull << b;
+      Sp.push_back(S);
+      pass_gates.emplace_back();
+      std::vector<PGate>& rg = pass_gates.back();
+      for (int b = 0; b < n; ++b)
+        while (occ[b] != b) {
+          const int hb = pos[b];
+          for (int k = 0; k < 3; ++k) {
+            PGate x;
+            x.kind = PG_X;
+            x.q = (k == 1) ? b : hb;
+            x.q2 = (k == 1) ? hb : b;
+            rg.push_back(x);
+          }
+          const int qa = occ[b], qb = occ[hb];
+          pos[qa] = hb;
+          pos[qb] = b;
+          occ[b] = qb;
+          occ[hb] = qa;
+        }
+      return 2;
     }
     if (!relabel || p + 1 == np) continue;
     if ((Sp[p] & ((1ull << c_low) - 1)) != ((1ull << c_low) - 1)) {
@@ -1647,19 +1700,7 @@ int relabel_passes(int n, int c_low, bool relabel, const std::vector<PGate>& G, 
         err = "internal: consecutive passes share too few qubits";
         return -1;
       }
-      const int hb = pos[a];  // swap index bits b and hb (both local in this pass)
-      for (int k = 0; k < 3; ++k) {
-        PGate x;
-        x.kind = PG_X;
-        x.q = (k == 1) ? b : hb;   // target
-        x.q2 = (k == 1) ? hb : b;  // control
-        pgl.push_back(x);
-      }
-      const int ob = occ[b];
-      pos[a] = b;
-      pos[ob] = hb;
-      occ[b] = a;
-      occ[hb] = ob;
+      swap_bits(b, pos[a]);
     }
   }
   return 0;
@@ -1710,7 +1751,11 @@ int plan_forward(int n, const std::vector<PGate>& gates_in, const std::vector<PG
   plan.m = std::min(n, o.m_max);
   plan.r = std::min(o.r, plan.m);
   const int m = plan.m, r = plan.r;
-  const bool relabel = o.relabel && !o.store_final && n > m;
+  // a kept final state is put back in qubit order by its last pass (or the plan
+  // is made again without relabelling when that pass cannot)
+  bool relabel = o.relabel && (!o.store_final || o.relabel_kept) && n > m;
+  const bool restore = o.store_final;
+again:
   const int c_low = n <= m ? 0 : std::min(relabel ? o.c_low_relabel : o.c_low, m - r);
   if (check_terms(meas, r, err)) return -1;
 
@@ -1757,11 +1802,17 @@ int plan_forward(int n, const std::vector<PGate>& gates_in, const std::vector<PG
     Ls.push_back(n <= m ? ((1ull << n) - 1) : ((1ull << m) - 1));
     lists.emplace_back();
   }
-  const int np = (int)Ls.size();
   std::vector<std::vector<PGate>> pass_gates;
   std::vector<uint64_t> Sp;
   std::vector<int> pos;
-  if (relabel_passes(n, c_low, relabel, G2, Ls, lists, pass_gates, Sp, pos, err)) return -1;
+  const int rr = relabel_passes(n, c_low, relabel && c_low > 0, G2, Ls, lists, pass_gates, Sp, pos, err,
+                                restore);
+  if (rr < 0) return -1;
+  if (rr == 1) {
+    relabel = false;
+    goto again;
+  }
+  const int np = (int)Sp.size();  // with a pass that only puts the qubits back in order (rr == 2)
   auto to_bits = [&](uint64_t mask) {
     uint64_t v = 0;
     for (int q = 0; q < n; ++q)
@@ -1797,9 +1848,11 @@ int plan_forward(int n, const std::vector<PGate>& gates_in, const std::vector<PG
     em.allow_fused_bits = true;
     em.allow_factored = o.factored && !plan.slots.empty();
     em.io_lo = o.io_lo;
-    em.allow_entry = o.factored && o.entry_perm;
+    // (a pass that only puts the qubits back in order swaps through an exchange:
+    // folded into its loads, the swaps would scatter the lanes' reads)
+    em.allow_entry = o.factored && o.entry_perm && !(rr == 2 && last);
     em.allow_exit = o.factored && o.exit_perm;
-    em.lanes_by_image = relabel && !last;
+    em.lanes_by_image = relabel && (!last || restore);
     std::vector<const PGate*> mod;
     for (const PGate& g : pass_gates[p]) mod.push_back(&g);
     em.emit(mod, last ? fin : std::vector<const PGate*>{}, flags, c_low, p);

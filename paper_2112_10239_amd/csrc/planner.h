@@ -109,6 +109,8 @@ struct PlanOptions {
                           // (single-state float kernels with r <= 4; needs plan.slots)
   bool relabel = false;   // without store_final: the qubits held in the low index bits change
                           // between passes (plan.qmap: the final map)
+  bool relabel_kept = false;  // also relabel plans that keep the final state (their last pass
+                              // puts the qubits back in order)
   int c_low_relabel = 5;  // c_low of plans that relabel
   bool early_terms = true;  // terms with X/Y factors measured in the gate passes once ready
 };

@@ -96,7 +96,7 @@ def test_store_first_stage_tfim_n15(Q, eng, oracle_mod):
     th = W.angles(c.n_params, [40, 15, 9])
     say("store-first-stage tfim n15 d9")
     want = oracle_mod.expect(c, H, th)
-    fixed = Q.Context(0, disable=qs.OFF_EARLY_TERMS)
+    fixed = Q.Context(0, disable=qs.OFF_EARLY_TERMS | qs.OFF_RELABEL)
     try:
         got, st = fixed.expect_circuit(c, H, th, mode=Q.MODE_DENSE, keep=True)
         st.destroy()
@@ -107,23 +107,48 @@ def test_store_first_stage_tfim_n15(Q, eng, oracle_mod):
     assert abs(again - want) <= tol(H), (again, want)
 
 
-def test_store_first_stage_zz_keep_and_grad(Q, eng, oracle_mod):
-    """CNOT brickwork n=14 depth 2 with a ZZ-only H: the kept (stored) final state
-    gets its measurement in a stage after the storing one."""
+@pytest.mark.parametrize("fixed", [True, False])
+def test_store_first_stage_zz_keep_and_grad(Q, eng, oracle_mod, fixed):
+    """CNOT brickwork n=14 depth 2 with a ZZ-only H: with qubits kept at their own
+    index bits (fixed) the kept (stored) final state gets its measurement in a stage
+    after the storing one; by default the kept plan relabels and its last pass puts
+    the qubits back in order (the kept state is compared amplitude by amplitude)."""
+    import paper_2112_10239_amd.qsim as qs
+
     n = 14
     c = W.brickwork_ry_rz_cnot(n, 2)
     H = ring_zz(n)
     th = W.angles(c.n_params, [41, n])
-    say("store-first-stage zz keep n14 d2")
+    say("store-first-stage zz keep n14 d2", "fixed" if fixed else "relabelled")
     want = oracle_mod.expect(c, H, th)
-    E, st = eng.expect_circuit(c, H, th, mode=Q.MODE_DENSE, keep=True)
-    assert abs(E - want) <= tol(H), (E, want)
-    psi = st.to_host()[0]
-    st.destroy()
-    np.testing.assert_allclose(psi, oracle_mod.statevector(c, th), atol=2e-6)
-    E2, g = eng.expect_grad(c, H, th)
-    assert abs(E2 - want) <= tol(H)
-    np.testing.assert_allclose(g, oracle_mod.grad_psr(c, H, th), atol=tol(H))
+    ctx = Q.Context(0, disable=qs.OFF_EARLY_TERMS | qs.OFF_RELABEL) if fixed else eng
+    try:
+        E, st = ctx.expect_circuit(c, H, th, mode=Q.MODE_DENSE, keep=True)
+        assert abs(E - want) <= tol(H), (E, want)
+        psi = st.to_host()[0]
+        st.destroy()
+        np.testing.assert_allclose(psi, oracle_mod.statevector(c, th), atol=2e-6)
+        E2, g = ctx.expect_grad(c, H, th)
+        assert abs(E2 - want) <= tol(H)
+        np.testing.assert_allclose(g, oracle_mod.grad_psr(c, H, th), atol=tol(H))
+    finally:
+        if fixed:
+            ctx.close()
+
+
+def test_kept_state_relabelled_vs_oracle(Q, eng, oracle_mod):
+    """Kept states of relabelled plans at n = 16, 18 and 20 (a pass of its own puts the
+    qubits back in order at n = 20): every amplitude against the oracle's."""
+    for n, depth in ((16, 8), (18, 6), (20, 10)):
+        c = W.brickwork_ry_rz_cnot(n, depth)
+        H = W.tfim(n, 0.5)
+        th = W.angles(c.n_params, [42, n, depth])
+        say("kept relabelled", n, depth, len(eng.plan_passes(c, H, keep=True)), "passes")
+        E, st = eng.expect_circuit(c, H, th, mode=Q.MODE_DENSE, keep=True)
+        psi = st.to_host()[0]
+        st.destroy()
+        assert abs(E - oracle_mod.expect(c, H, th)) <= tol(H)
+        np.testing.assert_allclose(psi, oracle_mod.statevector(c, th), atol=2e-6)
 
 
 # --- the batched gradient workload at its own batch --------------------------------------

@@ -234,8 +234,8 @@ def test_plan_passes_store_first_stage_shapes(Q):
     import paper_2112_10239_amd.qsim as qs
 
     ctx = Q.Context(-1)
-    # the shape is that of plans that measure X terms at the end
-    fixed = Q.Context(-1, disable=qs.OFF_EARLY_TERMS)
+    # the shape is that of plans that keep qubits at their own index bits and measure X terms at the end
+    fixed = Q.Context(-1, disable=qs.OFF_EARLY_TERMS | qs.OFF_RELABEL)
     try:
         def hazards(c, H, keep=False):
             ps = (fixed if keep else ctx).plan_passes(c, H, keep=keep)

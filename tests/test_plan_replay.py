@@ -62,15 +62,19 @@ def replay(oracle_mod, c, H, th, rec, coef, srcs):
             n_terms += 1
         else:
             assert kind == 4, kind
-    return E, n_terms
+    final = W.Circuit(c.n, np.array(rows, dtype=W.GATE_DTYPE), c.n_params, dict(mats))
+    return E, n_terms, final
 
 
 def _check(Q, oracle_mod, ctx, c, H, th, keep=False, dtype=None):
     rec, coef, srcs = ctx.plan_trace(c, H, keep=keep, dtype=Q.qsim.C64 if dtype is None else dtype)
-    got, n_terms = replay(oracle_mod, c, H, th, rec, coef, srcs)
+    got, n_terms, final = replay(oracle_mod, c, H, th, rec, coef, srcs)
     assert n_terms == sum(1 for _, ops in H.terms() if ops)
     want = oracle_mod.expect(c, H, th)
     assert abs(got - want) <= 1e-9 * max(1.0, H.abs_coeff_sum()), (got, want)
+    if keep:
+        # a kept state ends with every qubit at its own index bit
+        np.testing.assert_allclose(oracle_mod.statevector(final, th), oracle_mod.statevector(c, th), atol=1e-12)
     return rec
 
 
@@ -104,6 +108,26 @@ def test_replay_switches(Q, oracle_mod, off, keep):
         _check(Q, oracle_mod, ctx, c, H, th, keep=keep)
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("n,depth", [(14, 6), (15, 4), (16, 8)])
+def test_replay_kept_state_relabelled(Q, oracle_mod, n, depth):
+    """Kept final states relabel too: the last pass, or a pass of its own, puts every qubit
+    back at its own index bit (checked on the replayed final state)."""
+    import paper_2112_10239_amd.qsim as qs
+
+    c = W.brickwork_ry_rz_cnot(n, depth)
+    H = W.tfim(n, 0.6)
+    th = W.angles(c.n_params, [64, n, depth])
+    passes = {}
+    for off in (0, qs.OFF_RELABEL):
+        ctx = Q.Context(-1, tile_qubits=12, disable=off)
+        try:
+            rec = _check(Q, oracle_mod, ctx, c, H, th, keep=True)
+            passes[off] = len(ctx.plan_passes(c, H, keep=True))
+        finally:
+            ctx.close()
+    assert passes[0] <= passes[qs.OFF_RELABEL], passes
 
 
 def test_replay_complex128(Q, oracle_mod):
