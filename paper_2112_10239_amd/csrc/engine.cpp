@@ -186,6 +186,10 @@ PlanOptions dual_options(const qsim_options& co, int c128) {
   o.batch_probes = !opt_off(co, QSIM_OFF_BATCH_PROBES, "QSIM_BATCH_PROBES", true);
   // the rotations that end a stage as one factored group on both states (float, r <= 4)
   o.factored = !c128 && o.r <= 4 && !opt_off(co, QSIM_OFF_FACTORED, "QSIM_FACTORED", true);
+  // the sweep's final states are not used: its passes relabel (with the rotations
+  // sunk to their stage ends they still form factored groups; measured faster)
+  o.relabel = !opt_off(co, QSIM_OFF_RELABEL, "QSIM_RELABEL", true);
+  o.c_low_relabel = std::min(6, std::max(3, env_int("QSIM_DUAL_CLOW_RL", 5)));
   return o;
 }
 

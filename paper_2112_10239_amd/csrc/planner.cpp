@@ -403,6 +403,7 @@ struct PassEmitter {
   bool batch_probes = false;      // adjoint sweeps: diagonals and probes regrouped (see emit)
   bool allow_entry = false;       // fold a permute-only first stage into the loads
   bool allow_exit = false;        // apply the last stage's CNOT run in the store addresses
+  bool sink_rotations = true;     // see sink()
   bool lanes_by_image = false;    // store stage with an exit permutation: lane bits are the thread
                                   // bits whose images are lowest (the permutation may move index bits)
 
@@ -623,7 +624,35 @@ struct PassEmitter {
       sb.push_back(std::move(s));
       left.swap(rest);
     }
+    if (sink_rotations)
+      for (StageBuild& st : sb) sink(st.items);
     return sb;
+  }
+
+  // Uncontrolled rotations move to the end of their stage past every later item
+  // that leaves their qubit alone (probes, terms and diagonals on other qubits
+  // commute with them), so that they can form the stage's trailing factored group.
+  void sink(std::vector<const PGate*>& items) const {
+    std::vector<char> ht(n, 0);  // qubits of the items that stay ahead, after the current one
+    std::vector<const PGate*> head, tail;
+    for (size_t i = items.size(); i-- > 0;) {
+      const PGate* g = items[i];
+      const bool rot = (g->kind == PG_U || g->kind == PG_RY) && g->q2 < 0;
+      if (rot && !ht[g->q]) {
+        tail.push_back(g);
+        continue;
+      }
+      head.push_back(g);
+      if (is_term(*g)) {
+        for (int q = 0; q < n; ++q)
+          if (((g->fmask | g->zmask) >> q) & 1) ht[q] = 1;
+      } else {
+        if (g->q >= 0) ht[g->q] = 1;
+        if (g->q2 >= 0) ht[g->q2] = 1;
+      }
+    }
+    items.assign(head.rbegin(), head.rend());
+    items.insert(items.end(), tail.rbegin(), tail.rend());
   }
 
   // One OP_MEAS_ZS followed by a record per diagonal term items[i0, i1).
@@ -1926,24 +1955,31 @@ int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, P
   plan.m = std::min(n, o.m_max);
   plan.r = std::min(o.r, plan.m);
   const int m = plan.m, r = plan.r;
-  const int c_low = n <= m ? 0 : std::min(o.c_low, m - r);
+  // the sweep's final states are not used: its passes may relabel (see plan_forward)
+  const bool relabel = o.relabel && n > m;
+  const int c_low = n <= m ? 0 : std::min(relabel ? o.c_low_relabel : o.c_low, m - r);
   std::vector<uint64_t> Ls;
   std::vector<std::vector<int>> lists;
-  split_passes(n, m, c_low, gates, o.max_grad, Ls, lists);
+  split_passes(n, m, c_low, gates, o.max_grad, Ls, lists, relabel && c_low > 0);
   if (Ls.empty()) {  // no gates: one pass that changes nothing
     Ls.push_back(n <= m ? ((1ull << n) - 1) : ((1ull << m) - 1));
     lists.emplace_back();
   }
   const int np = (int)Ls.size();
+  std::vector<std::vector<PGate>> pass_gates;
+  std::vector<uint64_t> Sp;
+  std::vector<int> pos;
+  if (relabel_passes(n, c_low, relabel && c_low > 0, gates, Ls, lists, pass_gates, Sp, pos, err) < 0) return -1;
   for (int p = 0; p < np; ++p) {
     int flags = PF_LOAD_A | PF_LOAD_B;
     if (p != np - 1) flags |= PF_STORE_A | PF_STORE_B;
-    PassEmitter em(plan, n, m, r, Ls[p]);
+    PassEmitter em(plan, n, m, r, Sp[p]);
     em.allow_absorb = o.absorb;
     em.batch_probes = o.batch_probes;
     em.allow_factored = o.factored && !plan.slots.empty();
+    em.lanes_by_image = relabel && p != np - 1;
     std::vector<const PGate*> mod;
-    for (int idx : lists[p]) mod.push_back(&gates[idx]);
+    for (const PGate& g : pass_gates[p]) mod.push_back(&g);
     em.emit(mod, {}, flags, c_low, p);
   }
   stage_addressing(plan);
