@@ -190,6 +190,10 @@ PlanOptions dual_options(const qsim_options& co, int c128) {
   // sunk to their stage ends they still form factored groups; measured faster)
   o.relabel = !opt_off(co, QSIM_OFF_RELABEL, "QSIM_RELABEL", true);
   o.c_low_relabel = std::min(6, std::max(3, env_int("QSIM_DUAL_CLOW_RL", 5)));
+  // permute-only first stages folded into the loads, last CNOT runs into the store
+  // addresses of both states
+  o.entry_perm = !(co.disable & QSIM_OFF_ENTRY);
+  o.exit_perm = !(co.disable & QSIM_OFF_EXIT);
   return o;
 }
 

@@ -972,7 +972,7 @@ struct PassEmitter {
     pd.flags = flags;
     const int pass_no0 = (int)plan.passes.size();
     bool folded = false;
-    if (allow_entry && (flags & PF_LOAD_A) && !(flags & (PF_LOAD_B | PF_INIT)) && store_rel != 0 && sb.size() >= 2) {
+    if (allow_entry && (flags & PF_LOAD_A) && !(flags & PF_INIT) && store_rel != 0 && sb.size() >= 2) {
       choose_thread_orders(sb, 1, true, store_rel);  // the second stage loads once the first is folded
       folded = fold_entry(sb, pd);
     }
@@ -1977,6 +1977,8 @@ int plan_adjoint(int n, const std::vector<PGate>& gates, const PlanOptions& o, P
     em.allow_absorb = o.absorb;
     em.batch_probes = o.batch_probes;
     em.allow_factored = o.factored && !plan.slots.empty();
+    em.allow_entry = o.factored && o.entry_perm;
+    em.allow_exit = o.factored && o.exit_perm;
     em.lanes_by_image = relabel && p != np - 1;
     std::vector<const PGate*> mod;
     for (const PGate& g : pass_gates[p]) mod.push_back(&g);
