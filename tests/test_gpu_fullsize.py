@@ -57,7 +57,9 @@ def test_dense_tfim_full_paths(Q, eng, oracle_mod, n, depth, fixed):
     n=24: the relabelled plan with X terms measured in the gate passes and one
     measurement pass, and (fixed) the plan that keeps every qubit at its own
     index bit and measures X terms at the end (two measurement passes).  A second
-    call on the same inputs gives the same bits (fixed reduction order)."""
+    call on the same inputs gives the same bits (fixed reduction order).  Every
+    term's value <P_t> is checked too, at 1e-5 each (the 2n TFIM terms have unit
+    weight), so one wrong term cannot hide in the sum."""
     import paper_2112_10239_amd.qsim as qs
 
     c = W.brickwork_ry_rz_cnot(n, depth)
@@ -73,11 +75,15 @@ def test_dense_tfim_full_paths(Q, eng, oracle_mod, n, depth, fixed):
         if n == 24:
             assert meas_only == (2 if fixed else 1)
             assert fixed or early >= 2
-        want = oracle_mod.expect(c, H, th)
+        psi = oracle_mod.statevector(c, th)
+        want, want_terms, _ = oracle_mod.expect_state(c.n, psi, H)
+        del psi
         got = ctx.expect_circuit(c, H, th, mode=Q.MODE_DENSE)
         assert abs(got - want) <= tol(H), (got, want)
         again = ctx.expect_circuit(c, H, th, mode=Q.MODE_DENSE)
         assert again == got
+        got_terms = ctx.expect_terms(c, H, th, mode=Q.MODE_DENSE)
+        np.testing.assert_allclose(got_terms, want_terms, rtol=0, atol=TOL64)
     finally:
         if fixed:
             ctx.close()
