@@ -1071,6 +1071,21 @@ int enqueue_dense_passes(qsim_ctx* ctx, const Plan& P, const DenseBufs& b, int r
   return QSIM_OK;
 }
 
+// Sums of rows x per_row partials (plus add) written by the reduction kernel
+// straight into the pinned result buffer (device-visible host memory), so the
+// call ends with one stream synchronisation and no device-to-host copy.
+static int reduce_to_host(qsim_ctx* ctx, Workspace& ws, const double* part, int rows, int64_t per_row, double add,
+                          hipStream_t st, double* out_host) {
+  HIP_TRY(ws.h_out.ensure((size_t)rows * sizeof(double)), "pinned result buffer");
+  double* dres = nullptr;
+  HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&dres), ws.h_out.p, 0), "pinned result address");
+  HIP_TRY(launch_reduce_rows(part, rows, per_row, add, dres, st), "reduce launch");
+  HIP_TRY(hipStreamSynchronize(st), "stream sync");
+  timing_collect(ctx);
+  std::memcpy(out_host, ws.h_out.p, (size_t)rows * sizeof(double));
+  return QSIM_OK;
+}
+
 int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params, int rows,
               int c128, void* A, void* B, hipStream_t st, double* out_host) {
   const Plan& P = dp.plan;
@@ -1088,11 +1103,8 @@ int run_dense(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
       for (int r = 0; r < rows; ++r) out_host[r] = P.const_term;
       return QSIM_OK;
     }
-    HIP_TRY(ws.out.ensure((size_t)rows * sizeof(double)), "result buffer");
-    HIP_TRY(launch_reduce_rows((const double*)ws.meas.p, rows, (int64_t)P.n_meas * tiles, P.const_term,
-                               (double*)ws.out.p, st),
-            "reduce launch");
-    return fetch_out(ctx, ws, rows, st, out_host);
+    return reduce_to_host(ctx, ws, (const double*)ws.meas.p, rows, (int64_t)P.n_meas * tiles, P.const_term, st,
+                          out_host);
   }
   HIP_TRY(hipStreamSynchronize(st), "stream sync");
   timing_collect(ctx);
@@ -1264,10 +1276,7 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
               "cone pass launch");
     }
     timing_end(ctx, ti, st);
-    HIP_TRY(ws.out.ensure(sizeof(double)), "result buffer");
-    HIP_TRY(launch_reduce_rows((const double*)ws.slot_total.p, 1, dp.n_parts, P.const_term, (double*)ws.out.p, st),
-            "cone reduce");
-    return fetch_out(ctx, ws, 1, st, out_host);
+    return reduce_to_host(ctx, ws, (const double*)ws.slot_total.p, 1, dp.n_parts, P.const_term, st, out_host);
   }
   const int ti = timing_begin(ctx, st, dp.cone_bytes, 0, 1, dp.cone_flops);
   HIP_TRY(launch_cones(L, st), "cone launch");
@@ -1285,13 +1294,9 @@ int run_cones(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc
               "term values copy");
       return fetch_out(ctx, ws, T, st, terms_host);
     }
-    HIP_TRY(launch_reduce_rows((const double*)ws.slot_total.p, 1, T, P.const_term, (double*)ws.out.p, st),
-            "term reduce");
-  } else {
-    HIP_TRY(launch_reduce_rows((const double*)ws.meas.p, 1, (int64_t)nc, P.const_term, (double*)ws.out.p, st),
-            "cone reduce");
+    return reduce_to_host(ctx, ws, (const double*)ws.slot_total.p, 1, T, P.const_term, st, out_host);
   }
-  return fetch_out(ctx, ws, 1, st, out_host);
+  return reduce_to_host(ctx, ws, (const double*)ws.meas.p, 1, (int64_t)nc, P.const_term, st, out_host);
 }
 
 int run_cone_grad(qsim_ctx* ctx, Workspace& ws, const DevPlan& dp, const CircuitDesc& c, const ParamSrc& params,
